@@ -1,0 +1,169 @@
+"""Benchmark: sparse HOOI on one MI355X.
+
+A step is one HOOI invocation over all modes (TTM-chain, fixup, Gram,
+eigensolve, factor, then core and fit) on the 3-mode Zipf(1.1) tensor
+1,000,000 x 500,000 x 200,000 with 1e8 nonzeros, lognormal values, ranks
+10 x 10 x 10, inputs resident in HBM.  Prints one JSON line.
+
+  value      TTM-chain Gnnz/s per mode = m' / (mean over modes of the
+             TTM-chain + fixup time) / 1e9, from HIP events on the library's stream
+  ms/step    wall time of one HOOI invocation
+  roofline   the TTM-chain kernel's algorithmic bytes per launch / its average
+             launch time, against 8 TB/s
+  cpu_baseline  the FP64 oracle's TTM-chain timed on a bounded sample on the host
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(m, N, R, khat, dims, ranks, n):
+    """Per-launch bytes the TTM-chain must move: the mode-n copy of the tensor
+    (N-1 int32 coordinates + one FP32 value per nonzero), one write of the
+    compact Y_(n), one read of each other factor."""
+    b = m * (4 * (N - 1) + 4) + R * khat * 4
+    for j in range(N):
+        if j != n:
+            b += dims[j] * ranks[j] * 4
+    return b
+
+
+def cpu_baseline(w, target_s=15.0):
+    """The oracle's TTM-chain (FP64, NumPy) on the first nonzeros of the same
+    workload, grown until it runs for about target_s seconds."""
+    from oracle import ttm
+    dims = w["dims"]
+    F = w["F0"]
+    nnz_total = len(w["vals"])
+    n_s = 200_000
+    elapsed = 0.0
+    while True:
+        sl = slice(0, min(n_s, nnz_total))
+        idx = [i[sl] for i in w["idx"]]
+        vals = w["vals"][sl]
+        t0 = time.perf_counter()
+        ttm.ttm_chain(idx, vals, F, 0, dims)
+        elapsed = time.perf_counter() - t0
+        if elapsed >= target_s / 4 or n_s >= nnz_total:
+            break
+        n_s = int(n_s * min(8.0, max(2.0, target_s / 4 / max(elapsed, 1e-3))))
+    return {"value": round(len(vals) / elapsed / 1e9, 6), "unit": "Gnnz/s/mode", "cores": 1, "kind": "oracle",
+            "sample": f"FP64 NumPy TTM-chain along mode 1 over the first {len(vals)} drawn nonzeros of the same "
+                      f"workload (duplicates not merged), {elapsed:.1f} s on one host thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design in DESIGN.md",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import synth
+    import paper_1804_09494_amd as P
+
+    torch.cuda.set_device(0)
+    t = time.perf_counter()
+    w = synth.make_workload(args.workload, scale=args.scale)
+    gen_s = time.perf_counter() - t
+    dims, ranks = w["dims"], w["ranks"]
+    N = len(dims)
+    print(f"# generated {args.workload} dims={dims} nnz={len(w['vals'])} in {gen_s:.1f}s", file=sys.stderr,
+          flush=True)
+
+    idx_d = [torch.from_numpy(i).cuda() for i in w["idx"]]
+    vals_d = torch.from_numpy(w["vals"]).cuda()
+    ctx = P.TuckerContext(0)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    ctx.load_coo(idx_d, vals_d, dims)
+    torch.cuda.synchronize()
+    load_s = time.perf_counter() - t
+    del idx_d, vals_d
+    t = time.perf_counter()
+    ctx.set_ranks(ranks)
+    torch.cuda.synchronize()
+    part_s = time.perf_counter() - t
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    m, _ = ctx.tensor_info()
+    print(f"# coalesced m'={m} load {load_s:.2f}s partition+layout {part_s:.2f}s", file=sys.stderr, flush=True)
+
+    if args.warmup > 0:
+        ctx.hooi_iterate(args.warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fits = ctx.hooi_iterate(args.steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    K = args.steps
+    ms_per_step = (t1 - t0) * 1e3 / K
+    tm = ctx.timings()
+    ttm_ms = [tm[f"ttm[{n}]"] / K for n in range(N)]
+    kern_ms = [tm[f"ttm_kernel[{n}]"] / K for n in range(N)]
+    value = m / (np.mean(ttm_ms) * 1e-3) / 1e9
+    shapes = [ctx.ttm_shape(n) for n in range(N)]
+    B = [algorithmic_bytes(m, N, shapes[n][0], shapes[n][1], dims, ranks, n) for n in range(N)]
+    achieved = sum(B) / (sum(kern_ms) * 1e-3) / 1e9
+    stats = [ctx.partition_stats(n) for n in range(N)]
+    print(f"# fits {fits}", file=sys.stderr, flush=True)
+    print(f"# per-step ms: " + ", ".join(f"{k}={v / K:.3f}" for k, v in tm.items()), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(w)
+
+    out = {
+        "metric": "TTM-chain Gnnz/s/mode + HOOI iter time; FP32 vs BF16-Gram at rel err <=1e-5",
+        "value": round(value, 3),
+        "unit": "Gnnz/s/mode",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {N}-mode {'x'.join(str(d) for d in dims)}, "
+                               f"{len(w['vals'])} Zipf-drawn nonzeros ({m} after merging), ranks "
+                               f"{'x'.join(str(k) for k in ranks)}, one HOOI invocation per step",
+                   "m_coalesced": m, "ranks": list(ranks)},
+        "hooi_iter_ms": {"fp32": round(ms_per_step, 4)},
+        "ttm_ms_per_mode": [round(x, 4) for x in ttm_ms],
+        "ttm_kernel_ms_per_mode": [round(x, 4) for x in kern_ms],
+        "step_ms": {k: round(v / K, 4) for k, v in tm.items()},
+        "fit": fits[-1] if fits else None,
+        "partition_s": round(part_s, 3),
+        "partition_stats": stats,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "k_ttm<10,10,2,true> (TTM-chain)",
+                     "bytes_per_launch": [int(b) for b in B]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

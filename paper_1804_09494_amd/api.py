@@ -1,0 +1,291 @@
+"""Python binding of the tucker_hip C ABI: argument marshalling only.
+
+Every computation runs in libtucker_hip.so.  Arrays may be NumPy arrays
+(host memory) or torch tensors (CUDA tensors are passed as device pointers,
+CPU tensors as host pointers); torch supplies device memory and the stream.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import (TK_MEM_DEVICE, TK_MEM_HOST, TuckerError, c_f64, c_i32, c_i64, c_int, c_void_p, tk_options,
+                   tk_part_stats)
+
+try:
+    import torch
+except Exception:  # torch is optional for host-memory use
+    torch = None
+
+
+def _is_torch(x):
+    return torch is not None and isinstance(x, torch.Tensor)
+
+
+def _mem_of(x):
+    if _is_torch(x):
+        return TK_MEM_DEVICE if x.is_cuda else TK_MEM_HOST
+    return TK_MEM_HOST
+
+
+def _ptr(x):
+    if x is None:
+        return None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return c_void_p(x.data_ptr())
+    if not x.flags["C_CONTIGUOUS"]:
+        raise ValueError("array must be C-contiguous")
+    return x.ctypes.data_as(c_void_p)
+
+
+def _check_dtype(x, np_dtype, name):
+    if _is_torch(x):
+        want = {np.int32: torch.int32, np.float32: torch.float32, np.float64: torch.float64, np.int64: torch.int64,
+                np.uint8: torch.uint8}[np_dtype]
+        if x.dtype != want:
+            raise TypeError(f"{name}: expected {want}, got {x.dtype}")
+    elif np.asarray(x).dtype != np_dtype:
+        raise TypeError(f"{name}: expected {np.dtype(np_dtype)}, got {np.asarray(x).dtype}")
+
+
+def _current_stream(device):
+    if torch is not None and torch.cuda.is_available():
+        return c_void_p(torch.cuda.current_stream(device).cuda_stream)
+    return c_void_p(None)
+
+
+class TuckerContext:
+    """One library context on one GPU (tk_create / tk_destroy)."""
+
+    def __init__(self, device: int = 0, stream=None, **options):
+        self._L = _lib.load()
+        h = c_void_p()
+        if stream is None:
+            stream = _current_stream(device)
+        elif _is_torch_stream(stream):
+            stream = c_void_p(stream.cuda_stream)
+        self._check(self._L.tk_create(device, stream, ctypes.byref(h)), None)
+        self._h = h
+        self.device = device
+        self.N = 0
+        self.dims = ()
+        self.ranks = ()
+        if options:
+            self.set_options(**options)
+
+    # -- plumbing --
+    def _check(self, status, h="self"):
+        if status != _lib.TK_OK:
+            msg = self._L.tk_last_error(self._h if h == "self" else None)
+            raise TuckerError(status, (msg or b"").decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.tk_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_stream(self, stream):
+        s = c_void_p(stream.cuda_stream) if _is_torch_stream(stream) else c_void_p(stream)
+        self._check(self._L.tk_set_stream(self._h, s))
+
+    def options(self) -> tk_options:
+        o = tk_options()
+        self._L.tk_default_options(ctypes.byref(o))
+        return o
+
+    def set_options(self, **kw):
+        o = self.options()
+        prec = kw.pop("prec", None)
+        if prec is not None:
+            o.prec = {"fp32": _lib.TK_FP32, "bf16": _lib.TK_BF16}.get(prec, prec)
+        sweep = kw.pop("sweep", None)
+        if sweep is not None:
+            o.sweep = {"gauss_seidel": _lib.TK_SWEEP_GAUSS_SEIDEL, "jacobi": _lib.TK_SWEEP_JACOBI}.get(sweep, sweep)
+        for k, v in kw.items():
+            setattr(o, k, v)
+        self._check(self._L.tk_set_options(self._h, ctypes.byref(o)))
+
+    # -- tensor --
+    def load_coo(self, idx, vals, dims):
+        N = len(dims)
+        if len(idx) != N:
+            raise ValueError("need one coordinate array per mode")
+        mem = _mem_of(vals)
+        nnz = int(vals.shape[0])
+        for i, a in enumerate(idx):
+            _check_dtype(a, np.int32, f"idx[{i}]")
+            if _mem_of(a) != mem or int(a.shape[0]) != nnz:
+                raise ValueError("coordinate arrays must match vals in length and memory kind")
+        _check_dtype(vals, np.float32, "vals")
+        d = (c_i64 * N)(*[int(x) for x in dims])
+        ptrs = (c_void_p * N)(*[_ptr(a) for a in idx])
+        self._check(self._L.tk_load_coo(self._h, N, d, nnz, ptrs, _ptr(vals), mem))
+        self.N, self.dims = N, tuple(int(x) for x in dims)
+
+    def tensor_info(self):
+        m, nsq = c_i64(), c_f64()
+        self._check(self._L.tk_get_tensor_info(self._h, ctypes.byref(m), ctypes.byref(nsq)))
+        return m.value, nsq.value
+
+    def get_coo(self):
+        m, _ = self.tensor_info()
+        idx = [np.empty(m, np.int32) for _ in range(self.N)]
+        vals = np.empty(m, np.float32)
+        ptrs = (c_void_p * self.N)(*[_ptr(a) for a in idx])
+        self._check(self._L.tk_get_coo(self._h, ptrs, _ptr(vals), TK_MEM_HOST))
+        return idx, vals
+
+    # -- ranks and partition --
+    def set_ranks(self, ranks):
+        K = (c_i32 * self.N)(*[int(k) for k in ranks])
+        self._check(self._L.tk_set_ranks(self._h, K))
+        self.ranks = tuple(int(k) for k in ranks)
+
+    def partition_stats(self, n):
+        s = tk_part_stats()
+        self._check(self._L.tk_get_partition_stats(self._h, n, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in tk_part_stats._fields_}
+
+    def partition(self, n, elem_order=True):
+        st = self.partition_stats(n)
+        P, S, m = st["P"], st["R_sum"], st["m"]
+        out = dict(bin_ptr=np.empty(P + 1, np.int64), seg_bin=np.empty(S, np.int32),
+                   seg_slice=np.empty(S, np.int32), seg_begin=np.empty(S + 1, np.int64),
+                   seg_bad=np.empty(S, np.uint8))
+        eo = np.empty(m, np.int64) if elem_order else None
+        self._check(self._L.tk_get_partition(self._h, n, _ptr(out["bin_ptr"]), _ptr(eo), _ptr(out["seg_bin"]),
+                                             _ptr(out["seg_slice"]), _ptr(out["seg_begin"]), _ptr(out["seg_bad"]),
+                                             TK_MEM_HOST))
+        if elem_order:
+            out["elem_order"] = eo
+        out["stats"] = st
+        return out
+
+    # -- factors --
+    def set_factor(self, n, F):
+        _check_dtype(F, np.float64, "F")
+        if tuple(F.shape) != (self.dims[n], self.ranks[n]):
+            raise ValueError(f"factor {n} must be {self.dims[n]} x {self.ranks[n]}")
+        self._check(self._L.tk_set_factor(self._h, n, _ptr(F), _mem_of(F)))
+
+    def get_factor(self, n, out=None):
+        if out is None:
+            out = np.empty((self.dims[n], self.ranks[n]), np.float64)
+        self._check(self._L.tk_get_factor(self._h, n, _ptr(out), _mem_of(out)))
+        return out
+
+    # -- hot path --
+    def ttm_shape(self, n):
+        R, kh = c_i64(), c_i64()
+        self._check(self._L.tk_ttm_shape(self._h, n, ctypes.byref(R), ctypes.byref(kh)))
+        return R.value, kh.value
+
+    def ttm_chain(self, n, Y=None, row_slice=None, device=None):
+        """Y_(n) (R_n x Khat_n FP32) and its row slice ids.  With device=True
+        (or torch output tensors on the GPU) the result stays in device memory."""
+        R, kh = self.ttm_shape(n)
+        if Y is None:
+            if device:
+                Y = torch.empty((R, kh), dtype=torch.float32, device=f"cuda:{self.device}")
+                row_slice = torch.empty(R, dtype=torch.int32, device=f"cuda:{self.device}")
+            else:
+                Y = np.empty((R, kh), np.float32)
+                row_slice = np.empty(R, np.int32)
+        mem = _mem_of(Y)
+        self._check(self._L.tk_ttm_chain(self._h, n, _ptr(Y), _ptr(row_slice), mem))
+        return Y, row_slice
+
+    def hooi_iterate(self, iters):
+        fits = np.zeros(max(iters, 1), np.float64)
+        self._check(self._L.tk_hooi_iterate(self._h, iters, _ptr(fits)))
+        return fits[:iters].tolist()
+
+    def core(self):
+        out = np.empty(int(np.prod(self.ranks)), np.float64)
+        fit = c_f64()
+        self._check(self._L.tk_core(self._h, _ptr(out), ctypes.byref(fit), TK_MEM_HOST))
+        return out.reshape(self.ranks, order="F"), fit.value
+
+    def timings(self):
+        cap = c_int(64)
+        ms = (c_f64 * 64)()
+        names = (ctypes.c_char_p * 64)()
+        self._check(self._L.tk_get_timings(self._h, ms, names, ctypes.byref(cap)))
+        return {names[i].decode(): ms[i] for i in range(cap.value)}
+
+    # -- differentiation form --
+    def load_obs(self, idx, dims, ranks):
+        N = len(dims)
+        n_obs = int(idx[0].shape[0])
+        mem = _mem_of(idx[0])
+        for i, a in enumerate(idx):
+            _check_dtype(a, np.int32, f"idx[{i}]")
+        d = (c_i64 * N)(*[int(x) for x in dims])
+        K = (c_i32 * N)(*[int(k) for k in ranks])
+        ptrs = (c_void_p * N)(*[_ptr(a) for a in idx])
+        self._check(self._L.tk_load_obs(self._h, N, d, K, n_obs, ptrs, mem))
+        self.obs_dims, self.obs_ranks, self.n_obs = tuple(dims), tuple(ranks), n_obs
+
+    def tucker_eval(self, core, F, out=None):
+        mem = _mem_of(core)
+        if out is None:
+            if mem == TK_MEM_DEVICE:
+                out = torch.empty(self.n_obs, dtype=torch.float32, device=core.device)
+            else:
+                out = np.empty(self.n_obs, np.float32)
+        Fp = (c_void_p * len(F))(*[_ptr(f) for f in F])
+        self._check(self._L.tk_tucker_eval(self._h, _ptr(core), Fp, _ptr(out), mem))
+        return out
+
+    def tucker_adjoint(self, g, core, F):
+        mem = _mem_of(core)
+        if mem == TK_MEM_DEVICE:
+            dcore = torch.empty_like(core)
+            dF = [torch.empty_like(f) for f in F]
+        else:
+            dcore = np.empty_like(core)
+            dF = [np.empty_like(f) for f in F]
+        Fp = (c_void_p * len(F))(*[_ptr(f) for f in F])
+        dFp = (c_void_p * len(F))(*[_ptr(f) for f in dF])
+        self._check(self._L.tk_tucker_adjoint(self._h, _ptr(g), _ptr(core), Fp, _ptr(dcore), dFp, mem))
+        return dcore, dF
+
+
+def _is_torch_stream(s):
+    return torch is not None and isinstance(s, torch.cuda.Stream)
+
+
+if torch is not None:
+    class TuckerEval(torch.autograd.Function):
+        """model = TuckerEval.apply(ctx, core, F_1, ..., F_N): Tucker model values at
+        the observations loaded into ``ctx`` (tk_tucker_eval); the backward pass
+        calls the hand-written adjoint (tk_tucker_adjoint).  All tensors are FP32
+        and contiguous; core is stored first index fastest (flattened)."""
+
+        @staticmethod
+        def forward(fctx, tctx, core, *F):
+            fctx.tctx = tctx
+            fctx.save_for_backward(core, *F)
+            return tctx.tucker_eval(core.contiguous(), [f.contiguous() for f in F])
+
+        @staticmethod
+        def backward(fctx, g):
+            core, *F = fctx.saved_tensors
+            dcore, dF = fctx.tctx.tucker_adjoint(g.contiguous(), core.contiguous(), [f.contiguous() for f in F])
+            return (None, dcore, *dF)

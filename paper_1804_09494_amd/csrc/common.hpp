@@ -1,0 +1,250 @@
+// Shared host-side definitions of the tucker_hip library: the context, device
+// buffers, error plumbing and launch helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/tucker_hip.h"
+
+namespace tk {
+
+// Error carried out of internal functions and turned into a tk_status at the ABI.
+struct Error {
+  tk_status status;
+  std::string msg;
+};
+
+[[noreturn]] inline void fail(tk_status s, const std::string& msg) { throw Error{s, msg}; }
+
+#define TK_HIP(call)                                                                          \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      ::tk::fail(TK_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+#define TK_CHECK_LAUNCH() TK_HIP(hipGetLastError())
+
+#define TK_REQUIRE(cond, status, msg) \
+  do {                                \
+    if (!(cond)) ::tk::fail(status, msg); \
+  } while (0)
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+struct Ctx;
+
+// Device allocation owned by a Buf; freed on destruction.  Allocation goes
+// through the context so mem_limit_bytes is enforced.
+class Buf {
+ public:
+  Buf() = default;
+  Buf(Ctx* c, size_t bytes) { alloc(c, bytes); }
+  ~Buf() { release(); }
+  Buf(const Buf&) = delete;
+  Buf& operator=(const Buf&) = delete;
+  Buf(Buf&& o) noexcept : ctx_(o.ctx_), p_(o.p_), bytes_(o.bytes_) { o.p_ = nullptr; o.bytes_ = 0; }
+  Buf& operator=(Buf&& o) noexcept {
+    if (this != &o) { release(); ctx_ = o.ctx_; p_ = o.p_; bytes_ = o.bytes_; o.p_ = nullptr; o.bytes_ = 0; }
+    return *this;
+  }
+  void alloc(Ctx* c, size_t bytes);
+  void release();
+  template <class T> T* as() const { return static_cast<T*>(p_); }
+  void* get() const { return p_; }
+  size_t bytes() const { return bytes_; }
+  explicit operator bool() const { return p_ != nullptr; }
+
+ private:
+  Ctx* ctx_ = nullptr;
+  void* p_ = nullptr;
+  size_t bytes_ = 0;
+};
+
+// Per-mode plan: the Lite partition, the mode-sorted copy of the tensor and
+// the fixup table of slices shared by several bins.
+struct ModePlan {
+  int64_t L = 0;          // mode length
+  int64_t L_nz = 0;       // nonempty slices = rows of compact Y
+  int64_t P = 0, limit = 0, n_stage1 = 0, M2 = 0;
+  int64_t S = 0;          // segments (= R_sum)
+  int64_t n_bad = 0, n_slots = 0, E_max = 0, R_max = 0;
+  int64_t khat = 0;
+  int rows_cap = 0;       // LDS rows per bin the TTM kernel was sized for
+  Buf row_slice;          // int32[L_nz]  slice id of each compact row (ascending)
+  Buf bin_ptr;            // int64[P+1]
+  Buf seg_ptr;            // int32[P+1]
+  Buf seg_row;            // int32[S]     compact row of each segment
+  Buf seg_begin;          // int64[S+1]
+  Buf seg_slot;           // int32[S]     -1 = good, else partial-row slot
+  Buf bad_row;            // int32[n_bad]
+  Buf bad_slot;           // int32[n_bad+1] slots of bad slice k: [bad_slot[k], bad_slot[k+1])
+  Buf lay_idx[7];         // int32[m] other modes' coordinates in layout order (modes ascending)
+  Buf lay_val;            // float[m]
+  Buf lay_val_bf16;       // bf16[m] (precision form)
+  Buf elem_order;         // uint32[m] canonical element index per layout position (optional)
+};
+
+struct Timings {
+  std::vector<std::string> names;
+  std::vector<double> ms;
+  void clear() { names.clear(); ms.clear(); }
+  void add(const std::string& n, double v) {
+    for (size_t i = 0; i < names.size(); ++i)
+      if (names[i] == n) { ms[i] += v; return; }
+    names.push_back(n);
+    ms.push_back(v);
+  }
+};
+
+struct ObsSet {
+  int N = 0;
+  int64_t n_obs = 0;
+  int64_t dims[8] = {0};
+  int32_t K[8] = {0};
+  Buf idx[8];  // int32[n_obs], input order
+  ModePlan plan[8];  // Lite partition of the observations along each mode (adjoint TTM-chain)
+  Buf F32[8];        // padded FP32 copies of the caller's factors
+  int kp[8] = {0};
+  Buf gl;            // float[n_obs] upstream gradient in one mode's layout order
+  Buf Yg;            // float[max R_n x Khat_n]
+  Buf G32;           // float[prod K] core copy
+};
+
+struct Ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  tk_options opt{};
+  std::string last_error;
+  int64_t bytes_in_use = 0;
+  int cu_count = 256;
+  size_t lds_per_block = 65536;
+
+  // tensor
+  int N = 0;
+  int64_t dims[8] = {0};
+  int64_t m = 0;
+  double norm_sq = 0.0;
+  Buf idx_c[8];           // int32[m] canonical order
+  Buf val_c;              // float[m]
+  bool have_tensor = false;
+
+  // ranks / plans / factors
+  int32_t K[8] = {0};
+  bool have_ranks = false;
+  ModePlan plan[8];
+  Buf F64[8];             // double[L_n x K_n]
+  Buf F32[8];             // float [L_n x Kp_n], Kp_n = padded row stride
+  Buf F16[8];             // bf16  [L_n x Kb_n]
+  int kp32[8] = {0};      // FP32 row stride
+  int kp16[8] = {0};      // BF16 row stride
+
+  // work buffers (grown on demand)
+  Buf Y;                  // float [max R_n x Khat_n]
+  Buf Ybf16;              // bf16 copy of Y (precision form)
+  Buf partial;            // float [slots x Khat]
+  Buf work;               // general scratch
+  Buf gram_part;          // float/double partial Grams
+  Buf gram64;             // double[Khat x Khat]
+  Buf eig_vec;            // double[Khat x Khat] eigenvectors (warm start), per mode
+  Buf eig_val;            // double[Khat]
+  Buf eigv_mode[8];       // double[Khat_n x Khat_n] last eigenvectors per mode (warm start)
+  bool eig_warm[8] = {false, false, false, false, false, false, false, false};
+  Buf U64;                // double[R_n x K_n]
+  Buf small64;            // double scratch for K x K matrices, reductions
+  Buf core64;             // double[prod K]
+  Buf flag;               // int32 flags
+
+  Timings timings;
+  hipEvent_t ev_ttm[2] = {nullptr, nullptr};  // when set, bracket the TTM-chain kernel launch
+  ObsSet obs;
+  bool have_obs = false;
+
+  void* alloc_raw(size_t bytes);
+  void free_raw(void* p, size_t bytes);
+  void sync() { TK_HIP(hipStreamSynchronize(stream)); }
+};
+
+inline void Buf::alloc(Ctx* c, size_t bytes) {
+  release();
+  ctx_ = c;
+  bytes_ = bytes;
+  p_ = bytes ? c->alloc_raw(bytes) : nullptr;
+}
+
+inline void Buf::release() {
+  if (p_ && ctx_) ctx_->free_raw(p_, bytes_);
+  p_ = nullptr;
+  bytes_ = 0;
+}
+
+// Grow-only reuse of a work buffer.
+inline void ensure(Ctx* c, Buf& b, size_t bytes) {
+  if (b.bytes() < bytes) b.alloc(c, bytes);
+}
+
+template <class T>
+inline void h2d(Ctx* c, T* dst, const T* src, size_t n) {
+  if (n) TK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyHostToDevice, c->stream));
+}
+template <class T>
+inline void d2h(Ctx* c, T* dst, const T* src, size_t n) {
+  if (n) TK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+}
+template <class T>
+inline void d2d(Ctx* c, T* dst, const T* src, size_t n) {
+  if (n) TK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T), hipMemcpyDeviceToDevice, c->stream));
+}
+template <class T>
+inline void copy_out(Ctx* c, T* dst, const T* src, size_t n, tk_mem mem) {
+  if (!n) return;
+  TK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T),
+                        mem == TK_MEM_HOST ? hipMemcpyDeviceToHost : hipMemcpyDeviceToDevice, c->stream));
+}
+template <class T>
+inline void copy_in(Ctx* c, T* dst, const T* src, size_t n, tk_mem mem) {
+  if (!n) return;
+  TK_HIP(hipMemcpyAsync(dst, src, n * sizeof(T),
+                        mem == TK_MEM_HOST ? hipMemcpyHostToDevice : hipMemcpyDeviceToDevice, c->stream));
+}
+
+// Launch-size helper for grid-stride kernels.
+inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536) {
+  int64_t g = ceil_div(n > 0 ? n : 1, block);
+  return (unsigned)(g < cap ? g : cap);
+}
+
+// ---- primitives (prim.hip, rocPRIM) ----
+void sort_pairs_u32(Ctx* c, const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout,
+                    int64_t n, int end_bit);
+void sort_pairs_u64_u32(Ctx* c, const uint64_t* kin, uint64_t* kout, const uint32_t* vin, uint32_t* vout,
+                        int64_t n, int end_bit);
+void exclusive_scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
+void inclusive_scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
+void exclusive_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n);
+void reduce_max_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
+void reduce_min_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
+
+// ---- stages ----
+void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx, const float* vals,
+              tk_mem mem);
+void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
+                int64_t khat, int tile_w, bool keep_order);
+void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t* elem_order, int32_t* seg_bin,
+                      int32_t* seg_slice, int64_t* seg_begin, uint8_t* seg_bad, tk_mem mem);
+int ttm_rows_cap(Ctx* c, int64_t tile_w);
+int ttm_tile_width(int N, const int32_t* K, int n);
+void refresh_factor_copies(Ctx* c, int n);
+void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
+             const float* lay_val, int64_t m, float* Y);
+void ttm_chain(Ctx* c, int n, float* Y, bool bf16);
+void hooi_iterate(Ctx* c, int iters, double* fits);
+void core_and_fit(Ctx* c, double* core_dev, double* fit);
+
+}  // namespace tk

@@ -1,0 +1,293 @@
+// New factor from the leading eigenpairs of G = Y^T Y (Section 2.2: the new
+// F_n holds the leading K_n left singular vectors of Y_(n)):
+//   U  = Y W,  W = V_K diag(lam_k)^(-1/2)     (R_n x K_n, FP64 accumulation)
+//   CholeskyQR2 in FP64: A = U^T U, A = R^T R (Cholesky), U <- U R^-1, twice,
+//   which restores orthonormality to working precision;
+//   F_n = U on the nonempty slices' rows, zero elsewhere (FP64 master),
+//   plus the padded FP32 and BF16 working copies the TTM-chain gathers.
+// Columns whose singular value is zero (rank deficiency) are completed on the
+// host with unit vectors e_i (lowest i not yet spanned, Gram-Schmidt in FP64).
+#include <cmath>
+
+#include "common.hpp"
+
+namespace tk {
+
+constexpr int FT_ROWS = 64;  // rows of Y per workgroup
+
+// U = Y W and per-workgroup partial of U^T U.  W (khat x K, FP64) is in LDS;
+// Y rows are staged through LDS with a padded stride.
+__global__ __launch_bounds__(256) void k_uw(const float* __restrict__ Y, int64_t R, int khat,
+                                            const double* __restrict__ W, int K, double* __restrict__ U,
+                                            double* __restrict__ part) {
+  extern __shared__ double shd[];
+  double* w = shd;                                      // khat * K
+  double* ut = w + (size_t)khat * K;                    // FT_ROWS * K
+  float* yt = reinterpret_cast<float*>(ut + FT_ROWS * K);  // FT_ROWS * (khat + 1)
+  const int ys = khat + 1;
+  for (int i = threadIdx.x; i < khat * K; i += blockDim.x) w[i] = W[i];
+  const int64_t r0 = (int64_t)blockIdx.x * FT_ROWS;
+  const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
+  for (int i = threadIdx.x; i < nr * khat; i += blockDim.x) {
+    const int r = i / khat, cc = i - r * khat;
+    yt[r * ys + cc] = Y[(r0 + r) * khat + cc];
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
+    const int r = i / K, k = i - r * K;
+    double s = 0.0;
+    for (int cc = 0; cc < khat; ++cc) s += (double)yt[r * ys + cc] * w[cc * K + k];
+    ut[r * K + k] = s;
+    U[(r0 + r) * K + k] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
+    const int a = i / K, b = i - a * K;
+    double s = 0.0;
+    for (int r = 0; r < nr; ++r) s += ut[r * K + a] * ut[r * K + b];
+    part[(int64_t)blockIdx.x * K * K + i] = s;
+  }
+}
+
+// U <- U Rinv (upper triangular, K x K) and partial U^T U of the result.
+__global__ __launch_bounds__(256) void k_apply_rinv(double* __restrict__ U, int64_t R, int K,
+                                                    const double* __restrict__ Rinv, double* __restrict__ part) {
+  extern __shared__ double shd[];
+  double* ri = shd;               // K * K
+  double* ut = ri + K * K;        // FT_ROWS * K (old rows)
+  double* un = ut + FT_ROWS * K;  // FT_ROWS * K (new rows)
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) ri[i] = Rinv[i];
+  const int64_t r0 = (int64_t)blockIdx.x * FT_ROWS;
+  const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
+  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) ut[i] = U[r0 * K + i];
+  __syncthreads();
+  // new[r][k] = sum_{j <= k} old[r][j] * Rinv[j][k]
+  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
+    const int r = i / K, k = i - r * K;
+    double s = 0.0;
+    for (int j = 0; j <= k; ++j) s += ut[r * K + j] * ri[j * K + k];
+    un[i] = s;
+    U[r0 * K + i] = s;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
+    const int a = i / K, b = i - a * K;
+    double s = 0.0;
+    for (int r = 0; r < nr; ++r) s += un[r * K + a] * un[r * K + b];
+    part[(int64_t)blockIdx.x * K * K + i] = s;
+  }
+}
+
+// Sum K x K partials in workgroup order, Cholesky A = R^T R, Rinv = R^-1.
+// flag bit 0 set when a pivot is not positive relative to the largest diagonal.
+__global__ void k_chol_inv(const double* __restrict__ part, int nparts, int K, double* __restrict__ Rinv,
+                           int* __restrict__ flag) {
+  extern __shared__ double shd[];
+  double* A = shd;          // K * K
+  double* Rm = A + K * K;   // K * K
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
+    double s = 0.0;
+    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * K * K + i];
+    A[i] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double dmax = 0.0;
+    for (int i = 0; i < K; ++i) dmax = fmax(dmax, A[i * K + i]);
+    bool ok = dmax > 0.0;
+    for (int i = 0; i < K * K; ++i) Rm[i] = 0.0;
+    for (int j = 0; j < K && ok; ++j) {
+      double d = A[j * K + j];
+      for (int k = 0; k < j; ++k) d -= Rm[k * K + j] * Rm[k * K + j];
+      if (!(d > 1e-24 * dmax)) { ok = false; break; }
+      const double rjj = sqrt(d);
+      Rm[j * K + j] = rjj;
+      for (int i = j + 1; i < K; ++i) {
+        double s = A[j * K + i];
+        for (int k = 0; k < j; ++k) s -= Rm[k * K + j] * Rm[k * K + i];
+        Rm[j * K + i] = s / rjj;
+      }
+    }
+    if (!ok) {
+      flag[0] |= 1;
+      for (int i = 0; i < K * K; ++i) Rinv[i] = (i / K == i % K) ? 1.0 : 0.0;
+    } else {
+      // inverse of upper triangular R, column by column
+      for (int i = 0; i < K * K; ++i) Rinv[i] = 0.0;
+      for (int j = 0; j < K; ++j) {
+        Rinv[j * K + j] = 1.0 / Rm[j * K + j];
+        for (int i = j - 1; i >= 0; --i) {
+          double s = 0.0;
+          for (int k = i + 1; k <= j; ++k) s += Rm[i * K + k] * Rinv[k * K + j];
+          Rinv[i * K + j] = -s / Rm[i * K + i];
+        }
+      }
+    }
+  }
+}
+
+// W = V_K diag(lam)^(-1/2); a column with a non-positive or negligible
+// eigenvalue (relative to the largest) is zeroed and flagged (bit 1).
+__global__ void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam, int khat, int K,
+                         double* __restrict__ W, int* __restrict__ flag) {
+  const double l0 = lam[0];
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < khat * K; i += gridDim.x * blockDim.x) {
+    const int k = i % K;
+    const bool ok = k < khat && l0 > 0.0 && lam[k] > 1e-13 * l0 * (double)khat;  // only khat eigenpairs exist
+    W[i] = ok ? VK[i] / sqrt(lam[k]) : 0.0;
+    if (!ok && i < K) atomicOr(flag, 2);
+  }
+}
+
+// F64[row_slice[r]] = U[r]; FP32 / BF16 copies of the same rows.
+__global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
+                                 double* __restrict__ F64, float* __restrict__ F32, int kp32,
+                                 uint16_t* __restrict__ F16, int kp16) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R * K; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / K;
+    const int k = (int)(i - r * K);
+    const int64_t l = row_slice[r];
+    const double v = U[i];
+    F64[l * K + k] = v;
+    F32[l * kp32 + k] = (float)v;
+    if (F16) {
+      const float f = (float)v;
+      uint32_t b = __float_as_uint(f);
+      b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
+      F16[l * kp16 + k] = (uint16_t)(b >> 16);
+    }
+  }
+}
+
+// FP32 / BF16 working copies of a whole FP64 factor (padding stays zero).
+__global__ void k_factor_copies(const double* __restrict__ F64, int64_t L, int K, float* __restrict__ F32, int kp32,
+                                uint16_t* __restrict__ F16, int kp16) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * K; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = i / K;
+    const int k = (int)(i - l * K);
+    const float f = (float)F64[i];
+    F32[l * kp32 + k] = f;
+    uint32_t b = __float_as_uint(f);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    F16[l * kp16 + k] = (uint16_t)(b >> 16);
+  }
+}
+
+void refresh_factor_copies(Ctx* c, int n) {
+  const int64_t L = c->dims[n];
+  const int K = c->K[n];
+  TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
+  TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+  hipLaunchKernelGGL(k_factor_copies, dim3(grid_for(L * K, 256)), dim3(256), 0, c->stream, c->F64[n].as<double>(), L,
+                     K, c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
+  TK_CHECK_LAUNCH();
+}
+
+// Host-side completion of a rank-deficient factor (rare): orthonormalise the
+// computed columns by modified Gram-Schmidt with reorthogonalisation, drop the
+// ones that vanish, and fill the rest with unit vectors e_i (lowest i first).
+static void complete_on_host(Ctx* c, int n) {
+  const int64_t L = c->dims[n];
+  const int K = c->K[n];
+  std::vector<double> F((size_t)L * K);
+  d2h(c, F.data(), c->F64[n].as<double>(), F.size());
+  c->sync();
+  std::vector<std::vector<double>> cols;
+  for (int k = 0; k < K; ++k) {
+    std::vector<double> v(L);
+    double n0 = 0;
+    for (int64_t i = 0; i < L; ++i) { v[i] = F[i * K + k]; n0 += v[i] * v[i]; }
+    n0 = std::sqrt(n0);
+    if (n0 == 0) continue;
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& u : cols) {
+        double d = 0;
+        for (int64_t i = 0; i < L; ++i) d += u[i] * v[i];
+        for (int64_t i = 0; i < L; ++i) v[i] -= d * u[i];
+      }
+    double nv = 0;
+    for (int64_t i = 0; i < L; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    if (nv > 1e-6 * n0) {
+      for (auto& x : v) x /= nv;
+      cols.push_back(std::move(v));
+    }
+  }
+  for (int64_t e = 0; (int)cols.size() < K && e < L; ++e) {
+    std::vector<double> v(L, 0.0);
+    v[e] = 1.0;
+    for (int pass = 0; pass < 2; ++pass)
+      for (auto& u : cols) {
+        double d = 0;
+        for (int64_t i = 0; i < L; ++i) d += u[i] * v[i];
+        for (int64_t i = 0; i < L; ++i) v[i] -= d * u[i];
+      }
+    double nv = 0;
+    for (int64_t i = 0; i < L; ++i) nv += v[i] * v[i];
+    nv = std::sqrt(nv);
+    if (nv > 0.5) {
+      for (auto& x : v) x /= nv;
+      cols.push_back(std::move(v));
+    }
+  }
+  for (int k = 0; k < K; ++k)
+    for (int64_t i = 0; i < L; ++i) F[i * K + k] = cols[k][i];
+  h2d(c, c->F64[n].as<double>(), F.data(), F.size());
+  refresh_factor_copies(c, n);
+  c->sync();
+}
+
+// New factor n from Y (R x khat) and the leading eigenpairs (lam_k, VK).
+// Returns true when the completion path ran.
+bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
+                 int* flag_dev, bool check_flag) {
+  const int K = c->K[n];
+  const int64_t L = c->dims[n];
+  const int nwg = (int)std::max<int64_t>(1, ceil_div(R, FT_ROWS));
+  ensure(c, c->U64, sizeof(double) * (size_t)std::max<int64_t>(R, 1) * K);
+  ensure(c, c->small64, sizeof(double) * ((size_t)khat * K + 2 * (size_t)K * K + (size_t)nwg * K * K));
+  double* W = c->small64.as<double>();
+  double* Rinv = W + (size_t)khat * K;
+  double* part = Rinv + (size_t)K * K;
+  double* U = c->U64.as<double>();
+  TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, khat,
+                     K, W, flag_dev);
+  TK_CHECK_LAUNCH();
+  if (R > 0) {
+    size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
+    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat x K too large for LDS");
+    hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+    TK_CHECK_LAUNCH();
+    for (int pass = 0; pass < 2; ++pass) {
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), sizeof(double) * 2 * K * K, c->stream, part, nwg, K, Rinv,
+                         flag_dev);
+      TK_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_apply_rinv, dim3(nwg), dim3(256), sizeof(double) * ((size_t)K * K + 2 * FT_ROWS * K),
+                         c->stream, U, R, K, Rinv, part);
+      TK_CHECK_LAUNCH();
+    }
+  }
+  TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
+  TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
+  TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+  if (R > 0) {
+    hipLaunchKernelGGL(k_scatter_factor, dim3(grid_for(R * K, 256)), dim3(256), 0, c->stream, U, R, K,
+                       c->plan[n].row_slice.as<int32_t>(), c->F64[n].as<double>(), c->F32[n].as<float>(), c->kp32[n],
+                       c->F16[n].as<uint16_t>(), c->kp16[n]);
+    TK_CHECK_LAUNCH();
+  }
+  if (!check_flag && R >= K) return false;
+  int hflag = 0;
+  d2h(c, &hflag, flag_dev, 1);
+  c->sync();
+  if (hflag || R < K) {
+    if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
+    (void)L;
+    complete_on_host(c, n);
+    return true;
+  }
+  return false;
+}
+
+}  // namespace tk

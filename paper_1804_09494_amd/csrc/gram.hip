@@ -1,0 +1,178 @@
+// Gram matrix G = Y^T Y of the compact penultimate matrix (R rows x Khat
+// columns, FP32 row-major) on the matrix cores.  It replaces the paper's
+// Lanczos queries (Section 3, "SVD Component"): the leading left singular
+// vectors of Y are Y V S^-1 for the leading eigenpairs (V, S^2) of G.
+//
+// v_mfma_f32_16x16x4_f32: lane l supplies A[i = l%16][k = l/16] and
+// B[k = l/16][j = l%16]; with A = Y^T and B = Y both operands are
+// Y[row0 + l/16][col0 + l%16], i.e. one coalesced load of four 64-byte row
+// pieces feeds every tile in the same column block.  The result tile holds
+// D[4*(l/16) + r][l%16] in register r.
+//
+// Each wave accumulates its share of 4-row steps for a set of 16x16 tiles;
+// the four waves of a workgroup are combined in LDS in fixed order and each
+// workgroup writes one FP32 partial; a second kernel sums the partials in
+// FP64 in workgroup order (deterministic) and mirrors the upper triangle.
+#include "common.hpp"
+
+namespace tk {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// Tiles (bi, bj) of the macro pair: bi in [I0, I0+NBA), bj in [J0, J0+NBB);
+// DIAG = the pair is on the diagonal and only bi <= bj is computed.
+template <int NBA, int NBB, bool DIAG>
+struct TileSet {
+  static constexpr int count = DIAG ? NBA * (NBA + 1) / 2 : NBA * NBB;
+  __device__ static constexpr int ti(int t) {
+    if (!DIAG) return t / NBB;
+    int i = 0;
+    while (t >= NBA - i) { t -= NBA - i; ++i; }
+    return i;
+  }
+  __device__ static constexpr int tj(int t) {
+    if (!DIAG) return t % NBB;
+    int i = 0;
+    while (t >= NBA - i) { t -= NBA - i; ++i; }
+    return i + t;
+  }
+};
+
+// Macro pair of blockIdx.y: diagonal launches take (p, p); off-diagonal
+// launches enumerate I < J row by row.
+__device__ __forceinline__ void macro_pair(bool diag, int p, int MB, int& I, int& J) {
+  if (diag) { I = J = p; return; }
+  I = 0;
+  while (p >= MB - 1 - I) { p -= MB - 1 - I; ++I; }
+  J = I + 1 + p;
+}
+
+template <int NBA, int NBB, bool DIAG>
+__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64_t R, int khat, int rows_per_wg,
+                                              int MB, float* __restrict__ part) {
+  using TS = TileSet<NBA, NBB, DIAG>;
+  constexpr int T = TS::count;
+  extern __shared__ float red[];  // T * 256 floats
+  const int pair = blockIdx.y;
+  int PI, PJ;
+  macro_pair(DIAG, pair, MB, PI, PJ);
+  const int I0 = PI * NBA, J0 = PJ * NBB;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = min(r0 + rows_per_wg, R);
+  floatx4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int64_t r = r0 + 4 * wave; r < r1; r += 16) {
+    const int64_t row = r + lr;
+    const bool rok = row < r1;
+    float xa[NBA], xb[NBB];
+#pragma unroll
+    for (int b = 0; b < NBA; ++b) {
+      const int col = (I0 + b) * 16 + lc;
+      xa[b] = (rok && col < khat) ? Y[row * khat + col] : 0.f;
+    }
+    if constexpr (DIAG) {
+#pragma unroll
+      for (int b = 0; b < NBB; ++b) xb[b] = xa[b];
+    } else {
+#pragma unroll
+      for (int b = 0; b < NBB; ++b) {
+        const int col = (J0 + b) * 16 + lc;
+        xb[b] = (rok && col < khat) ? Y[row * khat + col] : 0.f;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < T; ++t)
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[TS::ti(t)], xb[TS::tj(t)], acc[t], 0, 0, 0);
+  }
+  // combine the four waves in fixed order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float* dst = red + t * 256 + q * 64 + lane;
+          *dst = (w == 0) ? acc[t][q] : *dst + acc[t][q];
+        }
+    }
+    __syncthreads();
+  }
+  float* out = part + ((int64_t)pair * gridDim.x + blockIdx.x) * (int64_t)T * 256;
+  for (int i = threadIdx.x; i < T * 256; i += blockDim.x) out[i] = red[i];
+}
+
+// Sum partials over the row chunks in FP64 and scatter into the full symmetric G.
+template <int NBA, int NBB, bool DIAG>
+__global__ void k_gram_reduce(const float* __restrict__ part, int nchunks, int MB, int khat,
+                              double* __restrict__ G) {
+  using TS = TileSet<NBA, NBB, DIAG>;
+  constexpr int T = TS::count;
+  const int pair = blockIdx.y;
+  int PI, PJ;
+  macro_pair(DIAG, pair, MB, PI, PJ);
+  const int I0 = PI * NBA, J0 = PJ * NBB;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;  // element of the T x 256 tile set
+  if (i >= T * 256) return;
+  const int t = i >> 8, e = i & 255;
+  const int q = e >> 6, lane = e & 63;
+  // register q of lane holds D[4*(lane/16) + q][lane%16]
+  const int rr = 4 * (lane >> 4) + q, cc = lane & 15;
+  const int gi = (I0 + TS::ti(t)) * 16 + rr;
+  const int gj = (J0 + TS::tj(t)) * 16 + cc;
+  if (gi >= khat || gj >= khat) return;
+  if (DIAG && TS::ti(t) == TS::tj(t) && rr > cc) return;  // the (cc, rr) thread writes both halves
+  double s = 0.0;
+  const float* p = part + (int64_t)pair * nchunks * T * 256 + i;
+  for (int k = 0; k < nchunks; ++k) s += (double)p[(int64_t)k * T * 256];
+  G[(int64_t)gi * khat + gj] = s;
+  G[(int64_t)gj * khat + gi] = s;
+}
+
+template <int NBA, int NBB, bool DIAG>
+static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, int MB, double* G) {
+  using TS = TileSet<NBA, NBB, DIAG>;
+  constexpr int T = TS::count;
+  if (npairs == 0) return;
+  int64_t target_wgs = std::max<int64_t>(1, 2048 / npairs);
+  int rows_per_wg = (int)std::max<int64_t>(64, ceil_div(ceil_div(R, target_wgs), 16) * 16);
+  int nchunks = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
+  ensure(c, c->gram_part, sizeof(float) * (size_t)npairs * nchunks * T * 256);
+  float* part = c->gram_part.as<float>();
+  hipLaunchKernelGGL((k_gram<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
+                     c->stream, Y, R, khat, rows_per_wg, MB, part);
+  TK_CHECK_LAUNCH();
+  hipLaunchKernelGGL((k_gram_reduce<NBA, NBB, DIAG>), dim3((T * 256 + 255) / 256, npairs), dim3(256), 0, c->stream,
+                     part, nchunks, MB, khat, G);
+  TK_CHECK_LAUNCH();
+}
+
+// G (khat x khat FP64, full) = Y^T Y.
+void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
+  const int NB = (khat + 15) / 16;
+  if (R == 0) {
+    TK_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)khat * khat, c->stream));
+    return;
+  }
+  if (NB <= 8) {
+    switch (NB) {
+      case 1: run_gram<1, 1, true>(c, Y, R, khat, 1, 1, G); break;
+      case 2: run_gram<2, 2, true>(c, Y, R, khat, 1, 1, G); break;
+      case 3: run_gram<3, 3, true>(c, Y, R, khat, 1, 1, G); break;
+      case 4: run_gram<4, 4, true>(c, Y, R, khat, 1, 1, G); break;
+      case 5: run_gram<5, 5, true>(c, Y, R, khat, 1, 1, G); break;
+      case 6: run_gram<6, 6, true>(c, Y, R, khat, 1, 1, G); break;
+      case 7: run_gram<7, 7, true>(c, Y, R, khat, 1, 1, G); break;
+      default: run_gram<8, 8, true>(c, Y, R, khat, 1, 1, G); break;
+    }
+    return;
+  }
+  // macro blocks of 4 column blocks (64 columns): diagonal pairs and the upper off-diagonal pairs
+  const int MB = (NB + 3) / 4;
+  run_gram<4, 4, true>(c, Y, R, khat, MB, MB, G);
+  run_gram<4, 4, false>(c, Y, R, khat, MB * (MB - 1) / 2, MB, G);
+}
+
+}  // namespace tk
