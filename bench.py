@@ -39,6 +39,28 @@ def algorithmic_bytes(m, N, R, khat, dims, ranks, n):
     return b
 
 
+COPY_BYTES = 1 << 31
+
+
+def device_copy_bandwidth(torch):
+    """Device-to-device copy of 2 GiB (read + write counted): the measured
+    reference next to the 8 TB/s peak, and the known-size kernel the HBM
+    byte counters are scaled against."""
+    src = torch.empty(COPY_BYTES, dtype=torch.uint8, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 5
+    del src, dst
+    return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
+
+
 def cpu_baseline(w, target_s=15.0):
     """The oracle's TTM-chain (FP64, NumPy) on the first nonzeros of the same
     workload, grown until it runs for about target_s seconds."""
@@ -108,6 +130,7 @@ def main():
     m, _ = ctx.tensor_info()
     print(f"# coalesced m'={m} load {load_s:.2f}s partition+layout {part_s:.2f}s", file=sys.stderr, flush=True)
 
+    copy_gbs = device_copy_bandwidth(torch)
     if args.warmup > 0:
         ctx.hooi_iterate(args.warmup)
     torch.cuda.synchronize()
@@ -160,6 +183,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
                      "kernel": "k_ttm<10,10,2,true> (TTM-chain)",
                      "bytes_per_launch": [int(b) for b in B]},
+        "device_copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -13,7 +13,8 @@
  *     fastest) into row l_n of Y_(n);
  *   - the leading K_n left singular vectors of Y_(n) as the new factor
  *     (Section 2.2, HOOI figure), here through the Gram matrix Y^T Y, an FP64
- *     eigensolve, U = Y V S^-1 and FP64 CholeskyQR2;
+ *     eigensolve (Householder tridiagonalisation, bisection, inverse
+ *     iteration), U = Y V S^-1 and FP64 CholeskyQR2;
  *   - the core G = T x_1 F_1^T ... x_N F_N^T once after the invocations
  *     (Section 2.2);
  *   - the elements of each mode are split over GPU workgroups ("bins") by the
@@ -69,11 +70,9 @@ typedef enum { TK_SWEEP_GAUSS_SEIDEL = 0, TK_SWEEP_JACOBI = 1 } tk_sweep;
 typedef struct {
   int32_t prec;                   /* tk_prec of the Kronecker tiles and the Gram (default TK_FP32) */
   int32_t sweep;                  /* tk_sweep (default Gauss-Seidel: mode n uses factors refined earlier in the invocation) */
-  int64_t wg_nnz_target;          /* target elements per bin (default 4096) */
+  int64_t wg_nnz_target;          /* target elements per bin (default 1024) */
   int32_t lds_rows_cap;           /* max slices per bin; 0 = from the LDS budget */
   int32_t refine;                 /* BF16 only: 1 = the last invocation runs in FP32 (default 1) */
-  int32_t max_jacobi_sweeps;      /* eigensolver sweep cap (default 30) */
-  double eig_tol;                 /* eigensolver off-diagonal tolerance, relative (default 1e-15) */
   int64_t mem_limit_bytes;        /* 0 = no limit; plans above it fail with TK_ERR_OOM before allocating */
   int32_t complete_rank_deficient;/* 1 (default) = complete U with unit vectors; 0 = TK_ERR_NUMERIC */
   int32_t keep_elem_order;        /* 1 (default) = keep each mode's element order for tk_get_partition */

@@ -24,7 +24,7 @@ TK_SWEEP_GAUSS_SEIDEL, TK_SWEEP_JACOBI = 0, 1
 
 class tk_options(ctypes.Structure):
     _fields_ = [("prec", c_i32), ("sweep", c_i32), ("wg_nnz_target", c_i64), ("lds_rows_cap", c_i32),
-                ("refine", c_i32), ("max_jacobi_sweeps", c_i32), ("eig_tol", c_f64), ("mem_limit_bytes", c_i64),
+                ("refine", c_i32), ("mem_limit_bytes", c_i64),
                 ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32)]
 
 

@@ -3,7 +3,7 @@
 // HOOI invocation (Section 2.2 and its figure), one mode at a time:
 //   Y_(n) = TTM-chain of T with the other factors (eq. 1)      -> ttm.hip
 //   G     = Y^T Y on the matrix cores                           -> gram.hip
-//   leading K_n eigenpairs of G in FP64 (Jacobi, warm start)    -> eig.hip
+//   leading K_n eigenpairs of G in FP64 (tridiagonal + bisection) -> eig.hip
 //   F_n   = orthonormalised Y V_K S_K^-1 (CholeskyQR2, FP64)    -> factor.hip
 // After the last mode the core G_(N) = F_N^T Y_(N) and the fit  -> core.hip
 // Gauss-Seidel by default: mode n uses factors already refined in this
@@ -20,8 +20,7 @@
 namespace tk {
 
 void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G);
-void eig_topk(Ctx* c, const double* G, int n0, int K, double* Vwarm, bool have_warm, double* lam_k, double* VK,
-              int* info_dev);
+void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK);
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
                  int* flag_dev, bool check_flag);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
@@ -117,7 +116,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       ModePlan& pl = c->plan[n];
       const int khat = (int)pl.khat;
       const int K = c->K[n];
-      TK_REQUIRE(K <= 64, TK_ERR_UNSUPPORTED, "rank above 64");
+      TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "HOOI supports ranks up to 32");
       hipEvent_t t0 = pool.next();
       TK_HIP(hipEventRecord(t0, c->stream));
       hipEvent_t k0 = pool.next(), k1 = pool.next();
@@ -142,14 +141,9 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       hipEvent_t t1 = mark("ttm[" + std::to_string(n) + "]", t0);
       gram(c, Y, pl.L_nz, khat, c->gram64.as<double>());
       hipEvent_t t2 = mark("gram", t1);
-      if (!c->eigv_mode[n]) {
-        c->eigv_mode[n].alloc(c, sizeof(double) * (size_t)khat * khat);
-      }
       double* lam_k = c->eig_val.as<double>();
       double* VK = lam_k + 64;
-      eig_topk(c, c->gram64.as<double>(), khat, K, c->eigv_mode[n].as<double>(), c->eig_warm[n], lam_k, VK,
-               c->flag.as<int>() + 1);
-      c->eig_warm[n] = true;
+      eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK);
       hipEvent_t t3 = mark("eig", t2);
       form_factor(c, n, Y, pl.L_nz, khat, lam_k, VK, c->flag.as<int>(), true);
       mark("factor", t3);
@@ -222,11 +216,9 @@ tk_status tk_default_options(tk_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->prec = TK_FP32;
   o->sweep = TK_SWEEP_GAUSS_SEIDEL;
-  o->wg_nnz_target = 4096;
+  o->wg_nnz_target = 1024;
   o->lds_rows_cap = 0;
   o->refine = 1;
-  o->max_jacobi_sweeps = 30;
-  o->eig_tol = 1e-15;
   o->mem_limit_bytes = 0;
   o->complete_rank_deficient = 1;
   o->keep_elem_order = 1;
@@ -313,8 +305,6 @@ tk_status tk_load_coo(tk_ctx* c, int N, const int64_t* dims, int64_t nnz, const 
       c->F64[j].release();
       c->F32[j].release();
       c->F16[j].release();
-      c->eigv_mode[j].release();
-      c->eig_warm[j] = false;
     }
     load_coo(c, N, dims, nnz, idx, vals, mem);
   });
@@ -366,8 +356,9 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
                  c->opt.keep_elem_order != 0);
     }
+    for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);
     for (int n = 0; n < N; ++n) {
-      c->kp32[n] = (K[n] + 3) & ~3;
+      c->kp32[n] = K[n] <= 16 ? 16 : (K[n] + 3) & ~3;  // 64-byte rows: one 16-lane MFMA operand load
       c->kp16[n] = (K[n] + 7) & ~7;
       c->F64[n].alloc(c, sizeof(double) * (size_t)c->dims[n] * K[n]);
       c->F32[n].alloc(c, sizeof(float) * (size_t)c->dims[n] * c->kp32[n]);
@@ -376,8 +367,6 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       for (int k = 0; k < K[n]; ++k) I[(size_t)k * K[n] + k] = 1.0;
       h2d(c, c->F64[n].as<double>(), I.data(), I.size());
       refresh_factor_copies(c, n);
-      c->eigv_mode[n].release();
-      c->eig_warm[n] = false;
       c->sync();
     }
     c->have_ranks = true;
@@ -418,7 +407,6 @@ tk_status tk_set_factor(tk_ctx* c, int n, const double* F, tk_mem mem) {
     TK_REQUIRE(n >= 0 && n < c->N && F, TK_ERR_INVALID_ARG, "mode out of range or F is NULL");
     copy_in(c, c->F64[n].as<double>(), F, (size_t)c->dims[n] * c->K[n], mem);
     refresh_factor_copies(c, n);
-    c->eig_warm[n] = false;
     c->sync();
   });
 }

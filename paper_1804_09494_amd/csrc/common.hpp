@@ -38,6 +38,8 @@ struct Error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+constexpr int FIX_CHUNK = 32;  // partial rows summed per first-level fixup block
+
 struct Ctx;
 
 // Device allocation owned by a Buf; freed on destruction.  Allocation goes
@@ -78,15 +80,28 @@ struct ModePlan {
   int64_t khat = 0;
   int rows_cap = 0;       // LDS rows per bin the TTM kernel was sized for
   Buf row_slice;          // int32[L_nz]  slice id of each compact row (ascending)
+  Buf label;              // int32[L]     storage row of each index in the working factor copies:
+                          //              descending slice size (hot rows packed first)
   Buf bin_ptr;            // int64[P+1]
   Buf seg_ptr;            // int32[P+1]
   Buf seg_row;            // int32[S]     compact row of each segment
   Buf seg_begin;          // int64[S+1]
   Buf seg_slot;           // int32[S]     -1 = good, else partial-row slot
+  // The TTM-chain streams a padded copy of the layout: every segment is padded
+  // to a multiple of 4 elements with zero-valued elements (coordinate 0), so an
+  // MFMA step over 4 consecutive elements never straddles two slices.
+  int64_t m_pad = 0;      // padded layout length
+  int64_t E_pad_max = 0;  // largest padded bin
+  Buf bin_pptr;           // int64[P+1]   padded bin offsets
+  Buf seg_pbegin;         // int64[S+1]   padded segment offsets
+  Buf order_pad;          // uint32[m_pad] element index at each padded position (0xffffffff = padding)
   Buf bad_row;            // int32[n_bad]
   Buf bad_slot;           // int32[n_bad+1] slots of bad slice k: [bad_slot[k], bad_slot[k+1])
-  Buf lay_idx[7];         // int32[m] other modes' coordinates in layout order (modes ascending)
-  Buf lay_val;            // float[m]
+  int64_t n_chunks = 0;   // fixup level 1: chunks of at most FIX_CHUNK consecutive slots of one bad slice
+  Buf chunk_slot;         // int32[n_chunks+1] first slot of each chunk (last entry = n_slots)
+  Buf chunk_ptr;          // int32[n_bad+1] chunks of bad slice k: [chunk_ptr[k], chunk_ptr[k+1])
+  Buf lay_idx[7];         // int32[m_pad] other modes' coordinates in padded layout order (modes ascending)
+  Buf lay_val;            // float[m_pad]
   Buf lay_val_bf16;       // bf16[m] (precision form)
   Buf elem_order;         // uint32[m] canonical element index per layout position (optional)
 };
@@ -152,10 +167,7 @@ struct Ctx {
   Buf work;               // general scratch
   Buf gram_part;          // float/double partial Grams
   Buf gram64;             // double[Khat x Khat]
-  Buf eig_vec;            // double[Khat x Khat] eigenvectors (warm start), per mode
   Buf eig_val;            // double[Khat]
-  Buf eigv_mode[8];       // double[Khat_n x Khat_n] last eigenvectors per mode (warm start)
-  bool eig_warm[8] = {false, false, false, false, false, false, false, false};
   Buf U64;                // double[R_n x K_n]
   Buf small64;            // double scratch for K x K matrices, reductions
   Buf core64;             // double[prod K]
@@ -236,10 +248,12 @@ void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* co
               tk_mem mem);
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
                 int64_t khat, int tile_w, bool keep_order);
+void relabel_layout(Ctx* c, ModePlan& pl, int N, int n, const ModePlan* plans, int64_t m);
 void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t* elem_order, int32_t* seg_bin,
                       int32_t* seg_slice, int64_t* seg_begin, uint8_t* seg_bad, tk_mem mem);
 int ttm_rows_cap(Ctx* c, int64_t tile_w);
 int ttm_tile_width(int N, const int32_t* K, int n);
+bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
              const float* lay_val, int64_t m, float* Y);

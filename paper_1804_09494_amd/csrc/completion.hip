@@ -60,7 +60,7 @@ void load_obs(Ctx* c, int N, const int64_t* dims, const int32_t* ranks, int64_t 
     maxY = std::max(maxY, o.plan[n].L_nz * khat);
   }
   for (int j = 0; j < N; ++j) {
-    o.kp[j] = (ranks[j] + 3) & ~3;
+    o.kp[j] = ranks[j] <= 16 ? 16 : (ranks[j] + 3) & ~3;
     o.F32[j].alloc(c, sizeof(float) * (size_t)dims[j] * o.kp[j]);
   }
   o.gl.alloc(c, sizeof(float) * (size_t)std::max<int64_t>(n_obs, 1));
@@ -182,8 +182,10 @@ __global__ void k_pad_copy(const float* __restrict__ src, int64_t L, int K, floa
 
 __global__ void k_gather_layout(const float* __restrict__ g, const uint32_t* __restrict__ order, int64_t m,
                                 float* __restrict__ out) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = g[order[i]];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t e = order[i];
+    out[i] = e == 0xffffffffu ? 0.f : g[e];   // padding positions carry zero
+  }
 }
 
 // Linear core index of (c_n = k, other modes from col with the first remaining mode fastest).
@@ -263,8 +265,9 @@ void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* 
   for (int n = 0; n < N; ++n) {
     ModePlan& pl = o.plan[n];
     const int khat = (int)pl.khat;
-    hipLaunchKernelGGL(k_gather_layout, dim3(grid_for(o.n_obs, 256)), dim3(256), 0, c->stream, gd,
-                       pl.elem_order.as<uint32_t>(), o.n_obs, o.gl.as<float>());
+    ensure(c, o.gl, sizeof(float) * (size_t)std::max<int64_t>(pl.m_pad, 1));
+    hipLaunchKernelGGL(k_gather_layout, dim3(grid_for(pl.m_pad, 256)), dim3(256), 0, c->stream, gd,
+                       pl.order_pad.as<uint32_t>(), pl.m_pad, o.gl.as<float>());
     TK_CHECK_LAUNCH();
     float* Yg = o.Yg.as<float>();
     ttm_run(c, pl, N, n, o.K, Fp, o.kp, o.gl.as<float>(), o.n_obs, Yg);

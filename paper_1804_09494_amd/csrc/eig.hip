@@ -1,241 +1,425 @@
-// FP64 symmetric eigensolver for the Gram matrix (Khat x Khat): cyclic
-// two-sided Jacobi in one workgroup, parallel over disjoint rotation pairs.
+// FP64 symmetric eigensolver for the Gram matrix G = Y^T Y (Khat x Khat):
+// the leading K_n eigenpairs give the leading K_n left singular vectors of Y
+// (Section 2.2: the SVD step of an HOOI invocation) as Y V_K S_K^-1.
 //
-// The leading K_n left singular vectors of Y (Section 2.2: the SVD step of an
-// HOOI invocation) are Y V_K S_K^-1 for the K_n largest eigenpairs (V, S^2)
-// of G = Y^T Y.  Jacobi is used for its high relative accuracy on a small
-// dense matrix.  A warm start rotates G into the previous invocation's
-// eigenbasis first (A = V0^T G V0, V = V0), which leaves it nearly diagonal
-// once HOOI settles.
-//
-// Parallel ordering: a round-robin tournament over n (even) indices; round r
-// pairs (r, n-1) and ((r+k) mod (n-1), (r-k) mod (n-1)) for k = 1..n/2-1, so
-// the n/2 pairs of a round are disjoint and n-1 rounds cover every pair once.
-// A round computes all rotations from the current diagonal blocks, then
-// updates every 2x2 block (pair k1, pair k2) of A as J_k1^T B J_k2, with
-// J = [[c, s], [-s, c]] in rows/columns (p, q).  A is kept as a packed upper
-// triangle; V (row-major, column j = eigenvector j) is rotated alongside.
+// One workgroup, data resident in LDS when it fits:
+//   1. Householder tridiagonalisation G = Q T Q^T (lower variant: reflector k
+//      is I - tau_k v_k v_k^T on rows/columns k+1..n-1, v_k[0] = 1, kept in
+//      column k below the diagonal);
+//   2. the K largest eigenvalues of T by multisection: 16 threads per
+//      eigenvalue evaluate Sturm counts (eigenvalues of T below x, from the
+//      signs of the LDL^T pivots) at 16 interior points and keep the
+//      sub-interval that holds it, 17x narrower per round;
+//   3. eigenvectors of T by inverse iteration (tridiagonal LU with partial
+//      pivoting, distinct seeded starts), then modified Gram-Schmidt across the
+//      K vectors, one more inverse-iteration step and a second pass;
+//   4. back-transformation z <- H_0 ... H_{n-3} z, one wave per vector.
+#include <cmath>
+
 #include "common.hpp"
 
 namespace tk {
 
-__device__ __forceinline__ int64_t pk(int i, int j, int n) {
-  if (i > j) { int t = i; i = j; j = t; }
-  return (int64_t)i * (2 * n - i + 1) / 2 + (j - i);
+struct EigLayout {
+  // offsets (in doubles) into the LDS or global workspace
+  int64_t A, d, e, e2, tau, p, v, red, Z, lu, lam, brk, cnt, gm;
+  int64_t total;
+};
+
+static EigLayout eig_layout(int n, int K, bool a_in_ws) {
+  EigLayout L{};
+  int64_t o = 0;
+  const int64_t stride = n + 1;
+  L.A = a_in_ws ? o : -1;
+  if (a_in_ws) o += (int64_t)n * stride;
+  L.d = o; o += n;
+  L.e = o; o += n;
+  L.e2 = o; o += n;
+  L.tau = o; o += n;
+  L.p = o; o += n;
+  L.v = o; o += n;
+  L.red = o; o += 64;
+  L.Z = o; o += (int64_t)K * n;
+  L.lu = o; o += (int64_t)K * 3 * n;
+  L.lam = o; o += K;
+  L.brk = o; o += 2 * (int64_t)K;
+  L.cnt = o; o += 32 * (int64_t)K;   // ints stored in doubles' space (generous)
+  L.gm = o; o += 2 * (int64_t)K * K + 2;
+  L.total = o;
+  return L;
 }
 
-__device__ __forceinline__ void round_pair(int r, int k, int n, int& p, int& q) {
-  int a, b;
-  if (k == 0) {
-    a = r;
-    b = n - 1;
-  } else {
-    a = (r + k) % (n - 1);
-    b = (r - k + (n - 1)) % (n - 1);
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+constexpr int EIG_THREADS = 512;
+constexpr int EIG_WAVES = EIG_THREADS / 64;
+
+// Sum over the workgroup: wave sums, then every thread adds the wave partials in order.
+__device__ __forceinline__ double block_sum(double x, double* red) {
+  x = wave_sum(x);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
+  double s = 0.0;
+#pragma unroll
+  for (int w = 0; w < EIG_WAVES; ++w) s += red[w];
+  __syncthreads();
+  return s;
+}
+
+// Number of eigenvalues of the symmetric tridiagonal (d, e) below x.
+__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
+  int cnt = 0;
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  cnt += q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
   }
-  p = a < b ? a : b;
-  q = a < b ? b : a;
+  return cnt;
 }
 
-// G: n x n FP64 (full), V0: n x n warm start (row-major) or null.
-// Outputs: lam[j] (eigenvalues, unsorted), Vout n x n (row-major), sweeps used in info[0].
-// Workspace: A (packed) and V in LDS when `lds_mode` bits allow, else in gA/gV.
-__global__ __launch_bounds__(1024) void k_jacobi(const double* __restrict__ G, const double* __restrict__ V0, int n0,
-                                                 int n, int max_sweeps, double tol, int lds_mode,
-                                                 double* __restrict__ gA, double* __restrict__ gV,
-                                                 double* __restrict__ lam, double* __restrict__ Vout,
-                                                 int* __restrict__ info) {
-  extern __shared__ double sh[];
-  const int tid = threadIdx.x, nt = blockDim.x;
-  const int64_t npk = (int64_t)n * (n + 1) / 2;
-  double* cs = sh;                   // c[k], s[k]: 2 * (n/2)
-  int* pr = reinterpret_cast<int*>(sh + n);   // p[k], q[k]: n ints (= n/2 doubles)
-  double* red = sh + n + (n + 1) / 2;         // 1024 doubles of reduction space
-  double* base = red + 1024;
-  double* A = (lds_mode & 1) ? base : gA;
-  double* V = (lds_mode & 2) ? ((lds_mode & 1) ? base + npk : base) : gV;
+// Counter-based start vector entry (SplitMix64 mix of (j, i)) in [-1, 1).
+__device__ __forceinline__ double start_entry(int j, int i) {
+  unsigned long long z = 0x9E3779B97F4A7C15ULL * (unsigned long long)(j * 1315423911u + i + 1);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z ^= z >> 31;
+  return (double)(z >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
 
-  // A = V0^T G V0 (or G), V = V0 (or I); padded index n0..n-1 gets a zero row/column.
-  // With a warm start, V first holds T = G V0 (n0 x n0, row-major, stride n).
-  if (V0) {
-    for (int64_t e = tid; e < (int64_t)n0 * n0; e += nt) {
-      const int a = (int)(e / n0), j = (int)(e % n0);
-      double t = 0.0;
-      for (int b = 0; b < n0; ++b) t += G[(int64_t)a * n0 + b] * V0[(int64_t)b * n0 + j];
-      V[(int64_t)a * n + j] = t;
+// Modified Gram-Schmidt over the K rows of Z (each of length n), block-wide.
+__device__ void mgs_rows(double* Z, int K, int n, double* red) {
+  for (int j = 0; j < K; ++j) {
+    double* zj = Z + (int64_t)j * n;
+    for (int i = 0; i < j; ++i) {
+      const double* zi = Z + (int64_t)i * n;
+      double s = 0.0;
+      for (int t = threadIdx.x; t < n; t += blockDim.x) s += zi[t] * zj[t];
+      s = block_sum(s, red);
+      for (int t = threadIdx.x; t < n; t += blockDim.x) zj[t] -= s * zi[t];
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  for (int64_t e = tid; e < npk; e += nt) {
-    int i = (int)((2.0 * n + 1 - sqrt((2.0 * n + 1) * (2.0 * n + 1) - 8.0 * (double)e)) / 2);
-    while (i > 0 && pk(i, i, n) > e) --i;
-    while (i + 1 < n && pk(i + 1, i + 1, n) <= e) ++i;
-    const int j = i + (int)(e - pk(i, i, n));
     double s = 0.0;
-    if (i < n0 && j < n0) {
-      if (V0) {
-        for (int a = 0; a < n0; ++a) s += V0[(int64_t)a * n0 + i] * V[(int64_t)a * n + j];
-      } else {
-        s = G[(int64_t)i * n0 + j];
-      }
-    }
-    A[e] = s;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) s += zj[t] * zj[t];
+    s = block_sum(s, red);
+    const double inv = s > 0.0 ? 1.0 / sqrt(s) : 0.0;
+    for (int t = threadIdx.x; t < n; t += blockDim.x) zj[t] *= inv;
+    __syncthreads();
   }
-  __syncthreads();
-  for (int64_t e = tid; e < (int64_t)n * n; e += nt) {
-    const int i = (int)(e / n), j = (int)(e % n);
-    double v;
-    if (i < n0 && j < n0) v = V0 ? V0[(int64_t)i * n0 + j] : (i == j ? 1.0 : 0.0);
-    else v = (i == j) ? 1.0 : 0.0;
-    V[e] = v;
-  }
-  __syncthreads();
+}
 
-  const int half = n / 2;
-  int sweep = 0;
-  for (; sweep < max_sweeps; ++sweep) {
-    // convergence: off-diagonal Frobenius^2 <= tol^2 * diagonal Frobenius^2
-    double off = 0.0, dia = 0.0;
-    for (int64_t e = tid; e < npk; e += nt) {
-      int i = (int)((2.0 * n + 1 - sqrt((2.0 * n + 1) * (2.0 * n + 1) - 8.0 * (double)e)) / 2);
-      while (i > 0 && pk(i, i, n) > e) --i;
-      while (i + 1 < n && pk(i + 1, i + 1, n) <= e) ++i;
-      double x = A[e];
-      if (pk(i, i, n) == e) dia += x * x; else off += x * x;
+// Orthonormalise the K rows of Z by CholeskyQR twice (Gram matrix of the rows,
+// its Cholesky factor R, rows <- R^-T rows); falls back to modified
+// Gram-Schmidt when a pivot is not safely positive.  gm: 2*K*K doubles, tmp: K*n.
+__device__ void orth_rows(double* Z, int K, int n, double* gm, double* tmp, double* red, int* flag) {
+  double* R = gm + K * K;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
+      const int a = q / K, b = q % K;
+      double s = 0.0;
+      if (a <= b)
+        for (int t = 0; t < n; ++t) s += Z[(int64_t)a * n + t] * Z[(int64_t)b * n + t];
+      gm[q] = s;
     }
-    red[tid] = off;
-    if (tid + nt < 1024) red[tid + nt] = 0.0;
     __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w && tid + w < 1024) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double offs = red[0];
-    __syncthreads();
-    red[tid] = dia;
-    if (tid + nt < 1024) red[tid + nt] = 0.0;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if (tid < w && tid + w < 1024) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double dias = red[0];
-    __syncthreads();
-    if (offs <= tol * tol * dias || offs == 0.0) break;
-
-    for (int r = 0; r < n - 1; ++r) {
-      if (tid < half) {
-        int p, q;
-        round_pair(r, tid, n, p, q);
-        const double app = A[pk(p, p, n)], aqq = A[pk(q, q, n)], apq = A[pk(p, q, n)];
-        double c = 1.0, s = 0.0;
-        if (apq != 0.0) {
-          const double theta = (aqq - app) / (2.0 * apq);
-          double t;
-          if (fabs(theta) > 1e150) t = 0.5 / theta;
-          else t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-          c = 1.0 / sqrt(t * t + 1.0);
-          s = t * c;
+    if (threadIdx.x == 0) {
+      int ok = 1;
+      double dmax = 0.0;
+      for (int i = 0; i < K; ++i) dmax = fmax(dmax, gm[i * K + i]);
+      for (int i = 0; i < K * K; ++i) R[i] = 0.0;
+      for (int j = 0; j < K && ok; ++j) {
+        double d = gm[j * K + j];
+        for (int k = 0; k < j; ++k) d -= R[k * K + j] * R[k * K + j];
+        if (!(d > 1e-20 * dmax)) { ok = 0; break; }
+        const double rjj = sqrt(d);
+        R[j * K + j] = rjj;
+        for (int i = j + 1; i < K; ++i) {
+          double v = gm[j * K + i];
+          for (int k = 0; k < j; ++k) v -= R[k * K + j] * R[k * K + i];
+          R[j * K + i] = v / rjj;
         }
-        cs[2 * tid] = c;
-        cs[2 * tid + 1] = s;
-        pr[2 * tid] = p;
-        pr[2 * tid + 1] = q;
+      }
+      flag[0] = ok;
+    }
+    __syncthreads();
+    if (!flag[0]) {  // (rare) nearly dependent vectors
+      mgs_rows(Z, K, n, red);
+      return;
+    }
+    // rows: q_j = (z_j - sum_{i<j} R[i][j] q_i) / R[j][j], solved column by column in parallel over t
+    for (int t = threadIdx.x; t < n; t += blockDim.x) {
+      for (int j = 0; j < K; ++j) {
+        double v = Z[(int64_t)j * n + t];
+        for (int i = 0; i < j; ++i) v -= R[i * K + j] * tmp[(int64_t)i * n + t];
+        tmp[(int64_t)j * n + t] = v / R[j * K + j];
+      }
+      for (int j = 0; j < K; ++j) Z[(int64_t)j * n + t] = tmp[(int64_t)j * n + t];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restrict__ G, int n, int K, int Kout,
+                                                   int a_in_lds, int ws_in_lds, double* __restrict__ gws,
+                                                   double* __restrict__ lam_out, double* __restrict__ VK) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x;
+  const int stride = n + 1;
+  // workspace layout mirrors eig_layout(n, K, a_in_lds)
+  double* ws = ws_in_lds ? sh : gws;
+  int64_t o = 0;
+  double* A;
+  if (a_in_lds) {
+    A = ws;
+    o += (int64_t)n * stride;
+  } else {
+    A = gws;  // A occupies the head of the global workspace
+  }
+  if (!a_in_lds && !ws_in_lds) o += (int64_t)n * stride;
+  double* d = ws + o; o += n;
+  double* e = ws + o; o += n;
+  double* e2 = ws + o; o += n;
+  double* tau = ws + o; o += n;
+  double* p = ws + o; o += n;
+  double* v = ws + o; o += n;
+  double* red = ws + o; o += 64;
+  double* Z = ws + o; o += (int64_t)K * n;
+  double* lu = ws + o; o += (int64_t)K * 3 * n;
+  double* lam = ws + o; o += K;
+  double* brk = ws + o; o += 2 * K;
+  int* cnt = reinterpret_cast<int*>(ws + o); o += 32 * K;
+  double* gm = ws + o; o += 2 * K * K;
+  int* oflag = reinterpret_cast<int*>(ws + o);
+
+  for (int64_t t = tid; t < (int64_t)n * n; t += blockDim.x) {
+    const int i = (int)(t / n), j = (int)(t % n);
+    A[(int64_t)i * stride + j] = G[t];
+  }
+  __syncthreads();
+
+  // 1. tridiagonalisation
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;
+    double s = 0.0;
+    for (int i = tid + 1; i < m; i += blockDim.x) {
+      const double x = A[(int64_t)(k + 1 + i) * stride + k];
+      s += x * x;
+    }
+    const double xn2 = block_sum(s, red);
+    const double alpha = A[(int64_t)(k + 1) * stride + k];
+    if (tid == 0) d[k] = A[(int64_t)k * stride + k];
+    if (xn2 == 0.0) {
+      if (tid == 0) {
+        tau[k] = 0.0;
+        e[k] = alpha;
       }
       __syncthreads();
-      // 2x2 blocks (k1 <= k2)
-      const int nblk = half * (half + 1) / 2;
-      for (int b = tid; b < nblk; b += nt) {
-        int k1 = (int)((2.0 * half + 1 - sqrt((2.0 * half + 1) * (2.0 * half + 1) - 8.0 * b)) / 2);
-        auto start = [&](int k) { return k * (2 * half - k + 1) / 2; };
-        while (k1 > 0 && start(k1) > b) --k1;
-        while (k1 + 1 < half && start(k1 + 1) <= b) ++k1;
-        const int k2 = k1 + (b - start(k1));
-        const int p1 = pr[2 * k1], q1 = pr[2 * k1 + 1];
-        const double c1 = cs[2 * k1], s1 = cs[2 * k1 + 1];
-        if (k1 == k2) {
-          const int64_t ipp = pk(p1, p1, n), iqq = pk(q1, q1, n), ipq = pk(p1, q1, n);
-          const double app = A[ipp], aqq = A[iqq], apq = A[ipq];
-          A[ipp] = c1 * c1 * app - 2.0 * c1 * s1 * apq + s1 * s1 * aqq;
-          A[iqq] = s1 * s1 * app + 2.0 * c1 * s1 * apq + c1 * c1 * aqq;
-          A[ipq] = 0.0;
+      continue;
+    }
+    const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    const double t = (beta - alpha) / beta;
+    const double scale = 1.0 / (alpha - beta);
+    for (int i = tid; i < m; i += blockDim.x) {
+      const double vi = i == 0 ? 1.0 : A[(int64_t)(k + 1 + i) * stride + k] * scale;
+      v[i] = vi;
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += blockDim.x) A[(int64_t)(k + 1 + i) * stride + k] = v[i];
+    // p = t * A22 v, four threads per row (quad reduction)
+    for (int i0 = 0; i0 < m; i0 += EIG_THREADS / 4) {
+      const int i = i0 + (tid >> 2), sub = tid & 3;
+      double acc = 0.0;
+      if (i < m) {
+        const double* row = A + (int64_t)(k + 1 + i) * stride + (k + 1);
+        for (int j = sub; j < m; j += 4) acc += row[j] * v[j];
+      }
+      acc += __shfl_xor(acc, 1, 64);
+      acc += __shfl_xor(acc, 2, 64);
+      if (i < m && sub == 0) p[i] = t * acc;
+    }
+    __syncthreads();
+    double pv = 0.0;
+    for (int i = tid; i < m; i += blockDim.x) pv += p[i] * v[i];
+    pv = block_sum(pv, red);
+    const double kc = 0.5 * t * pv;
+    for (int i = tid; i < m; i += blockDim.x) p[i] -= kc * v[i];
+    __syncthreads();
+    for (int64_t q = tid; q < (int64_t)m * m; q += blockDim.x) {
+      const int i = (int)(q / m), j = (int)(q % m);
+      A[(int64_t)(k + 1 + i) * stride + (k + 1 + j)] -= v[i] * p[j] + p[i] * v[j];
+    }
+    if (tid == 0) {
+      tau[k] = t;
+      e[k] = beta;
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    if (n >= 2) {
+      d[n - 2] = A[(int64_t)(n - 2) * stride + (n - 2)];
+      e[n - 2] = A[(int64_t)(n - 1) * stride + (n - 2)];
+      tau[n - 2] = 0.0;
+    }
+    d[n - 1] = A[(int64_t)(n - 1) * stride + (n - 1)];
+    e[n - 1] = 0.0;
+    tau[n - 1] = 0.0;
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += blockDim.x) e2[i] = e[i] * e[i];
+  __syncthreads();
+  // Gershgorin bounds and scales
+  double glo = 1e300, ghi = -1e300, emax = 0.0, tnorm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    glo = fmin(glo, d[i] - r);
+    ghi = fmax(ghi, d[i] + r);
+    emax = fmax(emax, i + 1 < n ? e2[i] : 0.0);
+    tnorm = fmax(tnorm, fabs(d[i]) + r);
+  }
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = fmax(2.2250738585072014e-308, eps * eps * emax);
+  const double widen = 2.0 * eps * fmax(fabs(glo), fabs(ghi)) + pivmin;
+  glo -= widen;
+  ghi += widen;
+  __syncthreads();
+
+  // 2. the K largest eigenvalues by multisection (32 threads per eigenvalue, 33x narrower per round)
+  constexpr int MS = 32;
+  for (int j0 = 0; j0 < K; j0 += EIG_THREADS / MS) {
+    const int g = tid / MS, q = tid % MS;
+    const int j = j0 + g;
+    const bool act = j < K;
+    if (act && q == 0) {
+      brk[2 * j] = glo;
+      brk[2 * j + 1] = ghi;
+    }
+    __syncthreads();
+    for (int round = 0; round < 12; ++round) {
+      if (act) {
+        const double a = brk[2 * j], b = brk[2 * j + 1];
+        const double x = a + (b - a) * (double)(q + 1) / (double)(MS + 1);
+        cnt[MS * j + q] = sturm_count(d, e2, n, x, pivmin);
+      }
+      __syncthreads();
+      if (act && q == 0) {
+        const int idx = n - 1 - j;  // ascending index of the j-th largest
+        const double a = brk[2 * j], b = brk[2 * j + 1];
+        double na = a, nb = b;
+        for (int r = 0; r < MS; ++r) {
+          const double x = a + (b - a) * (double)(r + 1) / (double)(MS + 1);
+          if (cnt[MS * j + r] <= idx) na = x;  // eigenvalue idx is at or above x
+          else { nb = x; break; }
+        }
+        brk[2 * j] = na;
+        brk[2 * j + 1] = nb;
+      }
+      __syncthreads();
+    }
+    if (act && q == 0) lam[j] = 0.5 * (brk[2 * j] + brk[2 * j + 1]);
+    __syncthreads();
+  }
+
+  // 3. eigenvectors of T by inverse iteration, thread j for eigenvector j
+  const double tiny = eps * fmax(tnorm, pivmin);
+  for (int j = tid; j < K; j += blockDim.x) {
+    double lj = lam[j];
+    // separate (numerically) equal eigenvalues so the factorisations differ
+    for (int i = 0; i < j; ++i)
+      if (fabs(lam[i] - lj) < 10.0 * eps * fmax(tnorm, 1e-300)) lj -= 10.0 * eps * fmax(tnorm, 1e-300);
+    double* u0 = lu + (int64_t)j * 3 * n;
+    double* u1 = u0 + n;
+    double* u2 = u1 + n;
+    double* z = Z + (int64_t)j * n;
+    for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
+    for (int it = 0; it < 3; ++it) {
+      // LU of T - lj I with partial pivoting, applied to z as it is formed, then back substitution
+      double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
+      for (int i = 0; i < n - 1; ++i) {
+        const double c = e[i], nd = d[i + 1] - lj, ns = i + 1 < n - 1 ? e[i + 1] : 0.0;
+        if (fabs(c) > fabs(a0)) {
+          u0[i] = c; u1[i] = nd; u2[i] = ns;
+          const double mlt = a0 / c;
+          const double t0 = z[i];
+          z[i] = z[i + 1];
+          z[i + 1] = t0 - mlt * z[i + 1];
+          a0 = a1 - mlt * nd;
+          a1 = a2 - mlt * ns;
+          a2 = 0.0;
         } else {
-          const int p2 = pr[2 * k2], q2 = pr[2 * k2 + 1];
-          const double c2 = cs[2 * k2], s2 = cs[2 * k2 + 1];
-          const int64_t i11 = pk(p1, p2, n), i12 = pk(p1, q2, n), i21 = pk(q1, p2, n), i22 = pk(q1, q2, n);
-          const double x11 = A[i11], x12 = A[i12], x21 = A[i21], x22 = A[i22];
-          const double y11 = c1 * x11 - s1 * x21, y12 = c1 * x12 - s1 * x22;
-          const double y21 = s1 * x11 + c1 * x21, y22 = s1 * x12 + c1 * x22;
-          A[i11] = c2 * y11 - s2 * y12;
-          A[i12] = s2 * y11 + c2 * y12;
-          A[i21] = c2 * y21 - s2 * y22;
-          A[i22] = s2 * y21 + c2 * y22;
+          if (a0 == 0.0) a0 = tiny;
+          u0[i] = a0; u1[i] = a1; u2[i] = a2;
+          const double mlt = c / a0;
+          z[i + 1] -= mlt * z[i];
+          a0 = nd - mlt * a1;
+          a1 = ns - mlt * a2;
+          a2 = 0.0;
         }
       }
-      // V <- V J
-      for (int e = tid; e < n * half; e += nt) {
-        const int i = e / half, k = e - i * half;
-        const int p = pr[2 * k], q = pr[2 * k + 1];
-        const double c = cs[2 * k], s = cs[2 * k + 1];
-        const double vp = V[(int64_t)i * n + p], vq = V[(int64_t)i * n + q];
-        V[(int64_t)i * n + p] = c * vp - s * vq;
-        V[(int64_t)i * n + q] = s * vp + c * vq;
+      if (a0 == 0.0) a0 = tiny;
+      u0[n - 1] = a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        double s = z[i];
+        if (i + 1 < n) s -= u1[i] * z[i + 1];
+        if (i + 2 < n) s -= u2[i] * z[i + 2];
+        z[i] = s / u0[i];
       }
-      __syncthreads();
+      double nrm = 0.0;
+      for (int i = 0; i < n; ++i) nrm += z[i] * z[i];
+      nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = 0; i < n; ++i) z[i] *= nrm;
     }
   }
-  for (int j = tid; j < n; j += nt) lam[j] = A[pk(j, j, n)];
-  for (int64_t e = tid; e < (int64_t)n * n; e += nt) Vout[e] = V[e];
-  if (tid == 0) info[0] = sweep;
-}
+  __syncthreads();
+  orth_rows(Z, K, n, gm, lu, red, oflag);
 
-// Order eigenpairs by eigenvalue, largest first (ties: lower index first), over
-// the first n0 indices (padding excluded); write the leading K values and
-// vectors: lam_k[k], VK[i * K + k] (n0 x K), and the full sorted basis Vs (n0 x n0)
-// for the next warm start.
-__global__ void k_eig_select(const double* __restrict__ lam, const double* __restrict__ V, int n0, int n, int K,
-                             double* __restrict__ lam_k, double* __restrict__ VK, double* __restrict__ Vs) {
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n0; i += gridDim.x * blockDim.x) {
-    const double li = lam[i];
-    int rank = 0;
-    for (int j = 0; j < n0; ++j) {
-      const double lj = lam[j];
-      rank += (lj > li) || (lj == li && j < i);
-    }
-    if (rank < K) lam_k[rank] = li;
-    for (int r = 0; r < n0; ++r) {
-      const double v = V[(int64_t)r * n + i];
-      if (rank < K) VK[(int64_t)r * K + rank] = v;
-      Vs[(int64_t)r * n0 + rank] = v;
+  // 4. back-transformation, one wave per vector
+  const int wave = tid >> 6, lane = tid & 63;
+  for (int j = wave; j < K; j += blockDim.x >> 6) {
+    double* z = Z + (int64_t)j * n;
+    for (int k = n - 3; k >= 0; --k) {
+      const double t = tau[k];
+      if (t == 0.0) continue;
+      const int m = n - k - 1;
+      double s = 0.0;
+      for (int i = lane; i < m; i += 64) s += A[(int64_t)(k + 1 + i) * stride + k] * z[k + 1 + i];
+      s = wave_sum(s);
+      for (int i = lane; i < m; i += 64) z[k + 1 + i] -= t * s * A[(int64_t)(k + 1 + i) * stride + k];
     }
   }
+  __syncthreads();
+  orth_rows(Z, K, n, gm, lu, red, oflag);   // restore orthonormality after back-transformation
+  for (int64_t t = tid; t < (int64_t)n * K; t += blockDim.x) {
+    const int i = (int)(t / K), j = (int)(t % K);
+    VK[(int64_t)i * Kout + j] = Z[(int64_t)j * n + i];
+  }
+  for (int j = tid; j < K; j += blockDim.x) lam_out[j] = lam[j];
 }
 
-// Eigen-decomposition of G (n0 x n0) -> leading K eigenpairs; warm start from
-// and update of Vwarm (n0 x n0, may be null on the first call: then *have_warm = false).
-void eig_topk(Ctx* c, const double* G, int n0, int K, double* Vwarm, bool have_warm, double* lam_k, double* VK,
-              int* info_dev) {
-  const int n = n0 + (n0 & 1);
-  const int64_t npk = (int64_t)n * (n + 1) / 2;
-  const size_t head = sizeof(double) * ((size_t)n + (size_t)(n + 1) / 2 + 1024);
-  const size_t bA = sizeof(double) * (size_t)npk, bV = sizeof(double) * (size_t)n * n;
+// Leading K eigenpairs of G (n0 x n0, FP64): lam_k[0..K) descending and VK (n0 x K).
+// Eigenpairs beyond n0 (K > n0) are reported as zero eigenvalues.
+void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK) {
+  const int Ke = K < n0 ? K : n0;
+  const EigLayout with_a = eig_layout(n0, Ke, true), no_a = eig_layout(n0, Ke, false);
   const size_t lim = c->lds_per_block;
-  int mode = 0;
-  size_t lds = head;
-  if (head + bA + bV <= lim) { mode = 3; lds = head + bA + bV; }
-  else if (head + bA <= lim) { mode = 1; lds = head + bA; }
-  ensure(c, c->work, (bA + bV + sizeof(double) * ((size_t)n * n + n)) );
-  double* gA = c->work.as<double>();
-  double* gV = gA + npk;
-  double* lam = gV + (size_t)n * n;
-  double* Vout = lam + n;
-  const int threads = 1024;
-  hipLaunchKernelGGL(k_jacobi, dim3(1), dim3(threads), lds, c->stream, G, have_warm ? Vwarm : nullptr, n0, n,
-                     c->opt.max_jacobi_sweeps > 0 ? c->opt.max_jacobi_sweeps : 30,
-                     c->opt.eig_tol > 0 ? c->opt.eig_tol : 1e-15, mode, gA, gV, lam, Vout, info_dev);
-  TK_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_eig_select, dim3((n0 + 255) / 256), dim3(256), 0, c->stream, lam, Vout, n0, n, K, lam_k, VK,
-                     Vwarm);
+  int a_in_lds = 0, ws_in_lds = 0;
+  size_t lds = 0;
+  if ((size_t)with_a.total * 8 <= lim) {
+    a_in_lds = 1;
+    ws_in_lds = 1;
+    lds = (size_t)with_a.total * 8;
+  } else if ((size_t)no_a.total * 8 <= lim) {
+    ws_in_lds = 1;
+    lds = (size_t)no_a.total * 8;
+  }
+  ensure(c, c->work, sizeof(double) * (size_t)(with_a.total + 16));
+  if (K > Ke) TK_HIP(hipMemsetAsync(lam_k, 0, sizeof(double) * K, c->stream));
+  hipLaunchKernelGGL(k_syev_topk, dim3(1), dim3(EIG_THREADS), lds, c->stream, G, n0, Ke, K, a_in_lds, ws_in_lds,
+                     c->work.as<double>(), lam_k, VK);
   TK_CHECK_LAUNCH();
 }
 

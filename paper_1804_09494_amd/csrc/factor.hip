@@ -16,9 +16,10 @@ namespace tk {
 constexpr int FT_ROWS = 64;  // rows of Y per workgroup
 
 // U = Y W and per-workgroup partial of U^T U.  W (khat x K, FP64) is in LDS;
-// Y rows are staged through LDS with a padded stride.
+// Y rows are staged through LDS with a padded stride, FT_ROWS at a time, over
+// `tiles` consecutive tiles per workgroup.
 __global__ __launch_bounds__(256) void k_uw(const float* __restrict__ Y, int64_t R, int khat,
-                                            const double* __restrict__ W, int K, double* __restrict__ U,
+                                            const double* __restrict__ W, int K, int tiles, double* __restrict__ U,
                                             double* __restrict__ part) {
   extern __shared__ double shd[];
   double* w = shd;                                      // khat * K
@@ -26,70 +27,108 @@ __global__ __launch_bounds__(256) void k_uw(const float* __restrict__ Y, int64_t
   float* yt = reinterpret_cast<float*>(ut + FT_ROWS * K);  // FT_ROWS * (khat + 1)
   const int ys = khat + 1;
   for (int i = threadIdx.x; i < khat * K; i += blockDim.x) w[i] = W[i];
-  const int64_t r0 = (int64_t)blockIdx.x * FT_ROWS;
-  const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
-  for (int i = threadIdx.x; i < nr * khat; i += blockDim.x) {
-    const int r = i / khat, cc = i - r * khat;
-    yt[r * ys + cc] = Y[(r0 + r) * khat + cc];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};  // entries tid, tid+256, ... of U^T U (K <= 32)
+  for (int tt = 0; tt < tiles; ++tt) {
+    const int64_t r0 = ((int64_t)blockIdx.x * tiles + tt) * FT_ROWS;
+    if (r0 >= R) break;
+    const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * khat; i += blockDim.x) {
+      const int r = i / khat, cc = i - r * khat;
+      yt[r * ys + cc] = Y[(r0 + r) * khat + cc];
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
+      const int r = i / K, k = i - r * K;
+      double s = 0.0;
+      for (int cc = 0; cc < khat; ++cc) s += (double)yt[r * ys + cc] * w[cc * K + k];
+      ut[r * K + k] = s;
+      U[(r0 + r) * K + k] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < K * K) {
+        const int a = i / K, b = i - a * K;
+        double s = acc[q];
+        for (int r = 0; r < nr; ++r) s += ut[r * K + a] * ut[r * K + b];
+        acc[q] = s;
+      }
+    }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
-    const int r = i / K, k = i - r * K;
-    double s = 0.0;
-    for (int cc = 0; cc < khat; ++cc) s += (double)yt[r * ys + cc] * w[cc * K + k];
-    ut[r * K + k] = s;
-    U[(r0 + r) * K + k] = s;
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
-    const int a = i / K, b = i - a * K;
-    double s = 0.0;
-    for (int r = 0; r < nr; ++r) s += ut[r * K + a] * ut[r * K + b];
-    part[(int64_t)blockIdx.x * K * K + i] = s;
+  for (int q = 0; q < 4; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    if (i < K * K) part[(int64_t)blockIdx.x * K * K + i] = acc[q];
   }
 }
 
-// U <- U Rinv (upper triangular, K x K) and partial U^T U of the result.
-__global__ __launch_bounds__(256) void k_apply_rinv(double* __restrict__ U, int64_t R, int K,
+// U <- U Rinv (upper triangular, K x K) and partial U^T U of the result, over
+// `tiles` consecutive 64-row tiles per workgroup.
+__global__ __launch_bounds__(256) void k_apply_rinv(double* __restrict__ U, int64_t R, int K, int tiles,
                                                     const double* __restrict__ Rinv, double* __restrict__ part) {
   extern __shared__ double shd[];
   double* ri = shd;               // K * K
   double* ut = ri + K * K;        // FT_ROWS * K (old rows)
   double* un = ut + FT_ROWS * K;  // FT_ROWS * K (new rows)
   for (int i = threadIdx.x; i < K * K; i += blockDim.x) ri[i] = Rinv[i];
-  const int64_t r0 = (int64_t)blockIdx.x * FT_ROWS;
-  const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
-  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) ut[i] = U[r0 * K + i];
-  __syncthreads();
-  // new[r][k] = sum_{j <= k} old[r][j] * Rinv[j][k]
-  for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
-    const int r = i / K, k = i - r * K;
-    double s = 0.0;
-    for (int j = 0; j <= k; ++j) s += ut[r * K + j] * ri[j * K + k];
-    un[i] = s;
-    U[r0 * K + i] = s;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int tt = 0; tt < tiles; ++tt) {
+    const int64_t r0 = ((int64_t)blockIdx.x * tiles + tt) * FT_ROWS;
+    if (r0 >= R) break;
+    const int nr = (int)min<int64_t>(FT_ROWS, R - r0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * K; i += blockDim.x) ut[i] = U[r0 * K + i];
+    __syncthreads();
+    // new[r][k] = sum_{j <= k} old[r][j] * Rinv[j][k]
+    for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
+      const int r = i / K, k = i - r * K;
+      double s = 0.0;
+      for (int j = 0; j <= k; ++j) s += ut[r * K + j] * ri[j * K + k];
+      un[i] = s;
+      U[r0 * K + i] = s;
+    }
+    __syncthreads();
+    for (int q = 0; q < 4; ++q) {
+      const int i = threadIdx.x + 256 * q;
+      if (i < K * K) {
+        const int a = i / K, b = i - a * K;
+        double s = acc[q];
+        for (int r = 0; r < nr; ++r) s += un[r * K + a] * un[r * K + b];
+        acc[q] = s;
+      }
+    }
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
-    const int a = i / K, b = i - a * K;
-    double s = 0.0;
-    for (int r = 0; r < nr; ++r) s += un[r * K + a] * un[r * K + b];
-    part[(int64_t)blockIdx.x * K * K + i] = s;
+  for (int q = 0; q < 4; ++q) {
+    const int i = threadIdx.x + 256 * q;
+    if (i < K * K) part[(int64_t)blockIdx.x * K * K + i] = acc[q];
   }
 }
 
-// Sum K x K partials in workgroup order, Cholesky A = R^T R, Rinv = R^-1.
+// Fixed-order sum of nparts rows of K*K doubles: one block per entry group.
+__global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ part, int nparts, int KK,
+                                                   double* __restrict__ out) {
+  __shared__ double sh[256];
+  for (int e = blockIdx.x; e < KK; e += gridDim.x) {
+    double s = 0.0;
+    for (int p = threadIdx.x; p < nparts; p += blockDim.x) s += part[(int64_t)p * KK + e];
+    sh[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[e] = sh[0];
+    __syncthreads();
+  }
+}
+
+// Cholesky A = R^T R of the summed K x K matrix, Rinv = R^-1.
 // flag bit 0 set when a pivot is not positive relative to the largest diagonal.
-__global__ void k_chol_inv(const double* __restrict__ part, int nparts, int K, double* __restrict__ Rinv,
-                           int* __restrict__ flag) {
+__global__ void k_chol_inv(const double* __restrict__ Asum, int K, double* __restrict__ Rinv, int* __restrict__ flag) {
   extern __shared__ double shd[];
   double* A = shd;          // K * K
   double* Rm = A + K * K;   // K * K
-  for (int i = threadIdx.x; i < K * K; i += blockDim.x) {
-    double s = 0.0;
-    for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * K * K + i];
-    A[i] = s;
-  }
+  for (int i = threadIdx.x; i < K * K; i += blockDim.x) A[i] = Asum[i];
   __syncthreads();
   if (threadIdx.x == 0) {
     double dmax = 0.0;
@@ -99,7 +138,7 @@ __global__ void k_chol_inv(const double* __restrict__ part, int nparts, int K, d
     for (int j = 0; j < K && ok; ++j) {
       double d = A[j * K + j];
       for (int k = 0; k < j; ++k) d -= Rm[k * K + j] * Rm[k * K + j];
-      if (!(d > 1e-24 * dmax)) { ok = false; break; }
+      if (!(d > 1e-16 * dmax)) { ok = false; break; }
       const double rjj = sqrt(d);
       Rm[j * K + j] = rjj;
       for (int i = j + 1; i < K; ++i) {
@@ -139,37 +178,39 @@ __global__ void k_make_w(const double* __restrict__ VK, const double* __restrict
   }
 }
 
-// F64[row_slice[r]] = U[r]; FP32 / BF16 copies of the same rows.
+__device__ __forceinline__ uint16_t to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+
+// F64[row_slice[r]] = U[r] (index order); FP32 / BF16 working copies of the
+// same rows at their storage labels.
 __global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
-                                 double* __restrict__ F64, float* __restrict__ F32, int kp32,
-                                 uint16_t* __restrict__ F16, int kp16) {
+                                 const int32_t* __restrict__ label, double* __restrict__ F64, float* __restrict__ F32,
+                                 int kp32, uint16_t* __restrict__ F16, int kp16) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R * K; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / K;
     const int k = (int)(i - r * K);
     const int64_t l = row_slice[r];
+    const int64_t s = label[l];
     const double v = U[i];
     F64[l * K + k] = v;
-    F32[l * kp32 + k] = (float)v;
-    if (F16) {
-      const float f = (float)v;
-      uint32_t b = __float_as_uint(f);
-      b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
-      F16[l * kp16 + k] = (uint16_t)(b >> 16);
-    }
+    F32[s * kp32 + k] = (float)v;
+    F16[s * kp16 + k] = to_bf16_rne((float)v);
   }
 }
 
-// FP32 / BF16 working copies of a whole FP64 factor (padding stays zero).
-__global__ void k_factor_copies(const double* __restrict__ F64, int64_t L, int K, float* __restrict__ F32, int kp32,
-                                uint16_t* __restrict__ F16, int kp16) {
+// FP32 / BF16 working copies of a whole FP64 factor at the storage labels (padding stays zero).
+__global__ void k_factor_copies(const double* __restrict__ F64, int64_t L, int K, const int32_t* __restrict__ label,
+                                float* __restrict__ F32, int kp32, uint16_t* __restrict__ F16, int kp16) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * K; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = i / K;
     const int k = (int)(i - l * K);
+    const int64_t s = label[l];
     const float f = (float)F64[i];
-    F32[l * kp32 + k] = f;
-    uint32_t b = __float_as_uint(f);
-    b += 0x7FFFu + ((b >> 16) & 1u);
-    F16[l * kp16 + k] = (uint16_t)(b >> 16);
+    F32[s * kp32 + k] = f;
+    F16[s * kp16 + k] = to_bf16_rne(f);
   }
 }
 
@@ -179,7 +220,8 @@ void refresh_factor_copies(Ctx* c, int n) {
   TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
   TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
   hipLaunchKernelGGL(k_factor_copies, dim3(grid_for(L * K, 256)), dim3(256), 0, c->stream, c->F64[n].as<double>(), L,
-                     K, c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
+                     K, c->plan[n].label.as<int32_t>(), c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(),
+                     c->kp16[n]);
   TK_CHECK_LAUNCH();
 }
 
@@ -242,13 +284,16 @@ static void complete_on_host(Ctx* c, int n) {
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
                  int* flag_dev, bool check_flag) {
   const int K = c->K[n];
-  const int64_t L = c->dims[n];
-  const int nwg = (int)std::max<int64_t>(1, ceil_div(R, FT_ROWS));
+  TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "factor step: rank above 32");
+  const int64_t ntile = std::max<int64_t>(1, ceil_div(R, FT_ROWS));
+  const int tiles = (int)std::max<int64_t>(1, ceil_div(ntile, 1024));
+  const int nwg = (int)ceil_div(ntile, tiles);
   ensure(c, c->U64, sizeof(double) * (size_t)std::max<int64_t>(R, 1) * K);
-  ensure(c, c->small64, sizeof(double) * ((size_t)khat * K + 2 * (size_t)K * K + (size_t)nwg * K * K));
+  ensure(c, c->small64, sizeof(double) * ((size_t)khat * K + 3 * (size_t)K * K + (size_t)nwg * K * K));
   double* W = c->small64.as<double>();
   double* Rinv = W + (size_t)khat * K;
-  double* part = Rinv + (size_t)K * K;
+  double* Asum = Rinv + (size_t)K * K;
+  double* part = Asum + (size_t)K * K;
   double* U = c->U64.as<double>();
   TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, khat,
@@ -257,14 +302,16 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   if (R > 0) {
     size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat x K too large for LDS");
-    hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+    hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, tiles, U, part);
     TK_CHECK_LAUNCH();
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(256), sizeof(double) * 2 * K * K, c->stream, part, nwg, K, Rinv,
+      hipLaunchKernelGGL(k_sum_parts, dim3(std::min(K * K, 1024)), dim3(256), 0, c->stream, part, nwg, K * K, Asum);
+      TK_CHECK_LAUNCH();
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), sizeof(double) * 2 * K * K, c->stream, Asum, K, Rinv,
                          flag_dev);
       TK_CHECK_LAUNCH();
       hipLaunchKernelGGL(k_apply_rinv, dim3(nwg), dim3(256), sizeof(double) * ((size_t)K * K + 2 * FT_ROWS * K),
-                         c->stream, U, R, K, Rinv, part);
+                         c->stream, U, R, K, tiles, Rinv, part);
       TK_CHECK_LAUNCH();
     }
   }
@@ -273,8 +320,8 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
   if (R > 0) {
     hipLaunchKernelGGL(k_scatter_factor, dim3(grid_for(R * K, 256)), dim3(256), 0, c->stream, U, R, K,
-                       c->plan[n].row_slice.as<int32_t>(), c->F64[n].as<double>(), c->F32[n].as<float>(), c->kp32[n],
-                       c->F16[n].as<uint16_t>(), c->kp16[n]);
+                       c->plan[n].row_slice.as<int32_t>(), c->plan[n].label.as<int32_t>(), c->F64[n].as<double>(),
+                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
     TK_CHECK_LAUNCH();
   }
   if (!check_flag && R >= K) return false;
@@ -283,7 +330,6 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   c->sync();
   if (hflag || R < K) {
     if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
-    (void)L;
     complete_on_host(c, n);
     return true;
   }

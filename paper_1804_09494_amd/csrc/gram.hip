@@ -64,10 +64,10 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
 #pragma unroll
   for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lr = lane >> 4, lc = lane & 15;
-  for (int64_t r = r0 + 4 * wave; r < r1; r += 16) {
+  // software pipeline: the next 4-row step is loaded while this one's MFMAs run
+  auto load = [&](int64_t r, float (&xa)[NBA], float (&xb)[NBB]) {
     const int64_t row = r + lr;
     const bool rok = row < r1;
-    float xa[NBA], xb[NBB];
 #pragma unroll
     for (int b = 0; b < NBA; ++b) {
       const int col = (I0 + b) * 16 + lc;
@@ -83,9 +83,20 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
         xb[b] = (rok && col < khat) ? Y[row * khat + col] : 0.f;
       }
     }
+  };
+  float xa[NBA], xb[NBB];
+  int64_t r = r0 + 4 * wave;
+  if (r < r1) load(r, xa, xb);
+  for (; r < r1; r += 16) {
+    float na[NBA], nb[NBB];
+    if (r + 16 < r1) load(r + 16, na, nb);
 #pragma unroll
     for (int t = 0; t < T; ++t)
       acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[TS::ti(t)], xb[TS::tj(t)], acc[t], 0, 0, 0);
+#pragma unroll
+    for (int b = 0; b < NBA; ++b) xa[b] = na[b];
+#pragma unroll
+    for (int b = 0; b < NBB; ++b) xb[b] = nb[b];
   }
   // combine the four waves in fixed order
   for (int w = 0; w < 4; ++w) {
@@ -100,13 +111,25 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
     }
     __syncthreads();
   }
-  float* out = part + ((int64_t)pair * gridDim.x + blockIdx.x) * (int64_t)T * 256;
+  float* out = part + ((int64_t)blockIdx.x * gridDim.y + pair) * (int64_t)T * 256;
   for (int i = threadIdx.x; i < T * 256; i += blockDim.x) out[i] = red[i];
 }
 
-// Sum partials over the row chunks in FP64 and scatter into the full symmetric G.
+// Level 1: sum groups of `group` consecutive chunk partials in FP64 (fixed order).
+__global__ void k_colsum_groups(const float* __restrict__ in, int64_t P, int64_t M, int group,
+                                double* __restrict__ out) {
+  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (col >= M) return;
+  const int64_t p0 = (int64_t)blockIdx.y * group;
+  const int64_t p1 = min<int64_t>(p0 + group, P);
+  double s = 0.0;
+  for (int64_t p = p0; p < p1; ++p) s += (double)in[p * M + col];
+  out[(int64_t)blockIdx.y * M + col] = s;
+}
+
+// Level 2: sum the group partials and scatter into the full symmetric G.
 template <int NBA, int NBB, bool DIAG>
-__global__ void k_gram_reduce(const float* __restrict__ part, int nchunks, int MB, int khat,
+__global__ void k_gram_reduce(const double* __restrict__ part, int nchunks, int MB, int khat,
                               double* __restrict__ G) {
   using TS = TileSet<NBA, NBB, DIAG>;
   constexpr int T = TS::count;
@@ -125,8 +148,10 @@ __global__ void k_gram_reduce(const float* __restrict__ part, int nchunks, int M
   if (gi >= khat || gj >= khat) return;
   if (DIAG && TS::ti(t) == TS::tj(t) && rr > cc) return;  // the (cc, rr) thread writes both halves
   double s = 0.0;
-  const float* p = part + (int64_t)pair * nchunks * T * 256 + i;
-  for (int k = 0; k < nchunks; ++k) s += (double)p[(int64_t)k * T * 256];
+  // part is [group][pair][T*256]
+  const double* p = part + (int64_t)pair * T * 256 + i;
+  const int64_t stride = (int64_t)gridDim.y * T * 256;
+  for (int k = 0; k < nchunks; ++k) s += p[k * stride];
   G[(int64_t)gi * khat + gj] = s;
   G[(int64_t)gj * khat + gi] = s;
 }
@@ -136,16 +161,25 @@ static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, in
   using TS = TileSet<NBA, NBB, DIAG>;
   constexpr int T = TS::count;
   if (npairs == 0) return;
-  int64_t target_wgs = std::max<int64_t>(1, 2048 / npairs);
-  int rows_per_wg = (int)std::max<int64_t>(64, ceil_div(ceil_div(R, target_wgs), 16) * 16);
-  int nchunks = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
-  ensure(c, c->gram_part, sizeof(float) * (size_t)npairs * nchunks * T * 256);
+  const int64_t target_wgs = std::max<int64_t>(1, 1024 / npairs);
+  const int rows_per_wg = (int)std::max<int64_t>(64, ceil_div(ceil_div(R, target_wgs), 16) * 16);
+  const int nchunks = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
+  const int group = 32;
+  const int ngroups = (nchunks + group - 1) / group;
+  const int64_t M = (int64_t)npairs * T * 256;   // the chunk partials are [chunk][pair][T*256]
+  const size_t b1 = sizeof(float) * (size_t)nchunks * M, b2 = sizeof(double) * (size_t)ngroups * M;
+  ensure(c, c->gram_part, b1 + b2 + 256);
   float* part = c->gram_part.as<float>();
+  double* part2 = reinterpret_cast<double*>(c->gram_part.as<char>() + ((b1 + 255) & ~(size_t)255));
+  TK_REQUIRE(((b1 + 255) & ~(size_t)255) + b2 <= c->gram_part.bytes(), TK_ERR_DEVICE, "gram scratch");
   hipLaunchKernelGGL((k_gram<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
                      c->stream, Y, R, khat, rows_per_wg, MB, part);
   TK_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_colsum_groups, dim3((unsigned)ceil_div(M, 256), ngroups), dim3(256), 0, c->stream, part,
+                     (int64_t)nchunks, M, group, part2);
+  TK_CHECK_LAUNCH();
   hipLaunchKernelGGL((k_gram_reduce<NBA, NBB, DIAG>), dim3((T * 256 + 255) / 256, npairs), dim3(256), 0, c->stream,
-                     part, nchunks, MB, khat, G);
+                     part2, ngroups, MB, khat, G);
   TK_CHECK_LAUNCH();
 }
 

@@ -82,6 +82,19 @@ __global__ void k_rank_of(const uint32_t* __restrict__ osize, const uint32_t* __
   }
 }
 
+// Storage label of every index of this mode: nonempty slices by descending
+// size (rank from the (size, id) sort read backwards), empty slices after them.
+__global__ void k_labels(const int32_t* __restrict__ rank_of, const int32_t* __restrict__ row_of,
+                         const int64_t* __restrict__ count, int64_t L, int64_t Lnz, int32_t* __restrict__ label) {
+  for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < L; l += (int64_t)gridDim.x * blockDim.x)
+    label[l] = count[l] > 0 ? (int32_t)(Lnz - 1 - rank_of[l]) : (int32_t)(Lnz + l - row_of[l]);
+}
+
+__global__ void k_apply_labels(int32_t* __restrict__ lay, int64_t m, const int32_t* __restrict__ label) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
+    lay[i] = label[lay[i]];
+}
+
 // Stage 1, pass A: first t of residue class p where the class's running load + s_t > limit.
 __global__ void k_stage1_first_fail(const int64_t* __restrict__ size, int64_t Lnz, int64_t P, int64_t limit,
                                     int64_t* __restrict__ cand) {
@@ -226,31 +239,62 @@ struct IdxOut {
   int32_t* p[8];
 };
 
-// Layout scatter: destination of every element, and its other-mode coordinates and value.
+// Layout scatter: destination of every element, and its other-mode
+// coordinates and value.  `dest` is the (exported, unpadded) layout position;
+// the TTM-chain copy uses the padded position of the same element inside its
+// segment.
+__device__ __forceinline__ int64_t padded_pos(int64_t dest, int64_t bin, const int32_t* __restrict__ seg_ptr,
+                                              const int64_t* __restrict__ seg_begin,
+                                              const int64_t* __restrict__ seg_pbegin) {
+  int lo = seg_ptr[bin], hi = seg_ptr[bin + 1] - 1;  // last segment with seg_begin <= dest
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (seg_begin[mid] <= dest) lo = mid; else hi = mid - 1;
+  }
+  return seg_pbegin[lo] + (dest - seg_begin[lo]);
+}
+
 __global__ void k_layout(const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sperm, int64_t m,
                          const int64_t* __restrict__ sstart, const int32_t* __restrict__ rank_of,
                          const int64_t* __restrict__ off1, const int64_t* __restrict__ X,
                          const int64_t* __restrict__ Gin, const int64_t* __restrict__ gap,
                          const int64_t* __restrict__ load1, const int64_t* __restrict__ bin_ptr, int64_t t_hat,
-                         int64_t P, IdxIn in_idx, int n_other, const float* __restrict__ vals, IdxOut out_idx,
-                         float* __restrict__ out_val, uint32_t* __restrict__ elem_order) {
+                         int64_t P, const int32_t* __restrict__ seg_ptr, const int64_t* __restrict__ seg_begin,
+                         const int64_t* __restrict__ seg_pbegin, IdxIn in_idx, int n_other,
+                         const float* __restrict__ vals, IdxOut out_idx, float* __restrict__ out_val,
+                         uint32_t* __restrict__ elem_order, uint32_t* __restrict__ order_pad) {
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
     uint32_t l = skey[s];
     uint32_t e = sperm[s];
     int64_t r = s - sstart[l];
     int64_t t = rank_of[l];
-    int64_t dest;
+    int64_t dest, bin;
     if (t < t_hat) {
-      int64_t p = t % P;
-      dest = bin_ptr[p] + off1[t] + r;
+      bin = t % P;
+      dest = bin_ptr[bin] + off1[t] + r;
     } else {
       int64_t x = X[t - t_hat] + r;
-      int64_t b = upper_bound_i64(Gin, P, x);
-      dest = bin_ptr[b] + load1[b] + (x - (Gin[b] - gap[b]));
+      bin = upper_bound_i64(Gin, P, x);
+      dest = bin_ptr[bin] + load1[bin] + (x - (Gin[bin] - gap[bin]));
     }
-    for (int j = 0; j < n_other; ++j) out_idx.p[j][dest] = in_idx.p[j][e];
-    if (out_val) out_val[dest] = vals[e];
+    const int64_t pd = padded_pos(dest, bin, seg_ptr, seg_begin, seg_pbegin);
+    for (int j = 0; j < n_other; ++j) out_idx.p[j][pd] = in_idx.p[j][e];
+    if (out_val) out_val[pd] = vals[e];
     if (elem_order) elem_order[dest] = e;
+    if (order_pad) order_pad[pd] = e;
+  }
+}
+
+__global__ void k_seg_padlen(const int64_t* __restrict__ seg_begin, int64_t S, int64_t* __restrict__ plen) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < S; k += (int64_t)gridDim.x * blockDim.x)
+    plen[k] = (seg_begin[k + 1] - seg_begin[k] + 3) & ~(int64_t)3;
+}
+
+__global__ void k_bin_pptr(const int32_t* __restrict__ seg_ptr, const int64_t* __restrict__ seg_pbegin, int64_t P,
+                           int64_t* __restrict__ bin_pptr, int64_t* __restrict__ bsize) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= P; p += (int64_t)gridDim.x * blockDim.x) {
+    bin_pptr[p] = seg_pbegin[seg_ptr[p]];
+    if (p < P) bsize[p] = seg_pbegin[seg_ptr[p + 1]] - seg_pbegin[seg_ptr[p]];
   }
 }
 
@@ -315,11 +359,15 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
                  max_bits);
   ckey.release();
   cval.release();
-  count.release();
   Buf rank_of(c, 4 * (size_t)L), size64(c, 8 * (size_t)Lnz1);
   hipLaunchKernelGGL(k_rank_of, dim3(grid_for(Lnz, B)), dim3(B), 0, c->stream, osize.as<uint32_t>(),
                      oslice.as<uint32_t>(), Lnz, rank_of.as<int32_t>(), size64.as<int64_t>());
   TK_CHECK_LAUNCH();
+  pl.label.alloc(c, 4 * (size_t)L);
+  hipLaunchKernelGGL(k_labels, dim3(grid_for(L, B)), dim3(B), 0, c->stream, rank_of.as<int32_t>(),
+                     row_of.as<int32_t>(), count.as<int64_t>(), L, Lnz, pl.label.as<int32_t>());
+  TK_CHECK_LAUNCH();
+  count.release();
 
   // 3. number of bins and the limit
   const int cap = c->opt.lds_rows_cap >= 3 ? std::min(c->opt.lds_rows_cap, ttm_rows_cap(c, tile_w))
@@ -428,11 +476,44 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
                        bscan.as<int32_t>(), n2, pl.bad_row.as<int32_t>(), pl.bad_slot.as<int32_t>());
     TK_CHECK_LAUNCH();
     c->sync();
+    // fixup chunk table: each bad slice's slots cut into runs of at most FIX_CHUNK
+    std::vector<int32_t> bs((size_t)nbad + 1), cs, cp((size_t)nbad + 1);
+    d2h(c, bs.data(), pl.bad_slot.as<int32_t>(), (size_t)nbad + 1);
+    c->sync();
+    for (int64_t k = 0; k < nbad; ++k) {
+      cp[k] = (int32_t)cs.size();
+      for (int32_t a = bs[k]; a < bs[k + 1]; a += FIX_CHUNK) cs.push_back(a);
+    }
+    cp[nbad] = (int32_t)cs.size();
+    cs.push_back(bs[nbad]);
+    pl.n_chunks = (int64_t)cs.size() - 1;
+    pl.chunk_slot.alloc(c, 4 * cs.size());
+    pl.chunk_ptr.alloc(c, 4 * cp.size());
+    h2d(c, pl.chunk_slot.as<int32_t>(), cs.data(), cs.size());
+    h2d(c, pl.chunk_ptr.as<int32_t>(), cp.data(), cp.size());
+    c->sync();
   }
   pl.n_bad = nbad;
 
-  // 7. layout
-  const int64_t m1 = m > 0 ? m : 1;
+  // 7. padded segment offsets, then the layout
+  {
+    Buf plen(c, 8 * (size_t)S1), bsize(c, 8 * (size_t)P);
+    pl.seg_pbegin.alloc(c, 8 * (size_t)(S + 1));
+    hipLaunchKernelGGL(k_seg_padlen, dim3(grid_for(S, B)), dim3(B), 0, c->stream, pl.seg_begin.as<int64_t>(), S,
+                       plen.as<int64_t>());
+    TK_CHECK_LAUNCH();
+    exclusive_scan_i64(c, plen.as<int64_t>(), pl.seg_pbegin.as<int64_t>(), S);
+    pl.m_pad = S > 0 ? fetch(c, pl.seg_pbegin.as<int64_t>() + S - 1) + fetch(c, plen.as<int64_t>() + S - 1) : 0;
+    h2d(c, pl.seg_pbegin.as<int64_t>() + S, &pl.m_pad, 1);
+    c->sync();
+    pl.bin_pptr.alloc(c, 8 * (size_t)(P + 1));
+    hipLaunchKernelGGL(k_bin_pptr, dim3(grid_for(P + 1, B)), dim3(B), 0, c->stream, pl.seg_ptr.as<int32_t>(),
+                       pl.seg_pbegin.as<int64_t>(), P, pl.bin_pptr.as<int64_t>(), bsize.as<int64_t>());
+    TK_CHECK_LAUNCH();
+    reduce_max_i64(c, bsize.as<int64_t>(), mx.as<int64_t>(), P);
+    pl.E_pad_max = fetch(c, mx.as<int64_t>());
+  }
+  const int64_t m1 = pl.m_pad > 0 ? pl.m_pad : 1;
   IdxIn ii{};
   IdxOut oo{};
   int no = 0;
@@ -443,15 +524,37 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
     oo.p[no] = pl.lay_idx[no].as<int32_t>();
     ++no;
   }
-  if (vals) pl.lay_val.alloc(c, 4 * (size_t)m1);
-  if (keep_order) pl.elem_order.alloc(c, 4 * (size_t)m1);
+  for (int j = 0; j < no; ++j) TK_HIP(hipMemsetAsync(oo.p[j], 0, 4 * (size_t)m1, c->stream));
+  if (vals) {
+    pl.lay_val.alloc(c, 4 * (size_t)m1);
+    TK_HIP(hipMemsetAsync(pl.lay_val.get(), 0, 4 * (size_t)m1, c->stream));
+  } else {
+    pl.order_pad.alloc(c, 4 * (size_t)m1);
+    TK_HIP(hipMemsetAsync(pl.order_pad.get(), 0xff, 4 * (size_t)m1, c->stream));
+  }
+  if (keep_order) pl.elem_order.alloc(c, 4 * (size_t)(m > 0 ? m : 1));
   hipLaunchKernelGGL(k_layout, dim3(grid_for(m, B)), dim3(B), 0, c->stream, skey.as<uint32_t>(),
                      sperm.as<uint32_t>(), m, sstart.as<int64_t>(), rank_of.as<int32_t>(), off1.as<int64_t>(),
                      X.as<int64_t>(), Gin.as<int64_t>(), gap.as<int64_t>(), load1.as<int64_t>(),
-                     pl.bin_ptr.as<int64_t>(), t_hat, P, ii, no, vals, oo, vals ? pl.lay_val.as<float>() : nullptr,
-                     keep_order ? pl.elem_order.as<uint32_t>() : nullptr);
+                     pl.bin_ptr.as<int64_t>(), t_hat, P, pl.seg_ptr.as<int32_t>(), pl.seg_begin.as<int64_t>(),
+                     pl.seg_pbegin.as<int64_t>(), ii, no, vals, oo, vals ? pl.lay_val.as<float>() : nullptr,
+                     keep_order ? pl.elem_order.as<uint32_t>() : nullptr,
+                     vals ? nullptr : pl.order_pad.as<uint32_t>());
   TK_CHECK_LAUNCH();
   c->sync();
+}
+
+// Rewrite the other modes' coordinates of plan n into storage labels.
+void relabel_layout(Ctx* c, ModePlan& pl, int N, int n, const ModePlan* plans, int64_t m) {
+  (void)m;
+  int no = 0;
+  for (int j = 0; j < N; ++j) {
+    if (j == n) continue;
+    hipLaunchKernelGGL(k_apply_labels, dim3(grid_for(pl.m_pad, 256)), dim3(256), 0, c->stream,
+                       pl.lay_idx[no].as<int32_t>(), pl.m_pad, plans[j].label.as<int32_t>());
+    TK_CHECK_LAUNCH();
+    ++no;
+  }
 }
 
 // ---- export -------------------------------------------------------------------------------------

@@ -19,6 +19,8 @@
 
 namespace tk {
 
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
 struct TtmArgs {
   const int64_t* bin_ptr;
   const int32_t* seg_ptr;
@@ -193,15 +195,210 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
   }
 }
 
-// Sum the partial rows of every split slice in bin order (deterministic).
-__global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ bad_slot,
-                        const float* __restrict__ partial, int khat, float* __restrict__ Y) {
+// ---- three-mode TTM-chain on the matrix cores ----------------------------------------------
+//
+// For the elements of one slice, Y[row] viewed as K_a x K_b is
+//   sum_e (val_e F_a[l_a(e)]) F_b[l_b(e)]^T,
+// a contraction over the slice's elements: v_mfma_f32_16x16x4_f32 with lane l
+// supplying A[i = l%16][k = l/16] = val_k F_a[l_a(k)][i] and
+// B[k = l/16][j = l%16] = F_b[l_b(k)][j] (factor rows padded to 16 floats, so
+// a 16-lane group reads one 64-byte row).  The result D[4*(l/16)+r][l%16] is
+// Y[row][i + K_a j].
+//
+// The layout this kernel streams pads every slice segment to a multiple of 4
+// elements (zero values), so one MFMA step (4 consecutive elements) lies in one
+// slice: a slice change is a scalar compare per step, with no masking.  Each of
+// the four waves streams a contiguous quarter of the bin in blocks of 16
+// elements (four steps) from the LDS copy of the bin, stored so that one
+// 16-byte read gives lane group k the elements g+k, g+4+k, g+8+k, g+12+k.
+// When a slice ends its accumulator goes straight to Y (or to the bin's partial
+// slot for a slice split over bins); the at most two slices a wave shares with
+// its neighbours are parked in LDS and added in wave order after a barrier.
+// No atomics: the result is deterministic.
+constexpr int TTM3_SLOT = 256;
+constexpr int TTM3_DEPTH = 2;  // blocks of 16 elements with gathers in flight per wave
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// position of padded element i inside the bin's LDS copy (4x4 transpose inside each block of 16)
+__device__ __forceinline__ int ttm3_lds_pos(int i) { return (i & ~15) | ((i & 3) << 2) | ((i >> 2) & 3); }
+
+__global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg_pad) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ka = A.KA, kb = A.KW;
+  const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
+  const int64_t e0 = A.bin_ptr[bin];
+  const int E = (int)(A.bin_ptr[bin + 1] - e0);   // multiple of 4
+  const int s0 = A.seg_ptr[bin];
+  const int nseg = A.seg_ptr[bin + 1] - s0;
+  int* send = reinterpret_cast<int*>(smem);                 // nseg_pad
+  int* sslot = send + nseg_pad;                             // nseg_pad
+  int* srow = sslot + nseg_pad;                             // nseg_pad
+  int* sia = srow + nseg_pad;                               // Epad
+  int* sib = sia + Epad;                                    // Epad
+  float* sv = reinterpret_cast<float*>(sib + Epad);         // Epad
+  float* slots = sv + Epad;                                 // 4 waves x 2 x 256
+  int* winfo = reinterpret_cast<int*>(slots + 8 * TTM3_SLOT);  // 4 waves x 2
+  float* rows = reinterpret_cast<float*>(winfo + 8);        // nseg x khat: the bin's rows of Y
+  const int khat = A.khat;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uni(tid >> 6);
+  for (int i = tid; i < nseg; i += 256) {
+    send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
+    sslot[i] = A.seg_slot[s0 + i];
+    srow[i] = A.seg_row[s0 + i];
+  }
+  const int Ep = (E + 15) & ~15;
+  const int32_t* __restrict__ la = A.lay[0];
+  const int32_t* __restrict__ lb = A.lay[1];
+  for (int i = tid; i < Ep; i += 256) {
+    const bool ok = i < E;
+    const int q = ttm3_lds_pos(i);
+    sia[q] = ok ? la[e0 + i] : 0;
+    sib[q] = ok ? lb[e0 + i] : 0;
+    sv[q] = ok ? A.val[e0 + i] : 0.f;
+  }
+  if (lane == 0) {
+    winfo[2 * wave] = -1;
+    winfo[2 * wave + 1] = -1;
+  }
+  __syncthreads();
+
+  // per-wave state below is uniform (scalar registers, scalar branches)
+  const int Q = (((E + 3) >> 2) + 15) & ~15;
+  const int cs = min(wave * Q, E), ce = min(cs + Q, E);
+  const int k = lane >> 4, cix = lane & 15;
+  const bool bok = cix < kb;
+  const float* __restrict__ Fa = A.F[0];
+  const float* __restrict__ Fb = A.F[1];
+  if (cs < ce) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (uni(send[mid]) > cs) hi = mid; else lo = mid + 1;
+    }
+    int sg = lo;
+    int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
+    int seg_hi = uni(send[sg]);
+    floatx4_t C = {0.f, 0.f, 0.f, 0.f};
+    auto flush = [&]() {
+      const bool left = seg_lo < cs, right = seg_hi > ce;
+      if (!left && !right) {
+        // LDS only inside the loop: global stores would share the load counter
+        // with the gathers in flight and serialise the prefetch ring
+        float* dst = rows + sg * khat;
+        if (bok) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * k + r < ka) dst[4 * k + r + ka * cix] = C[r];
+        }
+      } else {
+        float* sl = slots + (wave * 2 + (left ? 0 : 1)) * TTM3_SLOT;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sl[r * 64 + lane] = C[r];
+        if (lane == 0) {
+          if (left) winfo[2 * wave] = sg;
+          if (right) winfo[2 * wave + 1] = sg;
+        }
+      }
+      C = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    };
+    float rx[TTM3_DEPTH][4], rb[TTM3_DEPTH][4];
+    auto fetch = [&](int g, float (&x)[4], float (&b)[4]) {
+      const int4 ia4 = *reinterpret_cast<const int4*>(sia + g + 4 * k);
+      const int4 ib4 = *reinterpret_cast<const int4*>(sib + g + 4 * k);
+      const float4 v4 = *reinterpret_cast<const float4*>(sv + g + 4 * k);
+      const int ia[4] = {ia4.x, ia4.y, ia4.z, ia4.w}, ib[4] = {ib4.x, ib4.y, ib4.z, ib4.w};
+      const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+      // all 16 lanes load: the factor copies are zero beyond column K, so no
+      // predicate (a predicated load would make the in-flight count path dependent)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
+        b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
+      }
+    };
+    auto consume = [&](int g, const float (&x)[4], const float (&b)[4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gu = g + 4 * u;
+        if (gu >= ce) break;
+        if (gu >= seg_hi) {  // a new slice starts at this step
+          flush();
+          ++sg;
+          seg_lo = seg_hi;
+          seg_hi = uni(send[sg]);
+        }
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], b[u], C, 0, 0, 0);
+      }
+    };
+    // Refills are unconditional (clamped to the last staged block): every path
+    // then has the same loads in flight and the compiler waits only for the
+    // oldest block instead of draining the ring.
+    const int last = Ep - 16;
+#pragma unroll
+    for (int d = 0; d < TTM3_DEPTH; ++d) fetch(min(cs + 16 * d, last), rx[d], rb[d]);
+    for (int g = cs; g < ce; g += 16 * TTM3_DEPTH) {
+#pragma unroll
+      for (int d = 0; d < TTM3_DEPTH; ++d) {
+        const int gg = g + 16 * d;
+        consume(gg, rx[d], rb[d]);
+        fetch(min(gg + 16 * TTM3_DEPTH, last), rx[d], rb[d]);
+      }
+    }
+    flush();  // the slice open at the end of this wave's quarter
+  }
+  __syncthreads();
+  // add the parked partials of shared slices in wave order
+  {
+    const int r = tid >> 6, ln = tid & 63;
+    const int i = 4 * (ln >> 4) + r, j = ln & 15;
+    const bool valid = i < ka && j < kb;
+    float acc = 0.f;
+    for (int w = 0; w < 4; ++w) {
+      const int fl = winfo[2 * w], fr = winfo[2 * w + 1];
+      if (fl >= 0) {
+        acc += slots[(w * 2 + 0) * TTM3_SLOT + tid];
+        if (fr != fl) {
+          if (valid) rows[fl * khat + i + ka * j] = acc;
+          acc = 0.f;
+        }
+      }
+      if (fr >= 0 && fr != fl) acc = slots[(w * 2 + 1) * TTM3_SLOT + tid];
+    }
+  }
+  __syncthreads();
+  // the bin's rows out, coalesced: owned slices to Y, split slices to their partial slot
+  for (int q = tid; q < nseg * khat; q += 256) {
+    const int sgi = q / khat, col = q - sgi * khat;
+    const int slot = sslot[sgi];
+    float* dst = slot < 0 ? A.Y + (int64_t)srow[sgi] * khat : A.partial + (int64_t)slot * khat;
+    dst[col] = rows[q];
+  }
+}
+
+// Sum the partial rows of every split slice in bin order, in two fixed-order
+// levels: chunks of at most FIX_CHUNK consecutive slots, then the chunks of
+// each slice (deterministic, and parallel for slices split over many bins).
+__global__ void k_fixup_chunks(const int32_t* __restrict__ chunk_slot, const float* __restrict__ partial, int khat,
+                               float* __restrict__ csum) {
   const int k = blockIdx.x;
-  const int a = bad_slot[k], b = bad_slot[k + 1];
-  const int64_t row = bad_row[k];
+  const int a = chunk_slot[k], b = chunk_slot[k + 1];
   for (int c = threadIdx.x; c < khat; c += blockDim.x) {
     float s = 0.f;
     for (int t = a; t < b; ++t) s += partial[(int64_t)t * khat + c];
+    csum[(int64_t)k * khat + c] = s;
+  }
+}
+
+__global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ chunk_ptr,
+                        const float* __restrict__ csum, int khat, float* __restrict__ Y) {
+  const int k = blockIdx.x;
+  const int a = chunk_ptr[k], b = chunk_ptr[k + 1];
+  const int64_t row = bad_row[k];
+  for (int c = threadIdx.x; c < khat; c += blockDim.x) {
+    float s = 0.f;
+    for (int t = a; t < b; ++t) s += csum[(int64_t)t * khat + c];
     Y[row * khat + c] = s;
   }
 }
@@ -232,6 +429,15 @@ static TtmShape ttm_shape(int N, const int32_t* K, int n) {
   else { s.TW = 4; s.exact = false; }
   s.ntiles = (s.mode == 1) ? 1 : (int)ceil_div(KW, s.TW);
   return s;
+}
+
+// Three-mode tensors with both remaining ranks <= 16 and 16-float factor rows
+// take the matrix-core kernel.
+bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp) {
+  if (N != 3) return false;
+  for (int j = 0; j < 3; ++j)
+    if (j != n && (K[j] > 16 || kp[j] != 16)) return false;
+  return true;
 }
 
 int ttm_tile_width(int N, const int32_t* K, int n) {
@@ -266,10 +472,10 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   TtmShape s = ttm_shape(N, K, n);
   TK_REQUIRE(s.KA <= 32, TK_ERR_UNSUPPORTED, "rank of the first remaining mode above 32");
   TtmArgs a{};
-  a.bin_ptr = pl.bin_ptr.as<int64_t>();
+  a.bin_ptr = pl.bin_pptr.as<int64_t>();
   a.seg_ptr = pl.seg_ptr.as<int32_t>();
   a.seg_row = pl.seg_row.as<int32_t>();
-  a.seg_begin = pl.seg_begin.as<int64_t>();
+  a.seg_begin = pl.seg_pbegin.as<int64_t>();
   a.seg_slot = pl.seg_slot.as<int32_t>();
   int no = 0, prod = 1;
   for (int j = 0; j < N; ++j) {
@@ -287,7 +493,8 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   a.khat = (int)pl.khat;
   a.val = lay_val;
   a.Y = Y;
-  ensure(c, c->partial, sizeof(float) * (size_t)(pl.n_slots > 0 ? pl.n_slots : 1) * (size_t)pl.khat);
+  ensure(c, c->partial,
+         sizeof(float) * (size_t)((pl.n_slots > 0 ? pl.n_slots : 1) + pl.n_chunks) * (size_t)pl.khat);
   a.partial = c->partial.as<float>();
   a.P = pl.P;
   if (m == 0) {
@@ -296,7 +503,15 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   const int tw = ttm_tile_width(N, K, n);
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
-  if (s.exact) {
+  if (ttm_uses_mfma(N, K, n, kp)) {
+    const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
+    const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
+    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * 8 * TTM3_SLOT +
+                       sizeof(int) * 8 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
+    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
+    hipLaunchKernelGGL(k_ttm3_mfma, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+    TK_CHECK_LAUNCH();
+  } else if (s.exact) {
     if (s.mode == 2 && s.KA == 10) launch_ttm<10, 10, 2, true>(c, a, pl, s.ntiles, tw);
     else if (s.mode == 2 && s.KA == 5) launch_ttm<5, 5, 2, true>(c, a, pl, s.ntiles, tw);
     else if (s.mode == 2 && s.KA == 16) launch_ttm<16, 8, 2, true>(c, a, pl, s.ntiles, tw);
@@ -312,8 +527,13 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   if (c->ev_ttm[1]) TK_HIP(hipEventRecord(c->ev_ttm[1], c->stream));
   if (pl.n_bad > 0) {
+    const size_t nps = (size_t)(pl.n_slots > 0 ? pl.n_slots : 1) * (size_t)pl.khat;
+    float* csum = c->partial.as<float>() + nps;
+    hipLaunchKernelGGL(k_fixup_chunks, dim3((unsigned)pl.n_chunks), dim3(128), 0, c->stream,
+                       pl.chunk_slot.as<int32_t>(), c->partial.as<float>(), (int)pl.khat, csum);
+    TK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_fixup, dim3((unsigned)pl.n_bad), dim3(128), 0, c->stream, pl.bad_row.as<int32_t>(),
-                       pl.bad_slot.as<int32_t>(), c->partial.as<float>(), (int)pl.khat, Y);
+                       pl.chunk_ptr.as<int32_t>(), csum, (int)pl.khat, Y);
     TK_CHECK_LAUNCH();
   }
 }
