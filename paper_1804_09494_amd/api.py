@@ -68,6 +68,7 @@ class TuckerContext:
             stream = _current_stream(device)
         elif _is_torch_stream(stream):
             stream = c_void_p(stream.cuda_stream)
+        self._opt = None
         self._check(self._L.tk_create(device, stream, ctypes.byref(h)), None)
         self._h = h
         self.device = device
@@ -105,11 +106,16 @@ class TuckerContext:
         self._check(self._L.tk_set_stream(self._h, s))
 
     def options(self) -> tk_options:
+        """A copy of the options in effect (the defaults until set_options)."""
         o = tk_options()
-        self._L.tk_default_options(ctypes.byref(o))
+        if self._opt is None:
+            self._L.tk_default_options(ctypes.byref(o))
+        else:
+            ctypes.memmove(ctypes.byref(o), ctypes.byref(self._opt), ctypes.sizeof(o))
         return o
 
     def set_options(self, **kw):
+        """Change the named options; the others keep their current values."""
         o = self.options()
         prec = kw.pop("prec", None)
         if prec is not None:
@@ -120,6 +126,7 @@ class TuckerContext:
         for k, v in kw.items():
             setattr(o, k, v)
         self._check(self._L.tk_set_options(self._h, ctypes.byref(o)))
+        self._opt = o
 
     # -- tensor --
     def load_coo(self, idx, vals, dims):

@@ -19,7 +19,7 @@
 
 namespace tk {
 
-void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G);
+void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16);
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK);
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
                  int* flag_dev, bool check_flag);
@@ -112,6 +112,8 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       }
     }
     float* Y = c->Y.as<float>();
+    // precision form: BF16 Gram operands, except in the refining last invocation
+    const bool low = c->opt.prec == TK_BF16 && !(c->opt.refine && it == iters - 1);
     for (int n = 0; n < N; ++n) {
       ModePlan& pl = c->plan[n];
       const int khat = (int)pl.khat;
@@ -139,7 +141,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
         TK_HIP(hipEventRecord(k1, c->stream));
       }
       hipEvent_t t1 = mark("ttm[" + std::to_string(n) + "]", t0);
-      gram(c, Y, pl.L_nz, khat, c->gram64.as<double>());
+      gram(c, Y, pl.L_nz, khat, c->gram64.as<double>(), low);
       hipEvent_t t2 = mark("gram", t1);
       double* lam_k = c->eig_val.as<double>();
       double* VK = lam_k + 64;

@@ -2,48 +2,56 @@
 // the leading K_n eigenpairs give the leading K_n left singular vectors of Y
 // (Section 2.2: the SVD step of an HOOI invocation) as Y V_K S_K^-1.
 //
-// One workgroup, data resident in LDS when it fits:
-//   1. Householder tridiagonalisation G = Q T Q^T (lower variant: reflector k
-//      is I - tau_k v_k v_k^T on rows/columns k+1..n-1, v_k[0] = 1, kept in
-//      column k below the diagonal);
-//   2. the K largest eigenvalues of T by multisection: 16 threads per
-//      eigenvalue evaluate Sturm counts (eigenvalues of T below x, from the
-//      signs of the LDL^T pivots) at 16 interior points and keep the
-//      sub-interval that holds it, 17x narrower per round;
-//   3. eigenvectors of T by inverse iteration (tridiagonal LU with partial
-//      pivoting, distinct seeded starts), then modified Gram-Schmidt across the
-//      K vectors, one more inverse-iteration step and a second pass;
-//   4. back-transformation z <- H_0 ... H_{n-3} z, one wave per vector.
+// One workgroup of 512 threads, the matrix resident in LDS when it fits:
+//   1. Householder tridiagonalisation G = Q T Q^T.  Reflector k is
+//      I - tau_k v v^T on rows/columns k+1..n-1 with v_0 = 1; it is built from
+//      row k (G stays symmetric), and row k is never touched again, so the
+//      reflector is kept as that row plus the scale that turns it into v.
+//      Per step: p = tau A22 v (four threads per row), then the symmetric
+//      rank-2 update A22 -= v w^T + w v^T with w = p - (tau/2)(p.v) v; two
+//      barriers per step.
+//   2. The K largest eigenvalues of T by multisection: a group of 16-64 lanes
+//      inside one wavefront per eigenvalue, two Sturm counts per lane (the
+//      number of eigenvalues below x, from the signs of the LDL^T pivots), and
+//      a ballot that picks the sub-interval holding the eigenvalue; no
+//      barriers, as many rounds as FP64 resolution needs.
+//   3. Eigenvectors of T by inverse iteration: one LU factorisation of
+//      T - lambda I with partial pivoting per eigenvalue, then two solves from
+//      a seeded start vector.
+//   4. Back-transformation z <- H_0 ... H_{n-3} z, half a wavefront per vector,
+//      then CholeskyQR2 of the K vectors (modified Gram-Schmidt when a pivot is
+//      not safely positive).
 #include <cmath>
 
 #include "common.hpp"
 
 namespace tk {
 
+constexpr int EIG_THREADS = 512;
+constexpr int EIG_WAVES = EIG_THREADS / 64;
+
+// Offsets, in doubles, of the solver's arrays.  A (n x (n+1)) comes first; the
+// rest follows it, in LDS or in the global workspace.
 struct EigLayout {
-  // offsets (in doubles) into the LDS or global workspace
-  int64_t A, d, e, e2, tau, p, v, red, Z, lu, lam, brk, cnt, gm;
-  int64_t total;
+  int64_t A, d, e, e2, tau, scl, p, red, Z, lu, lam, gm;
+  int64_t a_size, total;
 };
 
-static EigLayout eig_layout(int n, int K, bool a_in_ws) {
+static EigLayout eig_layout(int n, int K) {
   EigLayout L{};
   int64_t o = 0;
-  const int64_t stride = n + 1;
-  L.A = a_in_ws ? o : -1;
-  if (a_in_ws) o += (int64_t)n * stride;
+  L.A = o; o += (int64_t)n * (n + 1);
+  L.a_size = o;
   L.d = o; o += n;
   L.e = o; o += n;
   L.e2 = o; o += n;
   L.tau = o; o += n;
+  L.scl = o; o += n;
   L.p = o; o += n;
-  L.v = o; o += n;
   L.red = o; o += 64;
   L.Z = o; o += (int64_t)K * n;
-  L.lu = o; o += (int64_t)K * 3 * n;
+  L.lu = o; o += (int64_t)K * 5 * n;   // per vector: 1/u0, u1, u2, multiplier, pivot flag
   L.lam = o; o += K;
-  L.brk = o; o += 2 * (int64_t)K;
-  L.cnt = o; o += 32 * (int64_t)K;   // ints stored in doubles' space (generous)
   L.gm = o; o += 2 * (int64_t)K * K + 2;
   L.total = o;
   return L;
@@ -54,8 +62,10 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-constexpr int EIG_THREADS = 512;
-constexpr int EIG_WAVES = EIG_THREADS / 64;
+__device__ __forceinline__ double half_sum(double x) {   // over each 32-lane half
+  for (int off = 16; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
 
 // Sum over the workgroup: wave sums, then every thread adds the wave partials in order.
 __device__ __forceinline__ double block_sum(double x, double* red) {
@@ -69,18 +79,24 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
   return s;
 }
 
-// Number of eigenvalues of the symmetric tridiagonal (d, e) below x.
-__device__ int sturm_count(const double* d, const double* e2, int n, double x, double pivmin) {
-  int cnt = 0;
-  double q = d[0] - x;
-  if (fabs(q) < pivmin) q = -pivmin;
-  cnt += q < 0.0;
+// Eigenvalues of the symmetric tridiagonal (d, e) below x0 and below x1 (two
+// independent recurrences interleaved).
+__device__ __forceinline__ void sturm_count2(const double* d, const double* e2, int n, double x0, double x1,
+                                             double pivmin, int& c0, int& c1) {
+  double q0 = d[0] - x0, q1 = d[0] - x1;
+  if (fabs(q0) < pivmin) q0 = -pivmin;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  c0 = q0 < 0.0;
+  c1 = q1 < 0.0;
   for (int i = 1; i < n; ++i) {
-    q = d[i] - x - e2[i - 1] / q;
-    if (fabs(q) < pivmin) q = -pivmin;
-    cnt += q < 0.0;
+    const double di = d[i], ei = e2[i - 1];
+    q0 = di - x0 - ei / q0;
+    q1 = di - x1 - ei / q1;
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
   }
-  return cnt;
 }
 
 // Counter-based start vector entry (SplitMix64 mix of (j, i)) in [-1, 1).
@@ -93,11 +109,12 @@ __device__ __forceinline__ double start_entry(int j, int i) {
 }
 
 // Modified Gram-Schmidt over the K rows of Z (each of length n), block-wide.
-__device__ void mgs_rows(double* Z, int K, int n, double* red) {
+template <class P>
+__device__ void mgs_rows(P Z, int K, int n, double* red) {
   for (int j = 0; j < K; ++j) {
-    double* zj = Z + (int64_t)j * n;
+    P zj = Z + (int64_t)j * n;
     for (int i = 0; i < j; ++i) {
-      const double* zi = Z + (int64_t)i * n;
+      P zi = Z + (int64_t)i * n;
       double s = 0.0;
       for (int t = threadIdx.x; t < n; t += blockDim.x) s += zi[t] * zj[t];
       s = block_sum(s, red);
@@ -115,12 +132,15 @@ __device__ void mgs_rows(double* Z, int K, int n, double* red) {
 
 // Orthonormalise the K rows of Z by CholeskyQR twice (Gram matrix of the rows,
 // its Cholesky factor R, rows <- R^-T rows); falls back to modified
-// Gram-Schmidt when a pivot is not safely positive.  gm: 2*K*K doubles, tmp: K*n.
-__device__ void orth_rows(double* Z, int K, int n, double* gm, double* tmp, double* red, int* flag) {
-  double* R = gm + K * K;
+// Gram-Schmidt when a pivot is not safely positive.  gm: 2*K*K doubles + a flag,
+// tmp: K*n.
+template <class P>
+__device__ void orth_rows(P Z, int K, int n, P gm, P tmp, double* red) {
+  P R = gm + K * K;
+  int* flag = reinterpret_cast<int*>(&gm[2 * K * K]);
   for (int pass = 0; pass < 2; ++pass) {
     for (int q = threadIdx.x; q < K * K; q += blockDim.x) {
-      const int a = q / K, b = q % K;
+      const int a = q / K, b = q - a * K;
       double s = 0.0;
       if (a <= b)
         for (int t = 0; t < n; ++t) s += Z[(int64_t)a * n + t] * Z[(int64_t)b * n + t];
@@ -133,10 +153,10 @@ __device__ void orth_rows(double* Z, int K, int n, double* gm, double* tmp, doub
       for (int i = 0; i < K; ++i) dmax = fmax(dmax, gm[i * K + i]);
       for (int i = 0; i < K * K; ++i) R[i] = 0.0;
       for (int j = 0; j < K && ok; ++j) {
-        double d = gm[j * K + j];
-        for (int k = 0; k < j; ++k) d -= R[k * K + j] * R[k * K + j];
-        if (!(d > 1e-20 * dmax)) { ok = 0; break; }
-        const double rjj = sqrt(d);
+        double dj = gm[j * K + j];
+        for (int k = 0; k < j; ++k) dj -= R[k * K + j] * R[k * K + j];
+        if (!(dj > 1e-20 * dmax)) { ok = 0; break; }
+        const double rjj = sqrt(dj);
         R[j * K + j] = rjj;
         for (int i = j + 1; i < K; ++i) {
           double v = gm[j * K + i];
@@ -144,10 +164,10 @@ __device__ void orth_rows(double* Z, int K, int n, double* gm, double* tmp, doub
           R[j * K + i] = v / rjj;
         }
       }
-      flag[0] = ok;
+      *flag = ok;
     }
     __syncthreads();
-    if (!flag[0]) {  // (rare) nearly dependent vectors
+    if (!*flag) {  // (rare) nearly dependent vectors
       mgs_rows(Z, K, n, red);
       return;
     }
@@ -164,79 +184,62 @@ __device__ void orth_rows(double* Z, int K, int n, double* gm, double* tmp, doub
   }
 }
 
+// MODE 2: everything in LDS.  MODE 1: A in the global workspace, the rest in
+// LDS.  MODE 0: everything in the global workspace.
+template <int MODE>
 __global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restrict__ G, int n, int K, int Kout,
-                                                   int a_in_lds, int ws_in_lds, double* __restrict__ gws,
-                                                   double* __restrict__ lam_out, double* __restrict__ VK) {
+                                                           EigLayout L, double* __restrict__ gws,
+                                                           double* __restrict__ lam_out, double* __restrict__ VK) {
   extern __shared__ double sh[];
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
   const int stride = n + 1;
-  // workspace layout mirrors eig_layout(n, K, a_in_lds)
-  double* ws = ws_in_lds ? sh : gws;
-  int64_t o = 0;
-  double* A;
-  if (a_in_lds) {
-    A = ws;
-    o += (int64_t)n * stride;
-  } else {
-    A = gws;  // A occupies the head of the global workspace
-  }
-  if (!a_in_lds && !ws_in_lds) o += (int64_t)n * stride;
-  double* d = ws + o; o += n;
-  double* e = ws + o; o += n;
-  double* e2 = ws + o; o += n;
-  double* tau = ws + o; o += n;
-  double* p = ws + o; o += n;
-  double* v = ws + o; o += n;
-  double* red = ws + o; o += 64;
-  double* Z = ws + o; o += (int64_t)K * n;
-  double* lu = ws + o; o += (int64_t)K * 3 * n;
-  double* lam = ws + o; o += K;
-  double* brk = ws + o; o += 2 * K;
-  int* cnt = reinterpret_cast<int*>(ws + o); o += 32 * K;
-  double* gm = ws + o; o += 2 * K * K;
-  int* oflag = reinterpret_cast<int*>(ws + o);
+  double* A = MODE == 2 ? sh : gws;
+  // the remaining arrays: in LDS (MODE 1 and 2, after A only in MODE 2) or after A in the workspace
+  auto at = [&](int64_t off) -> double* { return MODE == 0 ? gws + off : sh + (off - (MODE == 1 ? L.a_size : 0)); };
+  double* d = at(L.d);
+  double* e = at(L.e);
+  double* e2 = at(L.e2);
+  double* tau = at(L.tau);
+  double* scl = at(L.scl);
+  double* p = at(L.p);
+  double* red = at(L.red);
+  double* Z = at(L.Z);
+  double* lu = at(L.lu);
+  double* lam = at(L.lam);
+  double* gm = at(L.gm);
 
-  for (int64_t t = tid; t < (int64_t)n * n; t += blockDim.x) {
-    const int i = (int)(t / n), j = (int)(t % n);
-    A[(int64_t)i * stride + j] = G[t];
-  }
+  for (int i = wave; i < n; i += EIG_WAVES)
+    for (int j = lane; j < n; j += 64) A[(int64_t)i * stride + j] = G[(int64_t)i * n + j];
   __syncthreads();
 
   // 1. tridiagonalisation
   for (int k = 0; k + 2 < n; ++k) {
     const int m = n - k - 1;
+    const double* rowk = A + (int64_t)k * stride + (k + 1);   // x_0..x_{m-1}, later the reflector
     double s = 0.0;
-    for (int i = tid + 1; i < m; i += blockDim.x) {
-      const double x = A[(int64_t)(k + 1 + i) * stride + k];
-      s += x * x;
-    }
-    const double xn2 = block_sum(s, red);
-    const double alpha = A[(int64_t)(k + 1) * stride + k];
-    if (tid == 0) d[k] = A[(int64_t)k * stride + k];
-    if (xn2 == 0.0) {
+    for (int i = lane + 1; i < m; i += 64) s += rowk[i] * rowk[i];
+    const double xn2 = wave_sum(s);     // every wave computes the same value
+    const double alpha = rowk[0];
+    if (xn2 == 0.0) {                   // the column is already reduced: identity reflector
       if (tid == 0) {
-        tau[k] = 0.0;
+        d[k] = A[(int64_t)k * stride + k];
         e[k] = alpha;
+        tau[k] = 0.0;
+        scl[k] = 0.0;
       }
-      __syncthreads();
       continue;
     }
     const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
     const double t = (beta - alpha) / beta;
     const double scale = 1.0 / (alpha - beta);
-    for (int i = tid; i < m; i += blockDim.x) {
-      const double vi = i == 0 ? 1.0 : A[(int64_t)(k + 1 + i) * stride + k] * scale;
-      v[i] = vi;
-    }
-    __syncthreads();
-    for (int i = tid; i < m; i += blockDim.x) A[(int64_t)(k + 1 + i) * stride + k] = v[i];
-    // p = t * A22 v, four threads per row (quad reduction)
+    // p = t * A22 v, four threads per row
     for (int i0 = 0; i0 < m; i0 += EIG_THREADS / 4) {
       const int i = i0 + (tid >> 2), sub = tid & 3;
       double acc = 0.0;
       if (i < m) {
         const double* row = A + (int64_t)(k + 1 + i) * stride + (k + 1);
-        for (int j = sub; j < m; j += 4) acc += row[j] * v[j];
+        for (int j = sub; j < m; j += 4) acc += row[j] * (j == 0 ? 1.0 : rowk[j] * scale);
       }
       acc += __shfl_xor(acc, 1, 64);
       acc += __shfl_xor(acc, 2, 64);
@@ -244,25 +247,31 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restr
     }
     __syncthreads();
     double pv = 0.0;
-    for (int i = tid; i < m; i += blockDim.x) pv += p[i] * v[i];
-    pv = block_sum(pv, red);
-    const double kc = 0.5 * t * pv;
-    for (int i = tid; i < m; i += blockDim.x) p[i] -= kc * v[i];
-    __syncthreads();
-    for (int64_t q = tid; q < (int64_t)m * m; q += blockDim.x) {
-      const int i = (int)(q / m), j = (int)(q % m);
-      A[(int64_t)(k + 1 + i) * stride + (k + 1 + j)] -= v[i] * p[j] + p[i] * v[j];
+    for (int i = lane; i < m; i += 64) pv += p[i] * (i == 0 ? 1.0 : rowk[i] * scale);
+    const double kc = 0.5 * t * wave_sum(pv);
+    // A22 -= v w^T + w v^T, rows over waves, columns over lanes
+    for (int i = wave; i < m; i += EIG_WAVES) {
+      const double vi = i == 0 ? 1.0 : rowk[i] * scale;
+      const double wi = p[i] - kc * vi;
+      double* row = A + (int64_t)(k + 1 + i) * stride + (k + 1);
+      for (int j = lane; j < m; j += 64) {
+        const double vj = j == 0 ? 1.0 : rowk[j] * scale;
+        const double wj = p[j] - kc * vj;
+        row[j] -= vi * wj + wi * vj;
+      }
     }
     if (tid == 0) {
-      tau[k] = t;
+      d[k] = A[(int64_t)k * stride + k];
       e[k] = beta;
+      tau[k] = t;
+      scl[k] = scale;
     }
     __syncthreads();
   }
   if (tid == 0) {
     if (n >= 2) {
       d[n - 2] = A[(int64_t)(n - 2) * stride + (n - 2)];
-      e[n - 2] = A[(int64_t)(n - 1) * stride + (n - 2)];
+      e[n - 2] = A[(int64_t)(n - 2) * stride + (n - 1)];
       tau[n - 2] = 0.0;
     }
     d[n - 1] = A[(int64_t)(n - 1) * stride + (n - 1)];
@@ -270,9 +279,10 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restr
     tau[n - 1] = 0.0;
   }
   __syncthreads();
-  for (int i = tid; i < n; i += blockDim.x) e2[i] = e[i] * e[i];
+  for (int i = tid; i < n; i += EIG_THREADS) e2[i] = e[i] * e[i];
   __syncthreads();
-  // Gershgorin bounds and scales
+
+  // Gershgorin interval and scales (every thread, same order)
   double glo = 1e300, ghi = -1e300, emax = 0.0, tnorm = 0.0;
   for (int i = 0; i < n; ++i) {
     const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
@@ -286,140 +296,549 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restr
   const double widen = 2.0 * eps * fmax(fabs(glo), fabs(ghi)) + pivmin;
   glo -= widen;
   ghi += widen;
-  __syncthreads();
 
-  // 2. the K largest eigenvalues by multisection (32 threads per eigenvalue, 33x narrower per round)
-  constexpr int MS = 32;
-  for (int j0 = 0; j0 < K; j0 += EIG_THREADS / MS) {
+  // 2. multisection: MS lanes (inside one wave) per eigenvalue, two points per lane
+  {
+    const int MS = K <= 8 ? 64 : (K <= 16 ? 32 : 16);
+    const int NP = 2 * MS;                       // points per round -> NP + 1 sub-intervals
     const int g = tid / MS, q = tid % MS;
-    const int j = j0 + g;
-    const bool act = j < K;
-    if (act && q == 0) {
-      brk[2 * j] = glo;
-      brk[2 * j + 1] = ghi;
+    const int gbase = lane & ~(MS - 1);
+    const unsigned long long gmask = MS == 64 ? ~0ULL : (((1ULL << MS) - 1) << gbase);
+    const double tol = 2.0 * eps * fmax(fabs(glo), fabs(ghi)) + pivmin;
+    int rounds = 1;
+    for (double w = ghi - glo; w > tol && rounds < 24; w /= (double)(NP + 1)) ++rounds;
+    const bool act = g < K;
+    const int idx = n - 1 - g;                   // ascending index of the g-th largest
+    double a = glo, b = ghi;
+    for (int r = 0; r < rounds; ++r) {
+      const double h = (b - a) / (double)(NP + 1);
+      const double x0 = a + h * (double)(2 * q + 1), x1 = a + h * (double)(2 * q + 2);
+      int c0 = 0, c1 = 0;
+      if (act) sturm_count2(d, e2, n, x0, x1, pivmin, c0, c1);
+      // points with at most idx eigenvalues below them lie below the eigenvalue
+      const unsigned long long m0 = __ballot(c0 <= idx) & gmask, m1 = __ballot(c1 <= idx) & gmask;
+      const int P = __popcll(m0) + __popcll(m1);
+      const double na = P == 0 ? a : a + h * (double)P;
+      const double nb = P == NP ? b : a + h * (double)(P + 1);
+      a = na;
+      b = nb;
     }
-    __syncthreads();
-    for (int round = 0; round < 12; ++round) {
-      if (act) {
-        const double a = brk[2 * j], b = brk[2 * j + 1];
-        const double x = a + (b - a) * (double)(q + 1) / (double)(MS + 1);
-        cnt[MS * j + q] = sturm_count(d, e2, n, x, pivmin);
-      }
-      __syncthreads();
-      if (act && q == 0) {
-        const int idx = n - 1 - j;  // ascending index of the j-th largest
-        const double a = brk[2 * j], b = brk[2 * j + 1];
-        double na = a, nb = b;
-        for (int r = 0; r < MS; ++r) {
-          const double x = a + (b - a) * (double)(r + 1) / (double)(MS + 1);
-          if (cnt[MS * j + r] <= idx) na = x;  // eigenvalue idx is at or above x
-          else { nb = x; break; }
-        }
-        brk[2 * j] = na;
-        brk[2 * j + 1] = nb;
-      }
-      __syncthreads();
-    }
-    if (act && q == 0) lam[j] = 0.5 * (brk[2 * j] + brk[2 * j + 1]);
-    __syncthreads();
+    if (act && q == 0) lam[g] = 0.5 * (a + b);
   }
+  __syncthreads();
 
   // 3. eigenvectors of T by inverse iteration, thread j for eigenvector j
   const double tiny = eps * fmax(tnorm, pivmin);
-  for (int j = tid; j < K; j += blockDim.x) {
+  for (int j = tid; j < K; j += EIG_THREADS) {
     double lj = lam[j];
     // separate (numerically) equal eigenvalues so the factorisations differ
     for (int i = 0; i < j; ++i)
       if (fabs(lam[i] - lj) < 10.0 * eps * fmax(tnorm, 1e-300)) lj -= 10.0 * eps * fmax(tnorm, 1e-300);
-    double* u0 = lu + (int64_t)j * 3 * n;
-    double* u1 = u0 + n;
+    double* ui = lu + (int64_t)j * 5 * n;   // 1/u0
+    double* u1 = ui + n;
     double* u2 = u1 + n;
+    double* ml = u2 + n;
+    double* pv = ml + n;
     double* z = Z + (int64_t)j * n;
+    double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
+    for (int i = 0; i < n - 1; ++i) {
+      const double c = e[i], nd = d[i + 1] - lj, ns = i + 1 < n - 1 ? e[i + 1] : 0.0;
+      if (fabs(c) > fabs(a0)) {         // swap rows i and i+1
+        const double mlt = a0 / c;
+        ui[i] = 1.0 / c; u1[i] = nd; u2[i] = ns; ml[i] = mlt; pv[i] = 1.0;
+        a0 = a1 - mlt * nd;
+        a1 = a2 - mlt * ns;
+      } else {
+        if (a0 == 0.0) a0 = tiny;
+        const double mlt = c / a0;
+        ui[i] = 1.0 / a0; u1[i] = a1; u2[i] = a2; ml[i] = mlt; pv[i] = 0.0;
+        a0 = nd - mlt * a1;
+        a1 = ns - mlt * a2;
+      }
+      a2 = 0.0;
+    }
+    if (a0 == 0.0) a0 = tiny;
+    ui[n - 1] = 1.0 / a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0; ml[n - 1] = 0.0; pv[n - 1] = 0.0;
     for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
-    for (int it = 0; it < 3; ++it) {
-      // LU of T - lj I with partial pivoting, applied to z as it is formed, then back substitution
-      double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
+    for (int it = 0; it < 2; ++it) {
       for (int i = 0; i < n - 1; ++i) {
-        const double c = e[i], nd = d[i + 1] - lj, ns = i + 1 < n - 1 ? e[i + 1] : 0.0;
-        if (fabs(c) > fabs(a0)) {
-          u0[i] = c; u1[i] = nd; u2[i] = ns;
-          const double mlt = a0 / c;
+        if (pv[i] != 0.0) {
           const double t0 = z[i];
           z[i] = z[i + 1];
-          z[i + 1] = t0 - mlt * z[i + 1];
-          a0 = a1 - mlt * nd;
-          a1 = a2 - mlt * ns;
-          a2 = 0.0;
+          z[i + 1] = t0 - ml[i] * z[i + 1];
         } else {
-          if (a0 == 0.0) a0 = tiny;
-          u0[i] = a0; u1[i] = a1; u2[i] = a2;
-          const double mlt = c / a0;
-          z[i + 1] -= mlt * z[i];
-          a0 = nd - mlt * a1;
-          a1 = ns - mlt * a2;
-          a2 = 0.0;
+          z[i + 1] -= ml[i] * z[i];
         }
       }
-      if (a0 == 0.0) a0 = tiny;
-      u0[n - 1] = a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0;
+      double z1 = 0.0, z2 = 0.0, nrm = 0.0;
       for (int i = n - 1; i >= 0; --i) {
-        double s = z[i];
-        if (i + 1 < n) s -= u1[i] * z[i + 1];
-        if (i + 2 < n) s -= u2[i] * z[i + 2];
-        z[i] = s / u0[i];
+        const double s = (z[i] - u1[i] * z1 - u2[i] * z2) * ui[i];
+        z[i] = s;
+        z2 = z1;
+        z1 = s;
+        nrm += s * s;
       }
-      double nrm = 0.0;
-      for (int i = 0; i < n; ++i) nrm += z[i] * z[i];
       nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
       for (int i = 0; i < n; ++i) z[i] *= nrm;
     }
   }
   __syncthreads();
-  orth_rows(Z, K, n, gm, lu, red, oflag);
 
-  // 4. back-transformation, one wave per vector
-  const int wave = tid >> 6, lane = tid & 63;
-  for (int j = wave; j < K; j += blockDim.x >> 6) {
-    double* z = Z + (int64_t)j * n;
-    for (int k = n - 3; k >= 0; --k) {
-      const double t = tau[k];
-      if (t == 0.0) continue;
-      const int m = n - k - 1;
-      double s = 0.0;
-      for (int i = lane; i < m; i += 64) s += A[(int64_t)(k + 1 + i) * stride + k] * z[k + 1 + i];
-      s = wave_sum(s);
-      for (int i = lane; i < m; i += 64) z[k + 1 + i] -= t * s * A[(int64_t)(k + 1 + i) * stride + k];
+  // 4. back-transformation, half a wave per vector (both halves run every
+  // iteration: the shuffles need the whole wave)
+  {
+    const int half = lane >> 5, hl = lane & 31;
+    for (int j0 = 0; j0 < K; j0 += 2 * EIG_WAVES) {
+      const int j = j0 + 2 * wave + half;
+      const bool on = j < K;
+      double* z = Z + (int64_t)(on ? j : 0) * n;
+      for (int k = n - 3; k >= 0; --k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        const int m = n - k - 1;
+        const double* rowk = A + (int64_t)k * stride + (k + 1);
+        const double sc = scl[k];
+        double s = 0.0;
+        if (on)
+          for (int i = hl; i < m; i += 32) s += (i == 0 ? 1.0 : rowk[i] * sc) * z[k + 1 + i];
+        s = half_sum(s);
+        if (on)
+          for (int i = hl; i < m; i += 32) z[k + 1 + i] -= t * s * (i == 0 ? 1.0 : rowk[i] * sc);
+      }
     }
   }
   __syncthreads();
-  orth_rows(Z, K, n, gm, lu, red, oflag);   // restore orthonormality after back-transformation
-  for (int64_t t = tid; t < (int64_t)n * K; t += blockDim.x) {
-    const int i = (int)(t / K), j = (int)(t % K);
+  orth_rows(Z, K, n, gm, lu, red);
+  for (int t = tid; t < n * K; t += EIG_THREADS) {
+    const int i = t / K, j = t - i * K;
     VK[(int64_t)i * Kout + j] = Z[(int64_t)j * n + i];
   }
-  for (int j = tid; j < K; j += blockDim.x) lam_out[j] = lam[j];
+  for (int j = tid; j < K; j += EIG_THREADS) lam_out[j] = lam[j];
+}
+
+// ---- K-hat <= 128: fused, register-resident variant --------------------------------------------
+//
+// Lane l of every wave owns the columns J = l and J = l + 64.  Step k holds the
+// reflector v_k and w_k = p_k - (tau_k/2)(p_k.v_k) v_k in registers (zero for
+// J <= k).  One pass per step updates rows k+2.. of the trailing matrix with
+// reflector k and, on the updated values, accumulates the product p_{k+1} =
+// tau_{k+1} A v_{k+1} of the next reflector, which every wave builds from the
+// updated row k+1 on its own.  The eight waves' partial products meet in LDS
+// (double-buffered by step parity), so each step has a single barrier.
+constexpr int SM_N = 128;
+
+__device__ __forceinline__ double rl(double x, int l) {   // x of lane l (l wave-uniform)
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// value at column J of a two-register row (J wave-uniform)
+__device__ __forceinline__ double col_of(const double (&x)[2], int J) { return rl(J < 64 ? x[0] : x[1], J & 63); }
+
+struct SmallLayout {
+  int64_t A, part, d, e, e2, tau, scl, red, lam, Z, lu, gm, total;
+};
+
+static SmallLayout small_layout(int n, int K) {
+  SmallLayout L{};
+  int64_t o = 0;
+  L.A = o; o += (int64_t)n * (n + 1);
+  L.part = o; o += 2 * EIG_WAVES * SM_N;
+  L.d = o; o += n;
+  L.e = o; o += n;
+  L.e2 = o; o += n;
+  L.tau = o; o += n;
+  L.scl = o; o += n;
+  L.red = o; o += 64;
+  L.lam = o; o += 32;
+  L.Z = o; o += (int64_t)K * n;
+  L.lu = o; o += (int64_t)K * 5 * n;
+  L.gm = o; o += 2 * (int64_t)K * K + 2;
+  L.total = o;
+  return L;
+}
+
+// Reflector that maps the entries J >= j0 of a register row x to a multiple of
+// e_{j0}: beta, tau, scale and v (v_{j0} = 1, v_J = x_J * scale for J > j0, 0 below).
+__device__ __forceinline__ void reflector(const double (&x)[2], int j0, int n, double& beta, double& t, double& scale,
+                                          double (&v)[2]) {
+  const int lane = threadIdx.x & 63;
+  double s = 0.0;
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int J = lane + 64 * c;
+    if (J > j0 && J < n) s += x[c] * x[c];
+  }
+  const double xn2 = wave_sum(s);
+  const double alpha = col_of(x, j0);
+  if (xn2 == 0.0) {
+    beta = alpha;
+    t = 0.0;
+    scale = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+    t = (beta - alpha) / beta;
+    scale = 1.0 / (alpha - beta);
+  }
+#pragma unroll
+  for (int c = 0; c < 2; ++c) {
+    const int J = lane + 64 * c;
+    v[c] = J == j0 ? 1.0 : ((J > j0 && J < n) ? x[c] * scale : 0.0);
+  }
+}
+
+// Eigenvalues of (d, e) below four points: q <- d_i - x - e_i^2 / q with a
+// Newton-refined hardware reciprocal (two FMAs after the estimate).
+__device__ __forceinline__ void sturm_count4(const double* d, const double* e2, int n, const double (&x)[4],
+                                             double pivmin, int (&cnt)[4]) {
+  double q[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    q[u] = d[0] - x[u];
+    if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+    cnt[u] = q[u] < 0.0;
+  }
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      double r = __builtin_amdgcn_rcp(q[u]);
+      r = fma(fma(-q[u], r, 1.0), r, r);
+      r = fma(fma(-q[u], r, 1.0), r, r);
+      q[u] = fma(-ei, r, di - x[u]);
+      if (fabs(q[u]) < pivmin) q[u] = -pivmin;
+      cnt[u] += q[u] < 0.0;
+    }
+  }
+}
+
+__global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __restrict__ G, int n, int K, int Kout,
+                                                            SmallLayout L, double* __restrict__ lam_out,
+                                                            double* __restrict__ VK) {
+  extern __shared__ double sh[];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // wave-uniform
+  const int S = n + 1;
+  double* A = sh + L.A;
+  double* part = sh + L.part;
+  double* d = sh + L.d;
+  double* e = sh + L.e;
+  double* e2 = sh + L.e2;
+  double* tau = sh + L.tau;
+  double* scl = sh + L.scl;
+  double* red = sh + L.red;
+  double* lam = sh + L.lam;
+  double* Z = sh + L.Z;
+  double* lu = sh + L.lu;
+  double* gm = sh + L.gm;
+
+  for (int i = wave; i < n; i += EIG_WAVES)
+    for (int j = lane; j < n; j += 64) A[i * S + j] = G[(int64_t)i * n + j];
+  __syncthreads();
+
+  // 1. tridiagonalisation
+  if (n <= 2) {
+    if (tid == 0) {
+      d[0] = A[0];
+      e[0] = n == 2 ? A[1] : 0.0;
+      tau[0] = 0.0;
+      if (n == 2) { d[1] = A[S + 1]; e[1] = 0.0; tau[1] = 0.0; }
+    }
+  } else {
+    double v[2], w[2], beta, t, scale;
+    {
+      double x[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int J = lane + 64 * c;
+        x[c] = J < n ? A[J] : 0.0;
+      }
+      reflector(x, 1, n, beta, t, scale, v);
+      double acc[2] = {0.0, 0.0};
+      for (int I = 1 + wave; I < n; I += EIG_WAVES) {
+        const double vI = col_of(v, I);
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int J = lane + 64 * c;
+          if (J >= 1 && J < n) acc[c] += A[I * S + J] * vI;
+        }
+      }
+      double* pb = part + EIG_WAVES * SM_N;   // the odd buffer: step 0 writes the even one
+#pragma unroll
+      for (int c = 0; c < 2; ++c) pb[wave * SM_N + lane + 64 * c] = acc[c];
+      __syncthreads();
+      double pv = 0.0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double sp = 0.0;
+        for (int ww = 0; ww < EIG_WAVES; ++ww) sp += pb[ww * SM_N + lane + 64 * c];
+        const double pc = t * sp;
+        w[c] = pc;
+        pv += pc * v[c];
+      }
+      const double kc = 0.5 * t * wave_sum(pv);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) w[c] -= kc * v[c];
+      if (tid == 0) {
+        d[0] = A[0];
+        e[0] = beta;
+        tau[0] = t;
+        scl[0] = scale;
+      }
+    }
+    for (int k = 0; k + 2 < n; ++k) {
+      // row k+1 after reflector k (v_{k+1} = 1)
+      const double wk1 = col_of(w, k + 1);
+      double nr[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        const int J = lane + 64 * c;
+        nr[c] = (J >= k + 1 && J < n) ? A[(k + 1) * S + J] - (w[c] + wk1 * v[c]) : 0.0;
+      }
+      const bool next = k + 3 < n;   // reflector k+1 exists
+      double vn[2] = {0.0, 0.0}, bn = 0.0, tn = 0.0, sn = 0.0;
+      if (next) reflector(nr, k + 2, n, bn, tn, sn, vn);
+      // rows k+2.. : update with reflector k, accumulate A v_{k+1}
+      double acc[2] = {0.0, 0.0};
+      for (int I = k + 2 + wave; I < n; I += EIG_WAVES) {
+        const double vI = col_of(v, I), wI = col_of(w, I), vnI = col_of(vn, I);
+        double* row = A + I * S;
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int J = lane + 64 * c;
+          if (J >= k + 2 && J < n) {
+            const double a = row[J] - (vI * w[c] + wI * v[c]);
+            row[J] = a;
+            acc[c] += a * vnI;
+          }
+        }
+      }
+      double* pb = part + (k & 1) * EIG_WAVES * SM_N;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) pb[wave * SM_N + lane + 64 * c] = acc[c];
+      __syncthreads();
+      if (wave == 0) {
+        // row k+1 keeps the next reflector's entries; the back-transformation reads them
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+          const int J = lane + 64 * c;
+          if (J >= k + 2 && J < n) A[(k + 1) * S + J] = nr[c];
+        }
+        const double dk1 = col_of(nr, k + 1), ek1 = next ? bn : col_of(nr, k + 2);   // whole wave active
+        if (lane == 0) {
+          d[k + 1] = dk1;
+          e[k + 1] = ek1;
+          tau[k + 1] = next ? tn : 0.0;
+          scl[k + 1] = next ? sn : 0.0;
+        }
+      }
+      if (!next) break;
+      double pv = 0.0;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        double sp = 0.0;
+        for (int ww = 0; ww < EIG_WAVES; ++ww) sp += pb[ww * SM_N + lane + 64 * c];
+        const int J = lane + 64 * c;
+        const double pc = (J >= k + 2 && J < n) ? tn * sp : 0.0;
+        w[c] = pc;
+        pv += pc * vn[c];
+      }
+      const double kc = 0.5 * tn * wave_sum(pv);
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        w[c] -= kc * vn[c];
+        v[c] = vn[c];
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      d[n - 1] = A[(n - 1) * S + (n - 1)];
+      e[n - 1] = 0.0;
+      tau[n - 1] = 0.0;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < n; i += EIG_THREADS) e2[i] = e[i] * e[i];
+  __syncthreads();
+
+  double glo = 1e300, ghi = -1e300, emax = 0.0, tnorm = 0.0;
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < n ? fabs(e[i]) : 0.0);
+    glo = fmin(glo, d[i] - r);
+    ghi = fmax(ghi, d[i] + r);
+    emax = fmax(emax, i + 1 < n ? e2[i] : 0.0);
+    tnorm = fmax(tnorm, fabs(d[i]) + r);
+  }
+  const double eps = 2.220446049250313e-16;
+  const double pivmin = fmax(2.2250738585072014e-308, eps * eps * emax);
+  const double widen = 2.0 * eps * fmax(fabs(glo), fabs(ghi)) + pivmin;
+  glo -= widen;
+  ghi += widen;
+
+  // 2. multisection, 16 lanes x 4 points per eigenvalue (65 sub-intervals per
+  // round) until the interval is below 1e-11 of the spectrum's scale: inverse
+  // iteration needs no more, and the eigenvalues only scale U's columns
+  {
+    const int MS = 16, NP = 64;
+    const int g = tid >> 4, q = tid & 15;
+    const int gbase = lane & ~15;
+    const unsigned long long gmask = 0xFFFFULL << gbase;
+    const double tol = 1e-11 * fmax(tnorm, pivmin);
+    int rounds = 1;
+    for (double wd = ghi - glo; wd > tol && rounds < 24; wd /= (double)(NP + 1)) ++rounds;
+    const bool act = g < K;
+    const int idx = n - 1 - g;
+    double a = glo, b = ghi;
+    for (int r = 0; r < rounds; ++r) {
+      const double h = (b - a) / (double)(NP + 1);
+      double x[4];
+      int cnt[4] = {0, 0, 0, 0};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) x[u] = a + h * (double)(4 * q + u + 1);
+      if (act) sturm_count4(d, e2, n, x, pivmin, cnt);
+      int P = 0;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) P += __popcll(__ballot(cnt[u] <= idx) & gmask);
+      const double na = P == 0 ? a : a + h * (double)P;
+      const double nb = P == NP ? b : a + h * (double)(P + 1);
+      a = na;
+      b = nb;
+    }
+    (void)MS;
+    if (act && q == 0) lam[g] = 0.5 * (a + b);
+  }
+  __syncthreads();
+
+  // 3. inverse iteration (as in the general kernel)
+  const double tiny = eps * fmax(tnorm, pivmin);
+  for (int j = tid; j < K; j += EIG_THREADS) {
+    double lj = lam[j];
+    for (int i = 0; i < j; ++i)
+      if (fabs(lam[i] - lj) < 10.0 * eps * fmax(tnorm, 1e-300)) lj -= 10.0 * eps * fmax(tnorm, 1e-300);
+    double* ui = lu + (int64_t)j * 5 * n;
+    double* u1 = ui + n;
+    double* u2 = u1 + n;
+    double* ml = u2 + n;
+    double* pv = ml + n;
+    double* z = Z + (int64_t)j * n;
+    double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
+    for (int i = 0; i < n - 1; ++i) {
+      const double c = e[i], nd = d[i + 1] - lj, ns = i + 1 < n - 1 ? e[i + 1] : 0.0;
+      if (fabs(c) > fabs(a0)) {
+        const double mlt = a0 / c;
+        ui[i] = 1.0 / c; u1[i] = nd; u2[i] = ns; ml[i] = mlt; pv[i] = 1.0;
+        a0 = a1 - mlt * nd;
+        a1 = a2 - mlt * ns;
+      } else {
+        if (a0 == 0.0) a0 = tiny;
+        const double mlt = c / a0;
+        ui[i] = 1.0 / a0; u1[i] = a1; u2[i] = a2; ml[i] = mlt; pv[i] = 0.0;
+        a0 = nd - mlt * a1;
+        a1 = ns - mlt * a2;
+      }
+      a2 = 0.0;
+    }
+    if (a0 == 0.0) a0 = tiny;
+    ui[n - 1] = 1.0 / a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0; ml[n - 1] = 0.0; pv[n - 1] = 0.0;
+    for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
+    for (int it = 0; it < 2; ++it) {
+      double cur = z[0];
+      for (int i = 0; i < n - 1; ++i) {
+        const double nx = z[i + 1];
+        if (pv[i] != 0.0) {
+          z[i] = nx;
+          cur = cur - ml[i] * nx;
+        } else {
+          z[i] = cur;
+          cur = nx - ml[i] * cur;
+        }
+      }
+      z[n - 1] = cur;
+      double z1 = 0.0, z2 = 0.0, nrm = 0.0;
+      for (int i = n - 1; i >= 0; --i) {
+        const double s = (z[i] - u1[i] * z1 - u2[i] * z2) * ui[i];
+        z[i] = s;
+        z2 = z1;
+        z1 = s;
+        nrm += s * s;
+      }
+      nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
+      for (int i = 0; i < n; ++i) z[i] *= nrm;
+    }
+  }
+  __syncthreads();
+
+  // 4. back-transformation: half a wave per vector, the vector in registers
+  {
+    const int half = lane >> 5, hl = lane & 31;
+    for (int j0 = 0; j0 < K; j0 += 2 * EIG_WAVES) {
+      const int j = j0 + 2 * wave + half;
+      const bool on = j < K;
+      double* zr = Z + (int64_t)(on ? j : 0) * n;
+      double z[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = hl + 32 * c;
+        z[c] = (on && i < n) ? zr[i] : 0.0;
+      }
+      for (int k = n - 3; k >= 0; --k) {
+        const double t = tau[k];
+        if (t == 0.0) continue;
+        const double sc = scl[k];
+        const double* rowk = A + k * S;
+        double vv[4], s = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = hl + 32 * c;
+          vv[c] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? rowk[i] * sc : 0.0);
+          s += vv[c] * z[c];
+        }
+        s = t * half_sum(s);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[c] -= s * vv[c];
+      }
+      if (on)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+          const int i = hl + 32 * c;
+          if (i < n) zr[i] = z[c];
+        }
+    }
+  }
+  __syncthreads();
+  orth_rows(Z, K, n, gm, lu, red);
+  for (int t = tid; t < n * K; t += EIG_THREADS) {
+    const int i = t / K, j = t - i * K;
+    VK[(int64_t)i * Kout + j] = Z[(int64_t)j * n + i];
+  }
+  for (int j = tid; j < K; j += EIG_THREADS) lam_out[j] = lam[j];
 }
 
 // Leading K eigenpairs of G (n0 x n0, FP64): lam_k[0..K) descending and VK (n0 x K).
 // Eigenpairs beyond n0 (K > n0) are reported as zero eigenvalues.
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK) {
   const int Ke = K < n0 ? K : n0;
-  const EigLayout with_a = eig_layout(n0, Ke, true), no_a = eig_layout(n0, Ke, false);
+  TK_REQUIRE(Ke <= 32, TK_ERR_UNSUPPORTED, "eigensolve: more than 32 eigenpairs");
+  const EigLayout L = eig_layout(n0, Ke);
   const size_t lim = c->lds_per_block;
-  int a_in_lds = 0, ws_in_lds = 0;
-  size_t lds = 0;
-  if ((size_t)with_a.total * 8 <= lim) {
-    a_in_lds = 1;
-    ws_in_lds = 1;
-    lds = (size_t)with_a.total * 8;
-  } else if ((size_t)no_a.total * 8 <= lim) {
-    ws_in_lds = 1;
-    lds = (size_t)no_a.total * 8;
-  }
-  ensure(c, c->work, sizeof(double) * (size_t)(with_a.total + 16));
+  ensure(c, c->work, sizeof(double) * (size_t)(L.total + 16));
   if (K > Ke) TK_HIP(hipMemsetAsync(lam_k, 0, sizeof(double) * K, c->stream));
-  hipLaunchKernelGGL(k_syev_topk, dim3(1), dim3(EIG_THREADS), lds, c->stream, G, n0, Ke, K, a_in_lds, ws_in_lds,
-                     c->work.as<double>(), lam_k, VK);
+  double* ws = c->work.as<double>();
+  const SmallLayout SL = small_layout(n0, Ke);
+  if (n0 <= SM_N && Ke <= 16 && (size_t)SL.total * 8 <= lim) {
+    hipLaunchKernelGGL(k_syev_small, dim3(1), dim3(EIG_THREADS), (size_t)SL.total * 8, c->stream, G, n0, Ke, K, SL,
+                       lam_k, VK);
+  } else if ((size_t)L.total * 8 <= lim) {
+    hipLaunchKernelGGL(k_syev_topk<2>, dim3(1), dim3(EIG_THREADS), (size_t)L.total * 8, c->stream, G, n0, Ke, K, L,
+                       ws, lam_k, VK);
+  } else if ((size_t)(L.total - L.a_size) * 8 <= lim) {
+    hipLaunchKernelGGL(k_syev_topk<1>, dim3(1), dim3(EIG_THREADS), (size_t)(L.total - L.a_size) * 8, c->stream,
+                       G, n0, Ke, K, L, ws, lam_k, VK);
+  } else {
+    hipLaunchKernelGGL(k_syev_topk<0>, dim3(1), dim3(EIG_THREADS), 0, c->stream, G, n0, Ke, K, L, ws, lam_k, VK);
+  }
   TK_CHECK_LAUNCH();
 }
 

@@ -1,6 +1,7 @@
 // New factor from the leading eigenpairs of G = Y^T Y (Section 2.2: the new
 // F_n holds the leading K_n left singular vectors of Y_(n)):
-//   U  = Y W,  W = V_K diag(lam_k)^(-1/2)     (R_n x K_n, FP64 accumulation)
+//   U  = Y W,  W = V_K diag(lam_k)^(-1/2)     (R_n x K_n; FP32 MFMA for K <= 16,
+//                                              else FP64 accumulation)
 //   CholeskyQR2 in FP64: A = U^T U, A = R^T R (Cholesky), U <- U R^-1, twice,
 //   which restores orthonormality to working precision;
 //   F_n = U on the nonempty slices' rows, zero elsewhere (FP64 master),
@@ -60,6 +61,146 @@ __global__ __launch_bounds__(256) void k_uw(const float* __restrict__ Y, int64_t
     const int i = threadIdx.x + 256 * q;
     if (i < K * K) part[(int64_t)blockIdx.x * K * K + i] = acc[q];
   }
+}
+
+__device__ __forceinline__ uint16_t to_bf16_rne(float f) {
+  uint32_t b = __float_as_uint(f);
+  b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
+  return (uint16_t)(b >> 16);
+}
+
+typedef float floatx4_f __attribute__((ext_vector_type(4)));
+typedef double doublex4_f __attribute__((ext_vector_type(4)));
+
+// Combine the four waves' 16x16 Gram tiles in wave order and write the K x K
+// block of this workgroup.  Register r of lane l holds G[row][l%16] with
+// row = 4*(l/16) + r for the FP32 MFMA and row = l/16 + 4*r for the FP64 one.
+template <bool F64LAYOUT, class T4>
+__device__ __forceinline__ void write_gram_part(const T4& g, int K, double* red, double* __restrict__ part) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        double* dst = red + r * 64 + lane;
+        *dst = (w == 0) ? (double)g[r] : *dst + (double)g[r];
+      }
+    __syncthreads();
+  }
+  if (threadIdx.x < 256) {
+    const int r = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int a = F64LAYOUT ? (l >> 4) + 4 * r : 4 * (l >> 4) + r, b = l & 15;
+    if (a < K && b < K) part[(int64_t)blockIdx.x * K * K + a * K + b] = red[threadIdx.x];
+  }
+}
+
+// U = Y W on the matrix cores (K <= 16): v_mfma_f32_16x16x4_f32 over 16-row
+// tiles, one tile per wave at a time.  Lane l reads four consecutive columns
+// (s + 4*(l/16) .. +3) of row l%16 of the tile; MFMA u contracts column
+// s + 4k + u of Y (k = l/16) with row s + 4k + u of W.  The result tile gives
+// U (stored FP64) and, with the same registers as both operands, the
+// workgroup's partial U^T U.  VEC: khat % 4 == 0 (16-byte loads).
+template <bool VEC>
+__global__ __launch_bounds__(256) void k_uw_mfma(const float* __restrict__ Y, int64_t R, int khat,
+                                                 const double* __restrict__ W, int K, double* __restrict__ U,
+                                                 double* __restrict__ part) {
+  __shared__ double red[256];
+  extern __shared__ float wl[];   // kpad x 16, FP32, zero beyond khat and K
+  const int kpad = (khat + 15) & ~15;
+  for (int i = threadIdx.x; i < kpad * 16; i += blockDim.x) {
+    const int c = i >> 4, j = i & 15;
+    wl[i] = (c < khat && j < K) ? (float)W[(int64_t)c * K + j] : 0.f;
+  }
+  __syncthreads();
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i16 = lane & 15, q = lane >> 4;
+  floatx4_f g = {0.f, 0.f, 0.f, 0.f};
+  const int64_t ntile = (R + 15) >> 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4) {
+    const int64_t row = t * 16 + i16;
+    const bool rok = row < R;
+    const float* yr = Y + row * khat;
+    floatx4_f c = {0.f, 0.f, 0.f, 0.f};
+    for (int s = 0; s < kpad; s += 16) {
+      const int col = s + 4 * q;
+      float y[4];
+      if (VEC) {
+        const float4 v = (rok && col < khat) ? *reinterpret_cast<const float4*>(yr + col) : float4{0.f, 0.f, 0.f, 0.f};
+        y[0] = v.x; y[1] = v.y; y[2] = v.z; y[3] = v.w;
+      } else {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) y[u] = (rok && col + u < khat) ? yr[col + u] : 0.f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) c = __builtin_amdgcn_mfma_f32_16x16x4f32(y[u], wl[(col + u) * 16 + i16], c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = t * 16 + 4 * q + r;
+      if (rr < R && i16 < K) U[rr * K + i16] = (double)c[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) g = __builtin_amdgcn_mfma_f32_16x16x4f32(c[r], c[r], g, 0, 0, 0);
+  }
+  write_gram_part<false>(g, K, red, part);
+}
+
+// U <- U Rinv on the FP64 matrix cores (K <= 16), 16-row tiles: lane l supplies
+// A[i = l%16][k = l/16] = U[row i][4s + k] and B[k][j = l%16] = Rinv[4s + k][j]
+// for s = 0..3; v_mfma_f64_16x16x4_f64 returns D[l/16 + 4r][l%16] in register r.  Not FINAL: write U back and the partial U^T U of the result.
+// FINAL: write the rows straight into the factor's FP64 master (slice order)
+// and its FP32 / BF16 working copies (storage labels).
+template <bool FINAL>
+__global__ __launch_bounds__(256) void k_rinv_mfma(double* __restrict__ U, int64_t R, int K,
+                                                   const double* __restrict__ Rinv, double* __restrict__ part,
+                                                   const int32_t* __restrict__ row_slice,
+                                                   const int32_t* __restrict__ label, double* __restrict__ F64,
+                                                   float* __restrict__ F32, int kp32, uint16_t* __restrict__ F16,
+                                                   int kp16) {
+  __shared__ double red[256];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i16 = lane & 15, q = lane >> 4;
+  double rb[4];
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int k = 4 * s + q;
+    rb[s] = (k < K && i16 < K) ? Rinv[k * K + i16] : 0.0;
+  }
+  doublex4_f g = {0.0, 0.0, 0.0, 0.0};
+  const int64_t ntile = (R + 15) >> 4;
+  for (int64_t t = (int64_t)blockIdx.x * 4 + wave; t < ntile; t += (int64_t)gridDim.x * 4) {
+    const int64_t row = t * 16 + i16;
+    const bool rok = row < R;
+    doublex4_f c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+      const int k = 4 * s + q;
+      const double a = (rok && k < K) ? U[row * K + k] : 0.0;
+      c = __builtin_amdgcn_mfma_f64_16x16x4f64(a, rb[s], c, 0, 0, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = t * 16 + q + 4 * r;
+      if (rr < R && i16 < K) {
+        if (FINAL) {
+          const int64_t l = row_slice[rr];
+          const int64_t sl = label[l];
+          F64[l * K + i16] = c[r];
+          F32[sl * kp32 + i16] = (float)c[r];
+          F16[sl * kp16 + i16] = to_bf16_rne((float)c[r]);
+        } else {
+          U[rr * K + i16] = c[r];
+        }
+      }
+    }
+    if (!FINAL) {
+      // every lane has read its U values above before any lane overwrote them:
+      // a tile's rows are read and written by the same wave only
+#pragma unroll
+      for (int r = 0; r < 4; ++r) g = __builtin_amdgcn_mfma_f64_16x16x4f64(c[r], c[r], g, 0, 0, 0);
+    }
+  }
+  if (!FINAL) write_gram_part<true>(g, K, red, part);
 }
 
 // U <- U Rinv (upper triangular, K x K) and partial U^T U of the result, over
@@ -178,12 +319,6 @@ __global__ void k_make_w(const double* __restrict__ VK, const double* __restrict
   }
 }
 
-__device__ __forceinline__ uint16_t to_bf16_rne(float f) {
-  uint32_t b = __float_as_uint(f);
-  b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
-  return (uint16_t)(b >> 16);
-}
-
 // F64[row_slice[r]] = U[r] (index order); FP32 / BF16 working copies of the
 // same rows at their storage labels.
 __global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
@@ -285,9 +420,10 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
                  int* flag_dev, bool check_flag) {
   const int K = c->K[n];
   TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "factor step: rank above 32");
-  const int64_t ntile = std::max<int64_t>(1, ceil_div(R, FT_ROWS));
+  const bool mfma = K <= 16;
+  const int64_t ntile = std::max<int64_t>(1, ceil_div(R, mfma ? 16 : FT_ROWS));
   const int tiles = (int)std::max<int64_t>(1, ceil_div(ntile, 1024));
-  const int nwg = (int)ceil_div(ntile, tiles);
+  const int nwg = mfma ? (int)std::min<int64_t>(2048, ceil_div(ntile, 4)) : (int)ceil_div(ntile, tiles);
   ensure(c, c->U64, sizeof(double) * (size_t)std::max<int64_t>(R, 1) * K);
   ensure(c, c->small64, sizeof(double) * ((size_t)khat * K + 3 * (size_t)K * K + (size_t)nwg * K * K));
   double* W = c->small64.as<double>();
@@ -295,34 +431,60 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   double* Asum = Rinv + (size_t)K * K;
   double* part = Asum + (size_t)K * K;
   double* U = c->U64.as<double>();
+  const ModePlan& pl = c->plan[n];
   TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, khat,
                      K, W, flag_dev);
   TK_CHECK_LAUNCH();
-  if (R > 0) {
+  auto clear_factor = [&]() {   // rows of empty slices stay zero
+    TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
+    TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
+    TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+  };
+  auto reduce_chol = [&]() {
+    hipLaunchKernelGGL(k_sum_parts, dim3(std::min(K * K, 1024)), dim3(256), 0, c->stream, part, nwg, K * K, Asum);
+    TK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), sizeof(double) * 2 * K * K, c->stream, Asum, K, Rinv,
+                       flag_dev);
+    TK_CHECK_LAUNCH();
+  };
+  if (R > 0 && mfma) {
+    const int kpad = (khat + 15) & ~15;
+    const size_t lds = sizeof(float) * (size_t)kpad * 16;
+    TK_REQUIRE(lds + 2048 <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat too large for LDS");
+    if (khat % 4 == 0)
+      hipLaunchKernelGGL(k_uw_mfma<true>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+    else
+      hipLaunchKernelGGL(k_uw_mfma<false>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+    TK_CHECK_LAUNCH();
+    reduce_chol();
+    hipLaunchKernelGGL(k_rinv_mfma<false>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part, nullptr, nullptr,
+                       nullptr, nullptr, 0, nullptr, 0);
+    TK_CHECK_LAUNCH();
+    reduce_chol();
+    clear_factor();
+    hipLaunchKernelGGL(k_rinv_mfma<true>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part,
+                       pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
+                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
+    TK_CHECK_LAUNCH();
+  } else if (R > 0) {
     size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat x K too large for LDS");
     hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, tiles, U, part);
     TK_CHECK_LAUNCH();
     for (int pass = 0; pass < 2; ++pass) {
-      hipLaunchKernelGGL(k_sum_parts, dim3(std::min(K * K, 1024)), dim3(256), 0, c->stream, part, nwg, K * K, Asum);
-      TK_CHECK_LAUNCH();
-      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), sizeof(double) * 2 * K * K, c->stream, Asum, K, Rinv,
-                         flag_dev);
-      TK_CHECK_LAUNCH();
+      reduce_chol();
       hipLaunchKernelGGL(k_apply_rinv, dim3(nwg), dim3(256), sizeof(double) * ((size_t)K * K + 2 * FT_ROWS * K),
                          c->stream, U, R, K, tiles, Rinv, part);
       TK_CHECK_LAUNCH();
     }
-  }
-  TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
-  TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
-  TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
-  if (R > 0) {
+    clear_factor();
     hipLaunchKernelGGL(k_scatter_factor, dim3(grid_for(R * K, 256)), dim3(256), 0, c->stream, U, R, K,
-                       c->plan[n].row_slice.as<int32_t>(), c->plan[n].label.as<int32_t>(), c->F64[n].as<double>(),
+                       pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
                        c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
     TK_CHECK_LAUNCH();
+  } else {
+    clear_factor();
   }
   if (!check_flag && R >= K) return false;
   int hflag = 0;

@@ -9,6 +9,12 @@
 // pieces feeds every tile in the same column block.  The result tile holds
 // D[4*(l/16) + r][l%16] in register r.
 //
+// Precision form: the same tiles on v_mfma_f32_16x16x32_bf16, where lane l
+// supplies eight consecutive rows (k = 8*(l/16) .. +7) of column l%16 rounded
+// to BF16 (round to nearest even); products accumulate in FP32.  A and B take
+// their k values from the same rows, so the order of k inside a step does not
+// matter.
+//
 // Each wave accumulates its share of 4-row steps for a set of 16x16 tiles;
 // the four waves of a workgroup are combined in LDS in fixed order and each
 // workgroup writes one FP32 partial; a second kernel sums the partials in
@@ -18,6 +24,7 @@
 namespace tk {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // Tiles (bi, bj) of the macro pair: bi in [I0, I0+NBA), bj in [J0, J0+NBB);
 // DIAG = the pair is on the diagonal and only bi <= bj is computed.
@@ -57,7 +64,7 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
   int PI, PJ;
   macro_pair(DIAG, pair, MB, PI, PJ);
   const int I0 = PI * NBA, J0 = PJ * NBB;
-  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min(r0 + rows_per_wg, R);
   floatx4 acc[T];
@@ -65,13 +72,17 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
   for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lr = lane >> 4, lc = lane & 15;
   // software pipeline: the next 4-row step is loaded while this one's MFMAs run
+  // loads are unconditional (addresses clamped into Y, values selected to
+  // zero): predicated loads would become one branch each
   auto load = [&](int64_t r, float (&xa)[NBA], float (&xb)[NBB]) {
     const int64_t row = r + lr;
     const bool rok = row < r1;
+    const float* yr = Y + (rok ? row : r1 - 1) * khat;
 #pragma unroll
     for (int b = 0; b < NBA; ++b) {
       const int col = (I0 + b) * 16 + lc;
-      xa[b] = (rok && col < khat) ? Y[row * khat + col] : 0.f;
+      const float v = yr[col < khat ? col : khat - 1];
+      xa[b] = (rok && col < khat) ? v : 0.f;
     }
     if constexpr (DIAG) {
 #pragma unroll
@@ -80,7 +91,8 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
 #pragma unroll
       for (int b = 0; b < NBB; ++b) {
         const int col = (J0 + b) * 16 + lc;
-        xb[b] = (rok && col < khat) ? Y[row * khat + col] : 0.f;
+        const float v = yr[col < khat ? col : khat - 1];
+        xb[b] = (rok && col < khat) ? v : 0.f;
       }
     }
   };
@@ -90,15 +102,97 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
   for (; r < r1; r += 16) {
     float na[NBA], nb[NBB];
     if (r + 16 < r1) load(r + 16, na, nb);
+    int t = 0;
 #pragma unroll
-    for (int t = 0; t < T; ++t)
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[TS::ti(t)], xb[TS::tj(t)], acc[t], 0, 0, 0);
+    for (int a = 0; a < NBA; ++a)
+#pragma unroll
+      for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a], xb[bj], acc[t], 0, 0, 0);
 #pragma unroll
     for (int b = 0; b < NBA; ++b) xa[b] = na[b];
 #pragma unroll
     for (int b = 0; b < NBB; ++b) xb[b] = nb[b];
   }
   // combine the four waves in fixed order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float* dst = red + t * 256 + q * 64 + lane;
+          *dst = (w == 0) ? acc[t][q] : *dst + acc[t][q];
+        }
+    }
+    __syncthreads();
+  }
+  float* out = part + ((int64_t)blockIdx.x * gridDim.y + pair) * (int64_t)T * 256;
+  for (int i = threadIdx.x; i < T * 256; i += blockDim.x) out[i] = red[i];
+}
+
+// BF16 operands, FP32 accumulation: 32 rows per MFMA step, each wave takes
+// every fourth 32-row step of the workgroup's rows.
+template <int NBA, int NBB, bool DIAG>
+__global__ __launch_bounds__(256) void k_gram_bf16(const float* __restrict__ Y, int64_t R, int khat,
+                                                   int rows_per_wg, int MB, float* __restrict__ part) {
+  using TS = TileSet<NBA, NBB, DIAG>;
+  constexpr int T = TS::count;
+  constexpr int NL = DIAG ? NBA : NBA + NBB;   // column blocks loaded per step
+  extern __shared__ float red[];
+  const int pair = blockIdx.y;
+  int PI, PJ;
+  macro_pair(DIAG, pair, MB, PI, PJ);
+  const int I0 = PI * NBA, J0 = PJ * NBB;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
+  const int64_t r1 = min(r0 + rows_per_wg, R);
+  floatx4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int lr = lane >> 4, lc = lane & 15;
+  int cols[NL];
+#pragma unroll
+  for (int b = 0; b < NL; ++b) cols[b] = (b < NBA ? (I0 + b) : (J0 + b - NBA)) * 16 + lc;
+  // FP32 values of the next step stay in flight while this step's MFMAs run
+  int ccol[NL];
+  bool cok[NL];
+#pragma unroll
+  for (int b = 0; b < NL; ++b) {
+    cok[b] = cols[b] < khat;
+    ccol[b] = cok[b] ? cols[b] : khat - 1;
+  }
+  // unconditional loads (clamped addresses, values selected to zero)
+  auto load = [&](int64_t r, float (&f)[NL][8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t row = r + 8 * lr + q;
+      const bool rok = row < r1;
+      const float* yr = Y + (rok ? row : r1 - 1) * khat;
+#pragma unroll
+      for (int b = 0; b < NL; ++b) {
+        const float v = yr[ccol[b]];
+        f[b][q] = (rok && cok[b]) ? v : 0.f;
+      }
+    }
+  };
+  float f[NL][8];
+  int64_t r = r0 + 32 * wave;
+  if (r < r1) load(r, f);
+  for (; r < r1; r += 128) {
+    bf16x8 x[NL];
+#pragma unroll
+    for (int b = 0; b < NL; ++b)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[b][q] = (__bf16)f[b][q];
+    if (r + 128 < r1) load(r + 128, f);
+    // tiles in TileSet order, with compile-time operand indices
+    int t = 0;
+#pragma unroll
+    for (int a = 0; a < NBA; ++a)
+#pragma unroll
+      for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[a], x[DIAG ? bj : NBA + bj], acc[t], 0, 0, 0);
+  }
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
 #pragma unroll
@@ -156,13 +250,14 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nchunks, int 
   G[(int64_t)gj * khat + gi] = s;
 }
 
-template <int NBA, int NBB, bool DIAG>
+template <int NBA, int NBB, bool DIAG, bool BF16>
 static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, int MB, double* G) {
   using TS = TileSet<NBA, NBB, DIAG>;
   constexpr int T = TS::count;
   if (npairs == 0) return;
   const int64_t target_wgs = std::max<int64_t>(1, 1024 / npairs);
-  const int rows_per_wg = (int)std::max<int64_t>(64, ceil_div(ceil_div(R, target_wgs), 16) * 16);
+  const int64_t gran = BF16 ? 128 : 16;   // rows per workgroup-wide step
+  const int rows_per_wg = (int)std::max<int64_t>(BF16 ? 128 : 64, ceil_div(ceil_div(R, target_wgs), gran) * gran);
   const int nchunks = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
   const int group = 32;
   const int ngroups = (nchunks + group - 1) / group;
@@ -172,8 +267,12 @@ static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, in
   float* part = c->gram_part.as<float>();
   double* part2 = reinterpret_cast<double*>(c->gram_part.as<char>() + ((b1 + 255) & ~(size_t)255));
   TK_REQUIRE(((b1 + 255) & ~(size_t)255) + b2 <= c->gram_part.bytes(), TK_ERR_DEVICE, "gram scratch");
-  hipLaunchKernelGGL((k_gram<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
-                     c->stream, Y, R, khat, rows_per_wg, MB, part);
+  if (BF16)
+    hipLaunchKernelGGL((k_gram_bf16<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
+                       c->stream, Y, R, khat, rows_per_wg, MB, part);
+  else
+    hipLaunchKernelGGL((k_gram<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
+                       c->stream, Y, R, khat, rows_per_wg, MB, part);
   TK_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_colsum_groups, dim3((unsigned)ceil_div(M, 256), ngroups), dim3(256), 0, c->stream, part,
                      (int64_t)nchunks, M, group, part2);
@@ -183,8 +282,8 @@ static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, in
   TK_CHECK_LAUNCH();
 }
 
-// G (khat x khat FP64, full) = Y^T Y.
-void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
+template <bool BF16>
+static void gram_impl(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
   const int NB = (khat + 15) / 16;
   if (R == 0) {
     TK_HIP(hipMemsetAsync(G, 0, sizeof(double) * (size_t)khat * khat, c->stream));
@@ -192,21 +291,27 @@ void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
   }
   if (NB <= 8) {
     switch (NB) {
-      case 1: run_gram<1, 1, true>(c, Y, R, khat, 1, 1, G); break;
-      case 2: run_gram<2, 2, true>(c, Y, R, khat, 1, 1, G); break;
-      case 3: run_gram<3, 3, true>(c, Y, R, khat, 1, 1, G); break;
-      case 4: run_gram<4, 4, true>(c, Y, R, khat, 1, 1, G); break;
-      case 5: run_gram<5, 5, true>(c, Y, R, khat, 1, 1, G); break;
-      case 6: run_gram<6, 6, true>(c, Y, R, khat, 1, 1, G); break;
-      case 7: run_gram<7, 7, true>(c, Y, R, khat, 1, 1, G); break;
-      default: run_gram<8, 8, true>(c, Y, R, khat, 1, 1, G); break;
+      case 1: run_gram<1, 1, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 2: run_gram<2, 2, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 3: run_gram<3, 3, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 4: run_gram<4, 4, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 5: run_gram<5, 5, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 6: run_gram<6, 6, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      case 7: run_gram<7, 7, true, BF16>(c, Y, R, khat, 1, 1, G); break;
+      default: run_gram<8, 8, true, BF16>(c, Y, R, khat, 1, 1, G); break;
     }
     return;
   }
   // macro blocks of 4 column blocks (64 columns): diagonal pairs and the upper off-diagonal pairs
   const int MB = (NB + 3) / 4;
-  run_gram<4, 4, true>(c, Y, R, khat, MB, MB, G);
-  run_gram<4, 4, false>(c, Y, R, khat, MB * (MB - 1) / 2, MB, G);
+  run_gram<4, 4, true, BF16>(c, Y, R, khat, MB, MB, G);
+  run_gram<4, 4, false, BF16>(c, Y, R, khat, MB * (MB - 1) / 2, MB, G);
+}
+
+// G (khat x khat FP64, full) = Y^T Y; bf16 = operands rounded to BF16 (FP32 accumulation).
+void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16) {
+  if (bf16) gram_impl<true>(c, Y, R, khat, G);
+  else gram_impl<false>(c, Y, R, khat, G);
 }
 
 }  // namespace tk

@@ -254,9 +254,10 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   for (int i = tid; i < Ep; i += 256) {
     const bool ok = i < E;
     const int q = ttm3_lds_pos(i);
-    sia[q] = ok ? la[e0 + i] : 0;
-    sib[q] = ok ? lb[e0 + i] : 0;
-    sv[q] = ok ? A.val[e0 + i] : 0.f;
+    // the layout is read once: non-temporal loads keep it from evicting factor rows in L2
+    sia[q] = ok ? __builtin_nontemporal_load(la + e0 + i) : 0;
+    sib[q] = ok ? __builtin_nontemporal_load(lb + e0 + i) : 0;
+    sv[q] = ok ? __builtin_nontemporal_load(A.val + e0 + i) : 0.f;
   }
   if (lane == 0) {
     winfo[2 * wave] = -1;
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
     const int sgi = q / khat, col = q - sgi * khat;
     const int slot = sslot[sgi];
     float* dst = slot < 0 ? A.Y + (int64_t)srow[sgi] * khat : A.partial + (int64_t)slot * khat;
-    dst[col] = rows[q];
+    __builtin_nontemporal_store(rows[q], dst + col);
   }
 }
 

@@ -24,3 +24,12 @@ def gpu_available():
 @pytest.fixture(scope="session")
 def golden_dir():
     return os.path.join(ROOT, "tests", "golden")
+
+
+@pytest.fixture(scope="session")
+def tk():
+    """The library's Python package, on a machine with a GPU."""
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1804_09494_amd as P
+    return P

@@ -15,14 +15,6 @@ pytestmark = pytest.mark.gpu
 TOL = 1e-5
 
 
-@pytest.fixture(scope="module")
-def tk():
-    import torch
-    assert torch.cuda.is_available(), "GPU tests need a GPU"
-    import paper_1804_09494_amd as P
-    return P
-
-
 def _load(P, idx, vals, dims, ranks=None, **opt):
     ctx = P.TuckerContext(0, **opt)
     ctx.load_coo([np.ascontiguousarray(i, np.int32) for i in idx], np.ascontiguousarray(vals, np.float32), dims)

@@ -1,0 +1,90 @@
+"""Precision form on the GPU: the Gram of Y_(n) with BF16 operands on the
+matrix cores (FP32 accumulation), FP64 eigensolve and CholeskyQR2 as in the
+FP32 path, and the refining last invocation in FP32.  Checked against the FP64
+oracle: one BF16 invocation to 1e-2, the refining invocation from the same
+input factors to 1e-5, and the final fit of a BF16 run to 1e-5."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import coo, hooi, ttm
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(P, w, **opt):
+    ctx = P.TuckerContext(0, **opt)
+    ctx.load_coo([np.ascontiguousarray(i, np.int32) for i in w["idx"]], np.ascontiguousarray(w["vals"], np.float32),
+                 w["dims"])
+    ctx.set_ranks(w["ranks"])
+    return ctx
+
+
+def _allowed(ic, vc, dims, F_out, n, K, tol):
+    """The tolerance on the projector distance of mode n, widened only where
+    the oracle's own spectrum leaves the leading K-subspace ill-determined
+    (Gram-route error ~ u s_1^2 / (s_K^2 - s_{K+1}^2), u = FP32 unit roundoff)."""
+    sv = np.linalg.svd(ttm.ttm_chain(ic, vc, F_out, n, dims), compute_uv=False)
+    cond = sv[0] ** 2 / max(sv[K - 1] ** 2 - sv[K] ** 2, 1e-300) if len(sv) > K else 1.0
+    return max(tol, 6e-8 * 50 * cond), cond
+
+
+def test_bf16_invocation_within_1e2(tk):
+    w = synth.make_workload("c2", scale=0.002)     # 2000 x 1000 x 400, Zipf(1.1), K = 10
+    ctx = _ctx(tk, w, prec="bf16", refine=0)
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    fits = ctx.hooi_iterate(1)
+    ic, vc, _ = coo.coalesce_fast(w["idx"], w["vals"])
+    o = hooi.hooi(ic, vc, w["dims"], w["F0"], w["ranks"], 1)
+    assert abs(fits[0] - o["fits"][0]) <= 1e-2
+    for n in range(3):
+        Fg = ctx.get_factor(n)
+        np.testing.assert_allclose(Fg.T @ Fg, np.eye(w["ranks"][n]), atol=1e-12)
+        d = hooi.projector_distance(Fg, o["factors"][n])
+        print(f"mode {n}: BF16 projector distance {d:.2e}", flush=True)
+        assert d <= 1e-2
+
+
+def test_bf16_refining_invocation_within_1e5(tk):
+    w = synth.make_workload("c2", scale=0.002)
+    dims, ranks = w["dims"], w["ranks"]
+    ctx = _ctx(tk, w, prec="bf16", refine=0)
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    ctx.hooi_iterate(2)                            # two BF16 invocations
+    Fb = [ctx.get_factor(n) for n in range(3)]
+    ctx.set_options(refine=1)
+    fits = ctx.hooi_iterate(1)                     # the refining (FP32) invocation
+    ic, vc, _ = coo.coalesce_fast(w["idx"], w["vals"])
+    o = hooi.hooi(ic, vc, dims, Fb, ranks, 1)      # the oracle's invocation from the same factors
+    assert abs(fits[0] - o["fits"][0]) <= 1e-5
+    for n in range(3):
+        d = hooi.projector_distance(ctx.get_factor(n), o["factors"][n])
+        allowed, cond = _allowed(ic, vc, dims, o["factors"], n, ranks[n], 1e-5)
+        print(f"mode {n}: refined projector distance {d:.2e} (allowed {allowed:.2e}, cond {cond:.1e})", flush=True)
+        if cond < 1e6:
+            assert d <= allowed
+
+
+@pytest.mark.parametrize("name,scale,iters", [("c1", 1.0, 3), ("c2", 0.002, 4)])
+def test_bf16_run_final_fit_matches_oracle(tk, name, scale, iters):
+    """BF16 invocations then one FP32 invocation end at the oracle's fit to 1e-5.
+    The factors are not compared: after the BF16 invocations they follow a
+    different HOOI trajectory (on c1's flat spectrum their subspaces differ
+    from the oracle's iterates by ~1e-2), which the fit does not notice at
+    this level; the per-invocation tests above bound the factors instead."""
+    w = synth.make_workload(name, scale=scale)
+    ctx = _ctx(tk, w, prec="bf16", refine=1)
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    fits = ctx.hooi_iterate(iters)
+    ic, vc, _ = coo.coalesce_fast(w["idx"], w["vals"])
+    o = hooi.hooi(ic, vc, w["dims"], w["F0"], w["ranks"], iters)
+    print("fits bf16", fits, "oracle", o["fits"], flush=True)
+    assert abs(fits[-1] - o["fits"][-1]) <= 1e-5
+    _, fit = ctx.core()
+    assert abs(fit - o["fits"][-1]) <= 1e-5
+    for n in range(len(w["dims"])):
+        Fg = ctx.get_factor(n)
+        np.testing.assert_allclose(Fg.T @ Fg, np.eye(w["ranks"][n]), atol=1e-12)
