@@ -60,7 +60,7 @@ typedef enum {
   TK_ERR_OOM = 3,          /* device allocation failed or the plan exceeds mem_limit_bytes */
   TK_ERR_DEVICE = 4,       /* a HIP runtime call failed */
   TK_ERR_NUMERIC = 5,      /* rank-deficient Y_(n) with completion disabled */
-  TK_ERR_UNSUPPORTED = 6   /* a size outside what this build handles (e.g. m >= 2^32) */
+  TK_ERR_UNSUPPORTED = 6   /* a size outside what this build handles (e.g. nnz >= 2^31) */
 } tk_status;
 
 typedef enum { TK_MEM_HOST = 0, TK_MEM_DEVICE = 1 } tk_mem;
@@ -68,7 +68,10 @@ typedef enum { TK_FP32 = 0, TK_BF16 = 1 } tk_prec;
 typedef enum { TK_SWEEP_GAUSS_SEIDEL = 0, TK_SWEEP_JACOBI = 1 } tk_sweep;
 
 typedef struct {
-  int32_t prec;                   /* tk_prec of the Kronecker tiles and the Gram (default TK_FP32) */
+  int32_t prec;                   /* tk_prec of the Kronecker tiles and the Gram (default TK_FP32).
+                                     TK_BF16: factor rows gathered from BF16 copies and Gram operands
+                                     rounded to BF16, products accumulated in FP32; the eigensolve,
+                                     CholeskyQR2, core and fit stay FP64 */
   int32_t sweep;                  /* tk_sweep (default Gauss-Seidel: mode n uses factors refined earlier in the invocation) */
   int64_t wg_nnz_target;          /* target elements per bin (default 1024) */
   int32_t lds_rows_cap;           /* max slices per bin; 0 = from the LDS budget */
@@ -107,7 +110,8 @@ tk_status tk_set_stream(tk_ctx* ctx, void* hip_stream);
 /* ---- tensor (Section 3: the element list E) --------------------------------------------------- */
 
 /* Load a sparse tensor in COO form.  N in [2, 8]; dims[n] in [1, 2^31 - 1];
- * nnz in [0, 2^32 - 2]; idx[n] points to nnz int32 coordinates of mode n
+ * nnz in [0, 2^31 - 1] (larger lists give TK_ERR_UNSUPPORTED); idx[n] points
+ * to nnz int32 coordinates of mode n
  * (0-based, < dims[n]); vals to nnz finite floats.  `mem` applies to idx[n]
  * and vals (the arrays of pointers themselves are host memory).
  * Repeated coordinates are merged by summing their values in FP64 (input
@@ -155,10 +159,14 @@ tk_status tk_get_factor(tk_ctx* ctx, int n, double* F, tk_mem mem);
 tk_status tk_ttm_shape(tk_ctx* ctx, int n, int64_t* R_n, int64_t* Khat_n);
 /* TTM-chain along mode n with the current factors (eq. 1): Y gets the rows of
  * the nonempty slices in ascending slice id (R_n x Khat_n, row-major FP32);
- * row_slice (may be NULL) gets their slice ids (int32). */
+ * row_slice (may be NULL) gets their slice ids (int32).  With prec = TK_BF16
+ * the factor rows come from the BF16 copies (where the matrix-core kernel runs). */
 tk_status tk_ttm_chain(tk_ctx* ctx, int n, float* Y, int32_t* row_slice, tk_mem mem);
 /* Run `iters` HOOI invocations (Section 2.2): for each mode in turn, TTM-chain,
- * Gram, FP64 eigensolve, U = Y V S^-1, CholeskyQR2, new factor.
+ * Gram, FP64 eigensolve, U = Y V S^-1, CholeskyQR2, new factor.  The
+ * eigensolve is dense for Khat up to about 100 and a block Krylov method
+ * (warm-started from the mode's previous eigenvectors) for Khat >= 192.
+ * With prec = TK_BF16 and refine = 1 the last invocation runs in FP32.
  * fit_per_iter (host, may be NULL) gets 1 - sqrt(max(0, ||T||^2 - ||G||^2))/||T||
  * after each invocation. */
 tk_status tk_hooi_iterate(tk_ctx* ctx, int iters, double* fit_per_iter);

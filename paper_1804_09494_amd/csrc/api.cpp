@@ -20,7 +20,7 @@
 namespace tk {
 
 void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16);
-void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK);
+void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode);
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
                  int* flag_dev, bool check_flag);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
@@ -133,7 +133,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
         for (int j = 0; j < N; ++j)
           if (j != n) std::swap(c->F32[j], F32_in[j]);
       } else {
-        ttm_chain(c, n, Y, false);
+        ttm_chain(c, n, Y, low);   // precision form: BF16 factor rows in the Kronecker tiles
       }
       c->ev_ttm[0] = c->ev_ttm[1] = nullptr;
       if (c->m == 0) {  // no launch: give the bracket a zero-length interval
@@ -145,7 +145,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       hipEvent_t t2 = mark("gram", t1);
       double* lam_k = c->eig_val.as<double>();
       double* VK = lam_k + 64;
-      eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK);
+      eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK, n);
       hipEvent_t t3 = mark("eig", t2);
       form_factor(c, n, Y, pl.L_nz, khat, lam_k, VK, c->flag.as<int>(), true);
       mark("factor", t3);
@@ -441,10 +441,10 @@ tk_status tk_ttm_chain(tk_ctx* c, int n, float* Y, int32_t* row_slice, tk_mem me
     const size_t ny = (size_t)pl.L_nz * (size_t)pl.khat;
     if (Y) {
       if (mem == TK_MEM_DEVICE) {
-        ttm_chain(c, n, Y, false);
+        ttm_chain(c, n, Y, c->opt.prec == TK_BF16);
       } else {
         ensure(c, c->Y, sizeof(float) * std::max<size_t>(ny, 1));
-        ttm_chain(c, n, c->Y.as<float>(), false);
+        ttm_chain(c, n, c->Y.as<float>(), c->opt.prec == TK_BF16);
         copy_out(c, Y, c->Y.as<float>(), ny, mem);
         c->sync();
       }

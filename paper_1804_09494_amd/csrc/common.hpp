@@ -170,6 +170,9 @@ struct Ctx {
   Buf eig_val;            // double[Khat]
   Buf U64;                // double[R_n x K_n]
   Buf small64;            // double scratch for K x K matrices, reductions
+  Buf kr_work;            // block-Krylov eigensolver workspace (large Khat)
+  Buf eig_warm[8];        // last eigenvectors of each mode's Gram (Krylov warm start)
+  int eig_warm_k[8] = {0};
   Buf core64;             // double[prod K]
   Buf flag;               // int32 flags
 
@@ -227,6 +230,21 @@ inline void copy_in(Ctx* c, T* dst, const T* src, size_t n, tk_mem mem) {
 }
 
 // Launch-size helper for grid-stride kernels.
+// Buffer-resource loads: a byte offset at or beyond the resource's size returns
+// zero without touching memory, so edge tiles load with a computed offset and no
+// branch (a predicated global load becomes a branch and a full wait).
+constexpr uint32_t BUF_OOB = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ float buf_f32(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ __forceinline__ double buf_f64(__amdgpu_buffer_rsrc_t r, uint32_t off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
 inline unsigned grid_for(int64_t n, int block, int64_t cap = 65536) {
   int64_t g = ceil_div(n > 0 ? n : 1, block);
   return (unsigned)(g < cap ? g : cap);
@@ -256,7 +274,7 @@ int ttm_tile_width(int N, const int32_t* K, int n);
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y);
+             const float* lay_val, int64_t m, float* Y, const uint16_t* const* H16 = nullptr);
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16);
 void hooi_iterate(Ctx* c, int iters, double* fits);
 void core_and_fit(Ctx* c, double* core_dev, double* fit);

@@ -16,10 +16,10 @@ constexpr int CORE_TILE = 64;
 __global__ __launch_bounds__(256) void k_core_part(const float* __restrict__ Y, int64_t R, int khat,
                                                    const double* __restrict__ F, int K,
                                                    const int32_t* __restrict__ row_slice, int rows_per_wg,
-                                                   double* __restrict__ part) {
+                                                   int tile, double* __restrict__ part) {
   extern __shared__ double shc[];
-  double* ft = shc;                                      // CORE_TILE x K
-  float* yt = reinterpret_cast<float*>(ft + CORE_TILE * K);  // CORE_TILE x khat
+  double* ft = shc;                                      // tile x K
+  float* yt = reinterpret_cast<float*>(ft + tile * K);   // tile x khat
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
   const int64_t r1 = min<int64_t>(r0 + rows_per_wg, R);
   const int nent = K * khat;
@@ -28,8 +28,8 @@ __global__ __launch_bounds__(256) void k_core_part(const float* __restrict__ Y, 
     double acc[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    for (int64_t t0 = r0; t0 < r1; t0 += CORE_TILE) {
-      const int nr = (int)min<int64_t>(CORE_TILE, r1 - t0);
+    for (int64_t t0 = r0; t0 < r1; t0 += tile) {
+      const int nr = (int)min<int64_t>(tile, r1 - t0);
       __syncthreads();
       for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
         const int r = i / K, k = i - r * K;
@@ -97,10 +97,13 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   ensure(c, c->gram_part, sizeof(double) * (size_t)nwg * K * khat);
   double* part = c->gram_part.as<double>();
   if (R > 0) {
-    size_t lds = sizeof(double) * CORE_TILE * K + sizeof(float) * CORE_TILE * (size_t)khat;
-    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "core: Khat too large for LDS");
+    // rows staged per pass: CORE_TILE, fewer when Khat is wide
+    const int64_t per_row = sizeof(double) * K + sizeof(float) * (int64_t)khat;
+    const int tile = (int)std::min<int64_t>(CORE_TILE, ((int64_t)c->lds_per_block - 1024) / per_row);
+    TK_REQUIRE(tile >= 1, TK_ERR_UNSUPPORTED, "core: Khat too large for LDS");
+    const size_t lds = (size_t)per_row * tile;
     hipLaunchKernelGGL(k_core_part, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
-                       pl.row_slice.as<int32_t>(), rows_per_wg, part);
+                       pl.row_slice.as<int32_t>(), rows_per_wg, tile, part);
     TK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_core_reduce, dim3(grid_for((int64_t)K * khat, 256, 1024)), dim3(256), 0, c->stream, part,
                        nwg, K, khat, core);

@@ -67,6 +67,38 @@ __device__ __forceinline__ double half_sum(double x) {   // over each 32-lane ha
   return x;
 }
 
+// Data-parallel-primitive move of a double (both 32-bit halves with the same control).
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double x) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffLL), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Sum over each row of 16 lanes, in every lane of the row: swap neighbours,
+// swap pairs (quad permutes), then mirror within 8 and within 16 lanes.
+__device__ __forceinline__ double row16_sum(double x) {
+  x += dpp_mov<0xB1>(x);    // quad_perm [1,0,3,2]
+  x += dpp_mov<0x4E>(x);    // quad_perm [2,3,0,1]
+  x += dpp_mov<0x141>(x);   // row_half_mirror
+  x += dpp_mov<0x140>(x);   // row_mirror
+  return x;
+}
+
+__device__ __forceinline__ double lane_val(double x, int l) {   // x of lane l (l wave-uniform)
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Wave sum as a wave-uniform value (same order in every wave).
+__device__ __forceinline__ double wave_sum_u(double x) {
+  x = row16_sum(x);
+  return (lane_val(x, 0) + lane_val(x, 16)) + (lane_val(x, 32) + lane_val(x, 48));
+}
+
 // Sum over the workgroup: wave sums, then every thread adds the wave partials in order.
 __device__ __forceinline__ double block_sum(double x, double* red) {
   x = wave_sum(x);
@@ -427,12 +459,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_topk(const double* __restr
 // (double-buffered by step parity), so each step has a single barrier.
 constexpr int SM_N = 128;
 
-__device__ __forceinline__ double rl(double x, int l) {   // x of lane l (l wave-uniform)
-  const long long b = __double_as_longlong(x);
-  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
-  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
-}
+__device__ __forceinline__ double rl(double x, int l) { return lane_val(x, l); }
 
 // value at column J of a two-register row (J wave-uniform)
 __device__ __forceinline__ double col_of(const double (&x)[2], int J) { return rl(J < 64 ? x[0] : x[1], J & 63); }
@@ -471,7 +498,7 @@ __device__ __forceinline__ void reflector(const double (&x)[2], int j0, int n, d
     const int J = lane + 64 * c;
     if (J > j0 && J < n) s += x[c] * x[c];
   }
-  const double xn2 = wave_sum(s);
+  const double xn2 = wave_sum_u(s);
   const double alpha = col_of(x, j0);
   if (xn2 == 0.0) {
     beta = alpha;
@@ -578,7 +605,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
         w[c] = pc;
         pv += pc * v[c];
       }
-      const double kc = 0.5 * t * wave_sum(pv);
+      const double kc = 0.5 * t * wave_sum_u(pv);
 #pragma unroll
       for (int c = 0; c < 2; ++c) w[c] -= kc * v[c];
       if (tid == 0) {
@@ -602,16 +629,35 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
       if (next) reflector(nr, k + 2, n, bn, tn, sn, vn);
       // rows k+2.. : update with reflector k, accumulate A v_{k+1}
       double acc[2] = {0.0, 0.0};
-      for (int I = k + 2 + wave; I < n; I += EIG_WAVES) {
-        const double vI = col_of(v, I), wI = col_of(w, I), vnI = col_of(vn, I);
-        double* row = A + I * S;
+      bool cok[2];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-          const int J = lane + 64 * c;
-          if (J >= k + 2 && J < n) {
-            const double a = row[J] - (vI * w[c] + wI * v[c]);
-            row[J] = a;
-            acc[c] += a * vnI;
+      for (int c = 0; c < 2; ++c) {
+        const int J = lane + 64 * c;
+        cok[c] = J >= k + 2 && J < n;
+      }
+      // four rows per iteration: all loads are issued before the first store
+      for (int I0 = k + 2 + wave; I0 < n; I0 += 4 * EIG_WAVES) {
+        double a[4][2];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int I = I0 + u * EIG_WAVES;
+          const int Ic = I < n ? I : n - 1;
+#pragma unroll
+          for (int c = 0; c < 2; ++c) a[u][c] = A[Ic * S + (cok[c] ? lane + 64 * c : n - 1)];   // unconditional load
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int I = I0 + u * EIG_WAVES;
+          if (I < n) {
+            const double vI = col_of(v, I), wI = col_of(w, I), vnI = col_of(vn, I);
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+              if (cok[c]) {
+                const double x = a[u][c] - (vI * w[c] + wI * v[c]);
+                A[I * S + lane + 64 * c] = x;
+                acc[c] += x * vnI;
+              }
+            }
           }
         }
       }
@@ -645,7 +691,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
         w[c] = pc;
         pv += pc * vn[c];
       }
-      const double kc = 0.5 * tn * wave_sum(pv);
+      const double kc = 0.5 * tn * wave_sum_u(pv);
 #pragma unroll
       for (int c = 0; c < 2; ++c) {
         w[c] -= kc * vn[c];
@@ -723,9 +769,17 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     double* ml = u2 + n;
     double* pv = ml + n;
     double* z = Z + (int64_t)j * n;
+    // operands of step i+1 are loaded while step i computes (one lane per
+    // vector: nothing else hides the LDS latency)
     double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
+    double c_n = e[0], nd_n = n > 1 ? d[1] : 0.0, ns_n = n > 2 ? e[1] : 0.0;
     for (int i = 0; i < n - 1; ++i) {
-      const double c = e[i], nd = d[i + 1] - lj, ns = i + 1 < n - 1 ? e[i + 1] : 0.0;
+      const double c = c_n, nd = nd_n - lj, ns = i + 1 < n - 1 ? ns_n : 0.0;
+      if (i + 1 < n - 1) {
+        c_n = e[i + 1];
+        nd_n = d[i + 2];
+        ns_n = i + 2 < n - 1 ? e[i + 2] : 0.0;
+      }
       if (fabs(c) > fabs(a0)) {
         const double mlt = a0 / c;
         ui[i] = 1.0 / c; u1[i] = nd; u2[i] = ns; ml[i] = mlt; pv[i] = 1.0;
@@ -745,20 +799,34 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
     for (int it = 0; it < 2; ++it) {
       double cur = z[0];
+      double nx_n = n > 1 ? z[1] : 0.0, ml_n = ml[0], pv_n = pv[0];
       for (int i = 0; i < n - 1; ++i) {
-        const double nx = z[i + 1];
-        if (pv[i] != 0.0) {
+        const double nx = nx_n, mi = ml_n, pi = pv_n;
+        if (i + 2 < n) {
+          nx_n = z[i + 2];
+          ml_n = ml[i + 1];
+          pv_n = pv[i + 1];
+        }
+        if (pi != 0.0) {
           z[i] = nx;
-          cur = cur - ml[i] * nx;
+          cur = cur - mi * nx;
         } else {
           z[i] = cur;
-          cur = nx - ml[i] * cur;
+          cur = nx - mi * cur;
         }
       }
       z[n - 1] = cur;
       double z1 = 0.0, z2 = 0.0, nrm = 0.0;
+      double zi_n = z[n - 1], u1_n = u1[n - 1], u2_n = u2[n - 1], ui_n = ui[n - 1];
       for (int i = n - 1; i >= 0; --i) {
-        const double s = (z[i] - u1[i] * z1 - u2[i] * z2) * ui[i];
+        const double zi = zi_n, a = u1_n, b = u2_n, r = ui_n;
+        if (i > 0) {
+          zi_n = z[i - 1];
+          u1_n = u1[i - 1];
+          u2_n = u2[i - 1];
+          ui_n = ui[i - 1];
+        }
+        const double s = (zi - a * z1 - b * z2) * r;
         z[i] = s;
         z2 = z1;
         z1 = s;
@@ -792,10 +860,14 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
           const int i = hl + 32 * c;
-          vv[c] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? rowk[i] * sc : 0.0);
+          const double x = rowk[i < n ? i : n - 1];
+          vv[c] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? x * sc : 0.0);
           s += vv[c] * z[c];
         }
-        s = t * half_sum(s);
+        // sum over this half-wave: rows of 16 lanes, then the half's two rows
+        s = row16_sum(s);
+        const double s0 = lane_val(s, 0) + lane_val(s, 16), s1 = lane_val(s, 32) + lane_val(s, 48);
+        s = t * (half ? s1 : s0);
 #pragma unroll
         for (int c = 0; c < 4; ++c) z[c] -= s * vv[c];
       }
@@ -808,7 +880,11 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     }
   }
   __syncthreads();
-  orth_rows(Z, K, n, gm, lu, red);
+  // inverse iteration leaves vectors of eigenvalues more than 1e-3 ||T|| apart
+  // orthogonal to working accuracy; closer ones are orthonormalised together
+  bool cluster = false;
+  for (int j = 1; j < K; ++j) cluster |= fabs(lam[j - 1] - lam[j]) < 1e-3 * tnorm;
+  if (cluster) orth_rows(Z, K, n, gm, lu, red);
   for (int t = tid; t < n * K; t += EIG_THREADS) {
     const int i = t / K, j = t - i * K;
     VK[(int64_t)i * Kout + j] = Z[(int64_t)j * n + i];
@@ -816,18 +892,28 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
   for (int j = tid; j < K; j += EIG_THREADS) lam_out[j] = lam[j];
 }
 
+void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* lam_k, double* VK, int mode);
+
+constexpr int KRYLOV_MIN_N = 192;   // above this, and for K <= 16, the block-Krylov solver
+
 // Leading K eigenpairs of G (n0 x n0, FP64): lam_k[0..K) descending and VK (n0 x K).
-// Eigenpairs beyond n0 (K > n0) are reported as zero eigenvalues.
-void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK) {
+// Eigenpairs beyond n0 (K > n0) are reported as zero eigenvalues.  mode >= 0
+// lets the Krylov solver start from that mode's previous eigenvectors.
+void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode) {
   const int Ke = K < n0 ? K : n0;
   TK_REQUIRE(Ke <= 32, TK_ERR_UNSUPPORTED, "eigensolve: more than 32 eigenpairs");
-  const EigLayout L = eig_layout(n0, Ke);
   const size_t lim = c->lds_per_block;
+  const SmallLayout SL = small_layout(n0, Ke);
+  const bool small = n0 <= SM_N && Ke <= 16 && (size_t)SL.total * 8 <= lim;
+  if (!small && n0 >= KRYLOV_MIN_N && Ke <= 16) {
+    eig_topk_krylov(c, G, n0, Ke, K, lam_k, VK, mode);
+    return;
+  }
+  const EigLayout L = eig_layout(n0, Ke);
   ensure(c, c->work, sizeof(double) * (size_t)(L.total + 16));
   if (K > Ke) TK_HIP(hipMemsetAsync(lam_k, 0, sizeof(double) * K, c->stream));
   double* ws = c->work.as<double>();
-  const SmallLayout SL = small_layout(n0, Ke);
-  if (n0 <= SM_N && Ke <= 16 && (size_t)SL.total * 8 <= lim) {
+  if (small) {
     hipLaunchKernelGGL(k_syev_small, dim3(1), dim3(EIG_THREADS), (size_t)SL.total * 8, c->stream, G, n0, Ke, K, SL,
                        lam_k, VK);
   } else if ((size_t)L.total * 8 <= lim) {

@@ -26,6 +26,8 @@ namespace tk {
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
+constexpr int GRAM_BATCH = 4;   // FP32 Gram: 4-row steps whose loads are issued together
+
 // Tiles (bi, bj) of the macro pair: bi in [I0, I0+NBA), bj in [J0, J0+NBB);
 // DIAG = the pair is on the diagonal and only bi <= bj is computed.
 template <int NBA, int NBB, bool DIAG>
@@ -72,46 +74,49 @@ __global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64
   for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
   const int lr = lane >> 4, lc = lane & 15;
   // software pipeline: the next 4-row step is loaded while this one's MFMAs run
-  // loads are unconditional (addresses clamped into Y, values selected to
-  // zero): predicated loads would become one branch each
-  auto load = [&](int64_t r, float (&xa)[NBA], float (&xb)[NBB]) {
-    const int64_t row = r + lr;
-    const bool rok = row < r1;
-    const float* yr = Y + (rok ? row : r1 - 1) * khat;
+  // buffer loads over this workgroup's rows: a row past r1 lies beyond the
+  // resource and a column past khat carries an out-of-range offset, so both
+  // read as zero with no condition on the load
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Y + r0 * khat, (uint32_t)((r1 - r0) * khat * 4));
+  uint32_t ca[NBA], cb[NBB];
 #pragma unroll
-    for (int b = 0; b < NBA; ++b) {
-      const int col = (I0 + b) * 16 + lc;
-      const float v = yr[col < khat ? col : khat - 1];
-      xa[b] = (rok && col < khat) ? v : 0.f;
-    }
+  for (int b = 0; b < NBA; ++b) {
+    const int col = (I0 + b) * 16 + lc;
+    ca[b] = col < khat ? 4u * col : BUF_OOB;
+  }
+#pragma unroll
+  for (int b = 0; b < NBB; ++b) {
+    const int col = (J0 + b) * 16 + lc;
+    cb[b] = col < khat ? 4u * col : BUF_OOB;
+  }
+  auto load = [&](int64_t r, float (&xa)[NBA], float (&xb)[NBB]) {
+    const uint32_t rb = 4u * (uint32_t)((r + lr - r0) * khat);
+#pragma unroll
+    for (int b = 0; b < NBA; ++b) xa[b] = buf_f32(rs, rb + ca[b]);
     if constexpr (DIAG) {
 #pragma unroll
       for (int b = 0; b < NBB; ++b) xb[b] = xa[b];
     } else {
 #pragma unroll
-      for (int b = 0; b < NBB; ++b) {
-        const int col = (J0 + b) * 16 + lc;
-        const float v = yr[col < khat ? col : khat - 1];
-        xb[b] = (rok && col < khat) ? v : 0.f;
-      }
+      for (int b = 0; b < NBB; ++b) xb[b] = buf_f32(rs, rb + cb[b]);
     }
   };
-  float xa[NBA], xb[NBB];
-  int64_t r = r0 + 4 * wave;
-  if (r < r1) load(r, xa, xb);
-  for (; r < r1; r += 16) {
-    float na[NBA], nb[NBB];
-    if (r + 16 < r1) load(r + 16, na, nb);
-    int t = 0;
+  // batches of GRAM_BATCH steps: every load of a batch is issued first, then
+  // each step waits only for its own loads; no register value crosses an
+  // iteration (a loop-carried load forces a full wait); steps past r1 read zeros
+  for (int64_t r = r0 + 4 * wave; r < r1; r += 16 * GRAM_BATCH) {
+    float xa[GRAM_BATCH][NBA], xb[GRAM_BATCH][NBB];
 #pragma unroll
-    for (int a = 0; a < NBA; ++a)
+    for (int d = 0; d < GRAM_BATCH; ++d) load(r + 16 * d, xa[d], xb[d]);
 #pragma unroll
-      for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[a], xb[bj], acc[t], 0, 0, 0);
+    for (int d = 0; d < GRAM_BATCH; ++d) {
+      int t = 0;
 #pragma unroll
-    for (int b = 0; b < NBA; ++b) xa[b] = na[b];
+      for (int a = 0; a < NBA; ++a)
 #pragma unroll
-    for (int b = 0; b < NBB; ++b) xb[b] = nb[b];
+        for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[d][a], xb[d][bj], acc[t], 0, 0, 0);
+    }
   }
   // combine the four waves in fixed order
   for (int w = 0; w < 4; ++w) {
@@ -154,44 +159,40 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const float* __restrict__ Y, 
 #pragma unroll
   for (int b = 0; b < NL; ++b) cols[b] = (b < NBA ? (I0 + b) : (J0 + b - NBA)) * 16 + lc;
   // FP32 values of the next step stay in flight while this step's MFMAs run
-  int ccol[NL];
-  bool cok[NL];
+  // buffer loads over this workgroup's rows: rows past r1 lie beyond the
+  // resource, columns past khat carry an out-of-range offset (both read zero)
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Y + r0 * khat, (uint32_t)((r1 - r0) * khat * 4));
+  uint32_t coff[NL];
 #pragma unroll
-  for (int b = 0; b < NL; ++b) {
-    cok[b] = cols[b] < khat;
-    ccol[b] = cok[b] ? cols[b] : khat - 1;
-  }
-  // unconditional loads (clamped addresses, values selected to zero)
+  for (int b = 0; b < NL; ++b) coff[b] = cols[b] < khat ? 4u * cols[b] : BUF_OOB;
   auto load = [&](int64_t r, float (&f)[NL][8]) {
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
-      const int64_t row = r + 8 * lr + q;
-      const bool rok = row < r1;
-      const float* yr = Y + (rok ? row : r1 - 1) * khat;
+      const uint32_t rb = 4u * (uint32_t)((r + 8 * lr + q - r0) * khat);
 #pragma unroll
-      for (int b = 0; b < NL; ++b) {
-        const float v = yr[ccol[b]];
-        f[b][q] = (rok && cok[b]) ? v : 0.f;
-      }
+      for (int b = 0; b < NL; ++b) f[b][q] = buf_f32(rs, rb + coff[b]);
     }
   };
-  float f[NL][8];
-  int64_t r = r0 + 32 * wave;
-  if (r < r1) load(r, f);
-  for (; r < r1; r += 128) {
-    bf16x8 x[NL];
+  // batches of two 32-row steps: both steps' loads issued first, no register
+  // value crossing an iteration; steps past r1 read zeros
+  for (int64_t r = r0 + 32 * wave; r < r1; r += 256) {
+    float f[2][NL][8];
+    load(r, f[0]);
+    load(r + 128, f[1]);
 #pragma unroll
-    for (int b = 0; b < NL; ++b)
+    for (int d = 0; d < 2; ++d) {
+      bf16x8 x[NL];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) x[b][q] = (__bf16)f[b][q];
-    if (r + 128 < r1) load(r + 128, f);
-    // tiles in TileSet order, with compile-time operand indices
-    int t = 0;
+      for (int b = 0; b < NL; ++b)
 #pragma unroll
-    for (int a = 0; a < NBA; ++a)
+        for (int q = 0; q < 8; ++q) x[b][q] = (__bf16)f[d][b][q];
+      int t = 0;
 #pragma unroll
-      for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[a], x[DIAG ? bj : NBA + bj], acc[t], 0, 0, 0);
+      for (int a = 0; a < NBA; ++a)
+#pragma unroll
+        for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[a], x[DIAG ? bj : NBA + bj], acc[t], 0, 0, 0);
+    }
   }
   for (int w = 0; w < 4; ++w) {
     if (wave == w) {
@@ -257,7 +258,10 @@ static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, in
   if (npairs == 0) return;
   const int64_t target_wgs = std::max<int64_t>(1, 1024 / npairs);
   const int64_t gran = BF16 ? 128 : 16;   // rows per workgroup-wide step
-  const int rows_per_wg = (int)std::max<int64_t>(BF16 ? 128 : 64, ceil_div(ceil_div(R, target_wgs), gran) * gran);
+  int64_t rpw = std::max<int64_t>(BF16 ? 128 : 64, ceil_div(ceil_div(R, target_wgs), gran) * gran);
+  // a workgroup's rows form one buffer resource: keep them below 2^31 bytes
+  rpw = std::min<int64_t>(rpw, std::max<int64_t>(gran, ((int64_t)0x7fff0000 / (4 * (int64_t)khat)) / gran * gran));
+  const int rows_per_wg = (int)rpw;
   const int nchunks = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
   const int group = 32;
   const int ngroups = (nchunks + group - 1) / group;

@@ -30,6 +30,7 @@ struct TtmArgs {
   const int32_t* lay[7];    // other modes' coordinates in layout order (ascending mode)
   const float* val;
   const float* F[7];        // FP32 factor copies of the other modes
+  const uint16_t* H[7];     // BF16 copies (row stride 16) for the precision form, or null
   int fstride[7];
   int Kj[7];
   int div[7];               // prod of Kj[1..j-1] (digit divisors of the slow index)
@@ -223,6 +224,9 @@ __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlan
 // position of padded element i inside the bin's LDS copy (4x4 transpose inside each block of 16)
 __device__ __forceinline__ int ttm3_lds_pos(int i) { return (i & ~15) | ((i & 3) << 2) | ((i >> 2) & 3); }
 
+// BF: the factor rows are gathered from the BF16 copies (32-byte rows) and
+// widened to FP32 in registers; the contraction and the accumulation stay FP32.
+template <bool BF>
 __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.KA, kb = A.KW;
@@ -272,6 +276,8 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   const bool bok = cix < kb;
   const float* __restrict__ Fa = A.F[0];
   const float* __restrict__ Fb = A.F[1];
+  const uint16_t* __restrict__ Ha = A.H[0];
+  const uint16_t* __restrict__ Hb = A.H[1];
   if (cs < ce) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -315,8 +321,13 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
       // predicate (a predicated load would make the in-flight count path dependent)
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
-        b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
+        if (BF) {
+          x[u] = vv[u] * __uint_as_float((uint32_t)Ha[(uint32_t)(ia[u] * 16 + cix)] << 16);
+          b[u] = __uint_as_float((uint32_t)Hb[(uint32_t)(ib[u] * 16 + cix)] << 16);
+        } else {
+          x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
+          b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
+        }
       }
     };
     auto consume = [&](int g, const float (&x)[4], const float (&b)[4]) {
@@ -469,7 +480,7 @@ static void launch_ttm(Ctx* c, const TtmArgs& a, const ModePlan& pl, int ntiles,
 // TTM-chain of the elements of plan `pl` along mode n with FP32 factor copies
 // F32[j] (row stride kp[j]) of every mode j != n; values are the plan's layout values.
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y) {
+             const float* lay_val, int64_t m, float* Y, const uint16_t* const* H16) {
   TtmShape s = ttm_shape(N, K, n);
   TK_REQUIRE(s.KA <= 32, TK_ERR_UNSUPPORTED, "rank of the first remaining mode above 32");
   TtmArgs a{};
@@ -483,6 +494,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     if (j == n) continue;
     a.lay[no] = pl.lay_idx[no].as<int32_t>();
     a.F[no] = F32[j];
+    a.H[no] = H16 ? H16[j] : nullptr;
     a.fstride[no] = kp[j];
     a.Kj[no] = K[j];
     if (no >= 1) { a.div[no] = prod; prod *= K[j]; }
@@ -510,7 +522,10 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * 8 * TTM3_SLOT +
                        sizeof(int) * 8 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
-    hipLaunchKernelGGL(k_ttm3_mfma, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+    if (H16)
+      hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+    else
+      hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
     TK_CHECK_LAUNCH();
   } else if (s.exact) {
     if (s.mode == 2 && s.KA == 10) launch_ttm<10, 10, 2, true>(c, a, pl, s.ntiles, tw);
@@ -539,11 +554,18 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
 }
 
+// bf16: gather the BF16 factor copies (precision form); taken only where the
+// matrix-core kernel runs and every other factor's BF16 row stride is 16.
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16) {
-  (void)bf16;
   const float* F[8];
-  for (int j = 0; j < c->N; ++j) F[j] = c->F32[j].as<float>();
-  ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y);
+  const uint16_t* H[8];
+  bool bf_ok = bf16 && ttm_uses_mfma(c->N, c->K, n, c->kp32);
+  for (int j = 0; j < c->N; ++j) {
+    F[j] = c->F32[j].as<float>();
+    H[j] = c->F16[j].as<uint16_t>();
+    if (j != n && c->kp16[j] != 16) bf_ok = false;
+  }
+  ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y, bf_ok ? H : nullptr);
 }
 
 }  // namespace tk

@@ -232,6 +232,25 @@ def test_hooi_zipf_small_c2_shape(tk):
     _hooi_compare(tk, w, 2)
 
 
+def _wide_workload(dims, nnz, zipf, ranks, seed):
+    idx, vals = synth.make_tensor(dims, nnz, "zipf", zipf, "lognormal", seed=seed)
+    return {"dims": dims, "ranks": ranks, "idx": idx, "vals": vals,
+            "F0": synth.orthonormal_init(seed + 7690, dims, ranks)}
+
+
+def test_hooi_wide_khat_block_krylov(tk):
+    """Khat = 216 (4 modes, ranks 6): the eigensolve takes the block-Krylov path."""
+    w = _wide_workload((300, 200, 120, 60), 40_000, (0.9, 1.1, 1.3, 0.7), (6, 6, 6, 6), 41)
+    _hooi_compare(tk, w, 2)
+
+
+def test_hooi_khat_1000_precision_form_shape(tk):
+    """The precision form's shape at small scale: 4 modes, ranks 10 (Y_(n) has
+    1000 columns), Zipf 0.9/1.1/1.3/0.7; FP32 path against the oracle."""
+    w = _wide_workload((400, 300, 200, 60), 60_000, (0.9, 1.1, 1.3, 0.7), (10, 10, 10, 10), 42)
+    _hooi_compare(tk, w, 2)
+
+
 def test_hooi_fit_non_decreasing_and_timings(tk):
     w = synth.make_workload("c2", scale=0.001)
     ctx = _load(tk, w["idx"], w["vals"], w["dims"], w["ranks"])
