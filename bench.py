@@ -180,6 +180,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--scale", type=float, default=1.0)
+    ap.add_argument("--share", type=int, default=1, help="one GPU's share of the workload's draws (dims kept)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profile", metavar="DIR")
     args = ap.parse_args()
@@ -197,7 +198,7 @@ def main():
 
     torch.cuda.set_device(0)
     t = time.perf_counter()
-    w = synth.make_workload(args.workload, scale=args.scale)
+    w = synth.make_workload(args.workload, scale=args.scale, share=args.share)
     gen_s = time.perf_counter() - t
     dims, ranks = w["dims"], w["ranks"]
     N = len(dims)
@@ -249,7 +250,10 @@ def main():
     shapes = [ctx.ttm_shape(n) for n in range(N)]
     B = [algorithmic_bytes(m, N, shapes[n][0], shapes[n][1], dims, ranks, n) for n in range(N)]
     achieved = sum(B) / (sum(kern_ms) * 1e-3) / 1e9
-    traffic = committed_traffic()
+    mfma_path = N == 3 and all(ranks[j] <= 16 for j in range(N))
+    # the committed counter summary is of this kernel on c2 as a whole
+    traffic = committed_traffic() if (args.workload == "c2" and args.share == 1 and args.scale == 1.0
+                                      and mfma_path) else None
     stats = [ctx.partition_stats(n) for n in range(N)]
     print(f"# fits fp32 {fits}", file=sys.stderr, flush=True)
     print(f"# fits bf16 {bf_fits}", file=sys.stderr, flush=True)
@@ -274,7 +278,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}: {N}-mode {'x'.join(str(d) for d in dims)}, "
+        "config": {"workload": f"{args.workload}{'/' + str(args.share) if args.share > 1 else ''}: "
+                               f"{N}-mode {'x'.join(str(d) for d in dims)}, "
                                f"{len(w['vals'])} Zipf-drawn nonzeros ({m} after merging), ranks "
                                f"{'x'.join(str(k) for k in ranks)}, one HOOI invocation per step",
                    "m_coalesced": m, "ranks": list(ranks)},
@@ -291,7 +296,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(float(np.mean(traffic))) if traffic else None,
                      "traffic_bytes_per_mode": traffic,
-                     "kernel": "k_ttm3_mfma (TTM-chain)",
+                     "kernel": "k_ttm3_mfma (TTM-chain)" if mfma_path else "k_ttm (TTM-chain, vector ALU)",
                      "bytes_per_launch": [int(b) for b in B]},
         "device_copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,

@@ -68,10 +68,10 @@ typedef enum { TK_FP32 = 0, TK_BF16 = 1 } tk_prec;
 typedef enum { TK_SWEEP_GAUSS_SEIDEL = 0, TK_SWEEP_JACOBI = 1 } tk_sweep;
 
 typedef struct {
-  int32_t prec;                   /* tk_prec of the Kronecker tiles and the Gram (default TK_FP32).
-                                     TK_BF16: factor rows gathered from BF16 copies and Gram operands
-                                     rounded to BF16, products accumulated in FP32; the eigensolve,
-                                     CholeskyQR2, core and fit stay FP64 */
+  int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16: in HOOI invocations the Gram
+                                     operands are rounded to BF16 (FP32 accumulation); tk_ttm_chain
+                                     gathers BF16 factor rows.  The eigensolve, CholeskyQR2, core and
+                                     fit stay FP64 */
   int32_t sweep;                  /* tk_sweep (default Gauss-Seidel: mode n uses factors refined earlier in the invocation) */
   int64_t wg_nnz_target;          /* target elements per bin (default 1024) */
   int32_t lds_rows_cap;           /* max slices per bin; 0 = from the LDS budget */

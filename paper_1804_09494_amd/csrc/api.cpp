@@ -133,7 +133,11 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
         for (int j = 0; j < N; ++j)
           if (j != n) std::swap(c->F32[j], F32_in[j]);
       } else {
-        ttm_chain(c, n, Y, low);   // precision form: BF16 factor rows in the Kronecker tiles
+        // the precision form keeps the Kronecker tiles in FP32 here: BF16 factor
+        // rows perturb ||G||^2 by ~1e-3, more than the residual of a
+        // well-fitting decomposition, and gave no speed-up (the TTM-chain is
+        // bound by gather latency, not bytes)
+        ttm_chain(c, n, Y, false);
       }
       c->ev_ttm[0] = c->ev_ttm[1] = nullptr;
       if (c->m == 0) {  // no launch: give the bracket a zero-length interval
@@ -369,6 +373,8 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       for (int k = 0; k < K[n]; ++k) I[(size_t)k * K[n] + k] = 1.0;
       h2d(c, c->F64[n].as<double>(), I.data(), I.size());
       refresh_factor_copies(c, n);
+      c->fac_dirty[n] = true;
+      c->eig_warm_k[n] = 0;
       c->sync();
     }
     c->have_ranks = true;
@@ -409,6 +415,7 @@ tk_status tk_set_factor(tk_ctx* c, int n, const double* F, tk_mem mem) {
     TK_REQUIRE(n >= 0 && n < c->N && F, TK_ERR_INVALID_ARG, "mode out of range or F is NULL");
     copy_in(c, c->F64[n].as<double>(), F, (size_t)c->dims[n] * c->K[n], mem);
     refresh_factor_copies(c, n);
+    c->fac_dirty[n] = true;
     c->sync();
   });
 }

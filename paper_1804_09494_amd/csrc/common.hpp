@@ -173,6 +173,7 @@ struct Ctx {
   Buf kr_work;            // block-Krylov eigensolver workspace (large Khat)
   Buf eig_warm[8];        // last eigenvectors of each mode's Gram (Krylov warm start)
   int eig_warm_k[8] = {0};
+  bool fac_dirty[8] = {true, true, true, true, true, true, true, true};   // rows of empty slices may be nonzero
   Buf core64;             // double[prod K]
   Buf flag;               // int32 flags
 

@@ -56,12 +56,25 @@ __global__ __launch_bounds__(256) void k_core_part(const float* __restrict__ Y, 
   }
 }
 
-// Sum partials in workgroup order; write the core (first index fastest).
-__global__ void k_core_reduce(const double* __restrict__ part, int nwg, int K, int khat, double* __restrict__ core) {
+constexpr int CORE_GROUP = 32;   // workgroup partials summed per first-level thread
+
+// Level 1: sums of CORE_GROUP consecutive workgroup partials (fixed order).
+__global__ void k_core_group(const double* __restrict__ part, int nwg, int nent, double* __restrict__ gsum) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nent) return;
+  const int w0 = blockIdx.y * CORE_GROUP, w1 = min(w0 + CORE_GROUP, nwg);
+  double s = 0.0;
+  for (int w = w0; w < w1; ++w) s += part[(int64_t)w * nent + i];
+  gsum[(int64_t)blockIdx.y * nent + i] = s;
+}
+
+// Level 2: sum the groups in order; write the core (first index fastest).
+__global__ void k_core_reduce(const double* __restrict__ gsum, int ngroups, int K, int khat,
+                              double* __restrict__ core) {
   const int nent = K * khat;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nent; i += gridDim.x * blockDim.x) {
     double s = 0.0;
-    for (int w = 0; w < nwg; ++w) s += part[(int64_t)w * nent + i];
+    for (int g = 0; g < ngroups; ++g) s += gsum[(int64_t)g * nent + i];
     const int k = i / khat, col = i - k * khat;
     core[col + (int64_t)khat * k] = s;
   }
@@ -94,8 +107,11 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   const int K = c->K[n];
   int rows_per_wg = (int)std::max<int64_t>(CORE_TILE, ceil_div(ceil_div(std::max<int64_t>(R, 1), 1024), CORE_TILE) * CORE_TILE);
   const int nwg = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
-  ensure(c, c->gram_part, sizeof(double) * (size_t)nwg * K * khat);
+  const int nent = K * khat;
+  const int ngroups = (nwg + CORE_GROUP - 1) / CORE_GROUP;
+  ensure(c, c->gram_part, sizeof(double) * ((size_t)nwg + ngroups) * nent);
   double* part = c->gram_part.as<double>();
+  double* gsum = part + (size_t)nwg * nent;
   if (R > 0) {
     // rows staged per pass: CORE_TILE, fewer when Khat is wide
     const int64_t per_row = sizeof(double) * K + sizeof(float) * (int64_t)khat;
@@ -105,8 +121,11 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
     hipLaunchKernelGGL(k_core_part, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
                        pl.row_slice.as<int32_t>(), rows_per_wg, tile, part);
     TK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_core_reduce, dim3(grid_for((int64_t)K * khat, 256, 1024)), dim3(256), 0, c->stream, part,
-                       nwg, K, khat, core);
+    hipLaunchKernelGGL(k_core_group, dim3((unsigned)ceil_div(nent, 256), ngroups), dim3(256), 0, c->stream, part,
+                       nwg, nent, gsum);
+    TK_CHECK_LAUNCH();
+    hipLaunchKernelGGL(k_core_reduce, dim3(grid_for((int64_t)nent, 256, 1024)), dim3(256), 0, c->stream, gsum,
+                       ngroups, K, khat, core);
     TK_CHECK_LAUNCH();
   } else {
     TK_HIP(hipMemsetAsync(core, 0, sizeof(double) * (size_t)K * khat, c->stream));

@@ -306,6 +306,64 @@ __global__ void k_chol_inv(const double* __restrict__ Asum, int K, double* __res
   }
 }
 
+// The same for K <= 16 with one wavefront: right-looking Cholesky (lanes over
+// the trailing block), then column c of R^-1 by back substitution in lane c.
+__global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__ Asum, int K,
+                                                      double* __restrict__ Rinv, int* __restrict__ flag) {
+  __shared__ double A[16 * 16];
+  __shared__ double rdiag[16];
+  __shared__ int okf;
+  const int l = threadIdx.x;
+  for (int i = l; i < K * K; i += 64) A[i] = Asum[i];
+  if (l == 0) okf = 1;
+  __syncthreads();
+  double dmax = 0.0;
+  for (int i = 0; i < K; ++i) dmax = fmax(dmax, A[i * K + i]);
+  if (!(dmax > 0.0) && l == 0) okf = 0;
+  __syncthreads();
+  // A = R^T R, R stored in the upper triangle of A (row j: R[j][j..K-1])
+  for (int j = 0; j < K && okf; ++j) {
+    const double d = A[j * K + j];
+    __syncthreads();
+    if (!(d > 1e-16 * dmax)) {
+      if (l == 0) okf = 0;
+      __syncthreads();
+      break;
+    }
+    const double r = sqrt(d);
+    const double ri = 1.0 / r;
+    // row j of R: R[j][i] = A[j][i] / r for i > j
+    if (l > j && l < K) A[j * K + l] *= ri;
+    if (l == 0) { A[j * K + j] = r; rdiag[j] = ri; }
+    __syncthreads();
+    // trailing update A[i][k] -= R[j][i] R[j][k], i, k > j (upper triangle)
+    for (int q = l; q < K * K; q += 64) {
+      const int i = q / K, k = q - i * K;
+      if (i > j && k >= i) A[i * K + k] -= A[j * K + i] * A[j * K + k];
+    }
+    __syncthreads();
+  }
+  if (!okf) {
+    if (l == 0) flag[0] |= 1;
+    for (int i = l; i < K * K; i += 64) Rinv[i] = (i / K == i % K) ? 1.0 : 0.0;
+    return;
+  }
+  // column c of R^-1 (upper triangular): X[c][c] = 1/R[c][c], X[i][c] = -(sum_{k=i+1..c} R[i][k] X[k][c]) / R[i][i]
+  __shared__ double X[16 * 16];   // X[c][i] = R^-1[i][c] (LDS: a runtime-indexed register array would spill)
+  if (l < K) {
+    const int c = l;
+    double* x = X + c * 16;
+    for (int i = 0; i < K; ++i) x[i] = 0.0;
+    x[c] = rdiag[c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= c; ++k) s += A[i * K + k] * x[k];
+      x[i] = -s * rdiag[i];
+    }
+    for (int i = 0; i < K; ++i) Rinv[i * K + c] = x[i];
+  }
+}
+
 // W = V_K diag(lam)^(-1/2); a column with a non-positive or negligible
 // eigenvalue (relative to the largest) is zeroed and flagged (bit 1).
 __global__ void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam, int khat, int K,
@@ -436,16 +494,23 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, khat,
                      K, W, flag_dev);
   TK_CHECK_LAUNCH();
-  auto clear_factor = [&]() {   // rows of empty slices stay zero
+  // rows of empty slices (never written below) must be zero: clear the copies
+  // only when something else may have written them (tk_set_factor, completion)
+  auto clear_factor = [&]() {
+    if (!c->fac_dirty[n]) return;
     TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
     TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
     TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+    c->fac_dirty[n] = false;
   };
   auto reduce_chol = [&]() {
     hipLaunchKernelGGL(k_sum_parts, dim3(std::min(K * K, 1024)), dim3(256), 0, c->stream, part, nwg, K * K, Asum);
     TK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), sizeof(double) * 2 * K * K, c->stream, Asum, K, Rinv,
-                       flag_dev);
+    if (K <= 16)
+      hipLaunchKernelGGL(k_chol_inv_wave, dim3(1), dim3(64), 0, c->stream, Asum, K, Rinv, flag_dev);
+    else
+      hipLaunchKernelGGL(k_chol_inv, dim3(1), dim3(64), sizeof(double) * 2 * K * K, c->stream, Asum, K, Rinv,
+                         flag_dev);
     TK_CHECK_LAUNCH();
   };
   if (R > 0 && mfma) {
@@ -493,6 +558,7 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   if (hflag || R < K) {
     if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
     complete_on_host(c, n);
+    c->fac_dirty[n] = true;   // completion may use rows of empty slices
     return true;
   }
   return false;

@@ -197,15 +197,18 @@ def make_tensor(dims, nnz, dist="zipf", zipf=None, values_kind="lognormal", seed
     return idx, values(seed, nnz, values_kind)
 
 
-def make_workload(name: str, scale: float = 1.0):
+def make_workload(name: str, scale: float = 1.0, share: int = 1):
     """Coordinates, values, initial factors and ranks of a named workload.
 
     ``scale`` < 1 shrinks dims and nnz by that factor (same distributions),
-    used for parity cases the checker finishes in seconds."""
+    used for parity cases the checker finishes in seconds.  ``share`` > 1 keeps
+    the dims and takes the first nnz/share draws: one GPU's part of the
+    workload spread over ``share`` GPUs (the draws are counter-based, so this
+    is exactly the first contiguous shard)."""
     w = dict(WORKLOADS[name])
     c = w["number"]
     dims = tuple(max(2, int(round(L * scale))) for L in w["dims"])
-    nnz = max(1, int(round(w["nnz"] * scale)))
+    nnz = max(1, int(round(w["nnz"] * scale)) // max(1, int(share)))
     if w["values"] == "planted":
         raise ValueError("use make_completion for the planted-model workload")
     idx, vals = make_tensor(dims, nnz, w["dist"], w.get("zipf"), w["values"], seed=1804 + c)

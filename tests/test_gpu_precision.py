@@ -1,6 +1,7 @@
 """Precision form on the GPU: the Gram of Y_(n) with BF16 operands on the
 matrix cores (FP32 accumulation), FP64 eigensolve and CholeskyQR2 as in the
-FP32 path, and the refining last invocation in FP32.  Checked against the FP64
+FP32 path, and the refining last invocation in FP32; and the TTM-chain with
+BF16 factor rows (tk_ttm_chain with prec = BF16).  Checked against the FP64
 oracle: one BF16 invocation to 1e-2, the refining invocation from the same
 input factors to 1e-5, and the final fit of a BF16 run to 1e-5."""
 import numpy as np
@@ -27,6 +28,22 @@ def _allowed(ic, vc, dims, F_out, n, K, tol):
     sv = np.linalg.svd(ttm.ttm_chain(ic, vc, F_out, n, dims), compute_uv=False)
     cond = sv[0] ** 2 / max(sv[K - 1] ** 2 - sv[K] ** 2, 1e-300) if len(sv) > K else 1.0
     return max(tol, 6e-8 * 50 * cond), cond
+
+
+def test_bf16_kronecker_tiles_ttm_within_1e2(tk):
+    """tk_ttm_chain with prec = BF16 gathers BF16 factor rows (FP32 accumulation)."""
+    from oracle import coo as _coo
+    w = synth.make_workload("c2", scale=0.002)
+    ctx = _ctx(tk, w, prec="bf16")
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    ic, vc, _ = _coo.coalesce_fast(w["idx"], w["vals"])
+    for n in range(3):
+        Y, rows = ctx.ttm_chain(n)
+        Yo = ttm.ttm_chain(ic, vc, w["F0"], n, w["dims"])[rows]
+        err = float(np.linalg.norm(Y - Yo) / np.linalg.norm(Yo))
+        print(f"mode {n}: BF16 Kronecker tiles rel err {err:.2e}", flush=True)
+        assert 1e-5 < err <= 1e-2     # really rounded, and within the BF16 bound
 
 
 def test_bf16_invocation_within_1e2(tk):
