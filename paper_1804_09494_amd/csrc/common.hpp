@@ -273,6 +273,7 @@ void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t
 int ttm_rows_cap(Ctx* c, int64_t tile_w);
 int ttm_tile_width(int N, const int32_t* K, int n);
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
+bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
              const float* lay_val, int64_t m, float* Y, const uint16_t* const* H16 = nullptr);

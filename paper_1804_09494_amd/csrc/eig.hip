@@ -465,7 +465,7 @@ __device__ __forceinline__ double rl(double x, int l) { return lane_val(x, l); }
 __device__ __forceinline__ double col_of(const double (&x)[2], int J) { return rl(J < 64 ? x[0] : x[1], J & 63); }
 
 struct SmallLayout {
-  int64_t A, part, d, e, e2, tau, scl, red, lam, Z, lu, gm, total;
+  int64_t A, part, vec, d, e, e2, tau, scl, red, lam, Z, lu, gm, total;
 };
 
 static SmallLayout small_layout(int n, int K) {
@@ -473,6 +473,7 @@ static SmallLayout small_layout(int n, int K) {
   int64_t o = 0;
   L.A = o; o += (int64_t)n * (n + 1);
   L.part = o; o += 2 * EIG_WAVES * SM_N;
+  L.vec = o; o += 2 * 3 * SM_N;
   L.d = o; o += n;
   L.e = o; o += n;
   L.e2 = o; o += n;
@@ -541,6 +542,22 @@ __device__ __forceinline__ void sturm_count4(const double* d, const double* e2, 
   }
 }
 
+// One Sturm count with the same arithmetic as sturm_count4.
+__device__ __forceinline__ int sturm_count1(const double* d, const double* e2, int n, double x, double pivmin) {
+  double q = d[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int cnt = q < 0.0;
+  for (int i = 1; i < n; ++i) {
+    double r = __builtin_amdgcn_rcp(q);
+    r = fma(fma(-q, r, 1.0), r, r);
+    r = fma(fma(-q, r, 1.0), r, r);
+    q = fma(-e2[i - 1], r, d[i] - x);
+    if (fabs(q) < pivmin) q = -pivmin;
+    cnt += q < 0.0;
+  }
+  return cnt;
+}
+
 __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __restrict__ G, int n, int K, int Kout,
                                                             SmallLayout L, double* __restrict__ lam_out,
                                                             double* __restrict__ VK) {
@@ -550,6 +567,7 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
   const int S = n + 1;
   double* A = sh + L.A;
   double* part = sh + L.part;
+  double* vec = sh + L.vec;   // [v | w | v_next] of the current step, double-buffered by step parity
   double* d = sh + L.d;
   double* e = sh + L.e;
   double* e2 = sh + L.e2;
@@ -635,28 +653,45 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
         const int J = lane + 64 * c;
         cok[c] = J >= k + 2 && J < n;
       }
-      // four rows per iteration: all loads are issued before the first store
+      // the row constants v_I, w_I, v_next_I come from LDS as broadcast reads:
+      // every wave stores the same vectors, and reads back only its own stores
+      double* vb = vec + (k & 1) * 3 * SM_N;
+#pragma unroll
+      for (int c = 0; c < 2; ++c) {
+        vb[lane + 64 * c] = v[c];
+        vb[SM_N + lane + 64 * c] = w[c];
+        vb[2 * SM_N + lane + 64 * c] = vn[c];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      // four rows per iteration: all loads are issued before the first store;
+      // lanes outside the trailing block load and store the row's unused
+      // padding column, so no load or store is predicated
+      int coff[2];
+#pragma unroll
+      for (int c = 0; c < 2; ++c) coff[c] = cok[c] ? lane + 64 * c : n;
       for (int I0 = k + 2 + wave; I0 < n; I0 += 4 * EIG_WAVES) {
-        double a[4][2];
+        double a[4][2], cv[4], cw[4], cn[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int I = I0 + u * EIG_WAVES;
           const int Ic = I < n ? I : n - 1;
 #pragma unroll
-          for (int c = 0; c < 2; ++c) a[u][c] = A[Ic * S + (cok[c] ? lane + 64 * c : n - 1)];   // unconditional load
+          for (int c = 0; c < 2; ++c) a[u][c] = A[Ic * S + coff[c]];
+          cv[u] = vb[Ic];
+          cw[u] = vb[SM_N + Ic];
+          cn[u] = vb[2 * SM_N + Ic];
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int I = I0 + u * EIG_WAVES;
           if (I < n) {
-            const double vI = col_of(v, I), wI = col_of(w, I), vnI = col_of(vn, I);
 #pragma unroll
             for (int c = 0; c < 2; ++c) {
-              if (cok[c]) {
-                const double x = a[u][c] - (vI * w[c] + wI * v[c]);
-                A[I * S + lane + 64 * c] = x;
-                acc[c] += x * vnI;
-              }
+              const double x = a[u][c] - (cv[u] * w[c] + cw[u] * v[c]);
+              A[I * S + coff[c]] = x;
+              acc[c] += x * cn[u];
             }
           }
         }
@@ -732,11 +767,23 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     const int gbase = lane & ~15;
     const unsigned long long gmask = 0xFFFFULL << gbase;
     const double tol = 1e-11 * fmax(tnorm, pivmin);
-    int rounds = 1;
-    for (double wd = ghi - glo; wd > tol && rounds < 24; wd /= (double)(NP + 1)) ++rounds;
     const bool act = g < K;
     const int idx = n - 1 - g;
-    double a = glo, b = ghi;
+    // joint first round: one point per thread over the whole interval serves
+    // every eigenvalue at once (the partial-product buffer is free by now)
+    int* cnt0 = reinterpret_cast<int*>(part);
+    const double h0 = (ghi - glo) / (double)(EIG_THREADS + 1);
+    cnt0[tid] = sturm_count1(d, e2, n, glo + h0 * (double)(tid + 1), pivmin);
+    __syncthreads();
+    int t0 = -1, t1 = EIG_THREADS - 1;   // largest t with cnt0[t] <= idx (counts rise with x)
+    while (t0 < t1) {
+      const int mid = (t0 + t1 + 1) >> 1;
+      if (cnt0[mid] <= idx) t0 = mid; else t1 = mid - 1;
+    }
+    double a = t0 < 0 ? glo : glo + h0 * (double)(t0 + 1);
+    double b = t0 >= EIG_THREADS - 1 ? ghi : glo + h0 * (double)(t0 + 2);
+    int rounds = 1;
+    for (double wd = h0; wd > tol && rounds < 24; wd /= (double)(NP + 1)) ++rounds;
     for (int r = 0; r < rounds; ++r) {
       const double h = (b - a) / (double)(NP + 1);
       double x[4];

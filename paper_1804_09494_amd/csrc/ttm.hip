@@ -389,6 +389,179 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   }
 }
 
+// ---- four-mode TTM-chain on the matrix cores ------------------------------------------------
+//
+// With remaining modes a, b, c (ascending), Y[row] viewed as K_a x K_b x K_c is
+//   sum_e val_e F_a[l_a(e)] (x) F_b[l_b(e)] (x) F_c[l_c(e)],
+// and for each c-index q its K_a x K_b slab is the contraction
+//   sum_e (val_e F_c[l_c(e)][q] F_a[l_a(e)]) F_b[l_b(e)]^T:
+// the 3-mode MFMA step with the A operand scaled by the element's F_c entry.
+// KC MFMAs per 4-element step; lane group k reads the whole F_c row of its
+// element (64 bytes, the same address across the group).  Column of Y:
+// i + K_a (j + K_b q).  A wave's slices that continue into a neighbouring
+// wave keep their partial rows in registers and are added to the bin's LDS
+// rows in wave order after the main loop (no atomics, deterministic).
+template <int KC>
+__global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg_pad) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int ka = A.Kj[0], kb = A.Kj[1];
+  const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
+  const int64_t e0 = A.bin_ptr[bin];
+  const int E = (int)(A.bin_ptr[bin + 1] - e0);   // multiple of 4
+  const int s0 = A.seg_ptr[bin];
+  const int nseg = A.seg_ptr[bin + 1] - s0;
+  int* send = reinterpret_cast<int*>(smem);
+  int* sslot = send + nseg_pad;
+  int* srow = sslot + nseg_pad;
+  int* sia = srow + nseg_pad;
+  int* sib = sia + Epad;
+  int* sic = sib + Epad;
+  float* sv = reinterpret_cast<float*>(sic + Epad);
+  float* rows = sv + Epad;                                  // nseg x khat
+  const int khat = A.khat;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uni(tid >> 6);
+  for (int i = tid; i < nseg; i += 256) {
+    send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
+    sslot[i] = A.seg_slot[s0 + i];
+    srow[i] = A.seg_row[s0 + i];
+  }
+  for (int i = tid; i < nseg * khat; i += 256) rows[i] = 0.f;   // shared rows are summed into
+  const int Ep = (E + 15) & ~15;
+  for (int i = tid; i < Ep; i += 256) {
+    const bool ok = i < E;
+    const int q = ttm3_lds_pos(i);
+    sia[q] = ok ? __builtin_nontemporal_load(A.lay[0] + e0 + i) : 0;
+    sib[q] = ok ? __builtin_nontemporal_load(A.lay[1] + e0 + i) : 0;
+    sic[q] = ok ? __builtin_nontemporal_load(A.lay[2] + e0 + i) : 0;
+    sv[q] = ok ? __builtin_nontemporal_load(A.val + e0 + i) : 0.f;
+  }
+  __syncthreads();
+
+  const int Q = (((E + 3) >> 2) + 15) & ~15;
+  const int cs = min(wave * Q, E), ce = min(cs + Q, E);
+  const int k = lane >> 4, cix = lane & 15;
+  const float* __restrict__ Fa = A.F[0];
+  const float* __restrict__ Fb = A.F[1];
+  const float* __restrict__ Fc = A.F[2];
+  floatx4_t C[KC], Lp[KC];
+  bool has_left = false, has_right = false;
+  int left_sg = 0, right_sg = 0;
+  if (cs < ce) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (uni(send[mid]) > cs) hi = mid; else lo = mid + 1;
+    }
+    int sg = lo;
+    int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
+    int seg_hi = uni(send[sg]);
+#pragma unroll
+    for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    auto flush = [&]() {
+      const bool left = seg_lo < cs, right = seg_hi > ce;
+      if (!left && !right) {
+        float* dst = rows + sg * khat;
+        if (cix < kb) {
+#pragma unroll
+          for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] = C[q][r];
+        }
+      } else if (right) {   // the last slice of the quarter: stays in C
+        has_right = true;
+        right_sg = sg;
+        return;
+      } else {              // the first slice of the quarter, begun by an earlier wave
+#pragma unroll
+        for (int q = 0; q < KC; ++q) Lp[q] = C[q];
+        has_left = true;
+        left_sg = sg;
+      }
+#pragma unroll
+      for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    };
+    constexpr int NC4 = (KC + 3) / 4;
+    float rx[TTM3_DEPTH][4], rb[TTM3_DEPTH][4];
+    float4 rc[TTM3_DEPTH][4][NC4];
+    auto fetch = [&](int g, float (&x)[4], float (&b)[4], float4 (&cc)[4][NC4]) {
+      const int4 ia4 = *reinterpret_cast<const int4*>(sia + g + 4 * k);
+      const int4 ib4 = *reinterpret_cast<const int4*>(sib + g + 4 * k);
+      const int4 ic4 = *reinterpret_cast<const int4*>(sic + g + 4 * k);
+      const float4 v4 = *reinterpret_cast<const float4*>(sv + g + 4 * k);
+      const int ia[4] = {ia4.x, ia4.y, ia4.z, ia4.w}, ib[4] = {ib4.x, ib4.y, ib4.z, ib4.w};
+      const int ic[4] = {ic4.x, ic4.y, ic4.z, ic4.w};
+      const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
+        b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
+        const float4* crow = reinterpret_cast<const float4*>(Fc + (uint32_t)(ic[u] * 16));
+#pragma unroll
+        for (int h = 0; h < NC4; ++h) cc[u][h] = crow[h];
+      }
+    };
+    auto consume = [&](int g, const float (&x)[4], const float (&b)[4], const float4 (&cc)[4][NC4]) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gu = g + 4 * u;
+        if (gu >= ce) break;
+        if (gu >= seg_hi) {
+          flush();
+          ++sg;
+          seg_lo = seg_hi;
+          seg_hi = uni(send[sg]);
+        }
+        const float* cv = reinterpret_cast<const float*>(&cc[u][0]);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) C[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u] * cv[q], b[u], C[q], 0, 0, 0);
+      }
+    };
+    const int last = Ep - 16;
+#pragma unroll
+    for (int d = 0; d < TTM3_DEPTH; ++d) fetch(min(cs + 16 * d, last), rx[d], rb[d], rc[d]);
+    for (int g = cs; g < ce; g += 16 * TTM3_DEPTH) {
+#pragma unroll
+      for (int d = 0; d < TTM3_DEPTH; ++d) {
+        const int gg = g + 16 * d;
+        consume(gg, rx[d], rb[d], rc[d]);
+        fetch(min(gg + 16 * TTM3_DEPTH, last), rx[d], rb[d], rc[d]);
+      }
+    }
+    flush();
+  }
+  __syncthreads();
+  // partial rows of slices shared between waves, added in wave order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w && cix < kb) {
+      if (has_left) {
+        float* dst = rows + left_sg * khat;
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += Lp[q][r];
+      }
+      if (has_right) {
+        float* dst = rows + right_sg * khat;
+#pragma unroll
+        for (int q = 0; q < KC; ++q)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
+      }
+    }
+    __syncthreads();
+  }
+  for (int q = tid; q < nseg * khat; q += 256) {
+    const int sgi = q / khat, col = q - sgi * khat;
+    const int slot = sslot[sgi];
+    float* dst = slot < 0 ? A.Y + (int64_t)srow[sgi] * khat : A.partial + (int64_t)slot * khat;
+    __builtin_nontemporal_store(rows[q], dst + col);
+  }
+}
+
 // Sum the partial rows of every split slice in bin order, in two fixed-order
 // levels: chunks of at most FIX_CHUNK consecutive slots, then the chunks of
 // each slice (deterministic, and parallel for slices split over many bins).
@@ -452,8 +625,26 @@ bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp) {
   return true;
 }
 
+// Four-mode tensors with all remaining ranks <= 16 and 16-float factor rows
+// take the four-mode matrix-core kernel.
+bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp) {
+  if (N != 4) return false;
+  for (int j = 0; j < 4; ++j)
+    if (j != n && (K[j] > 16 || kp[j] != 16)) return false;
+  return true;
+}
+
 int ttm_tile_width(int N, const int32_t* K, int n) {
   TtmShape s = ttm_shape(N, K, n);
+  int kp16[8];
+  for (int j = 0; j < N; ++j) kp16[j] = K[j] <= 16 ? 16 : 0;
+  // the matrix-core kernels keep whole rows of Y in LDS
+  if (ttm_uses_mfma(N, K, n, kp16) || ttm_uses_mfma4(N, K, n, kp16)) {
+    int kh = 1;
+    for (int j = 0; j < N; ++j)
+      if (j != n) kh *= K[j];
+    return kh;
+  }
   int kmax = s.exact ? s.KA : (s.mode == 1 ? 32 : (s.KA <= 16 ? 16 : 32));
   return kmax * s.TW;
 }
@@ -526,6 +717,23 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
       hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
     else
       hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+    TK_CHECK_LAUNCH();
+  } else if (ttm_uses_mfma4(N, K, n, kp)) {
+    const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
+    const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
+    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 16 * (size_t)Epad +
+                       sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
+    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
+    const dim3 g((unsigned)pl.P), b(256);
+    switch (a.Kj[2]) {
+#define TK_TTM4_CASE(KC) \
+      case KC: hipLaunchKernelGGL(k_ttm4_mfma<KC>, g, b, lds, c->stream, a, Epad, nseg_pad); break;
+      TK_TTM4_CASE(1) TK_TTM4_CASE(2) TK_TTM4_CASE(3) TK_TTM4_CASE(4) TK_TTM4_CASE(5) TK_TTM4_CASE(6)
+      TK_TTM4_CASE(7) TK_TTM4_CASE(8) TK_TTM4_CASE(9) TK_TTM4_CASE(10) TK_TTM4_CASE(11) TK_TTM4_CASE(12)
+      TK_TTM4_CASE(13) TK_TTM4_CASE(14) TK_TTM4_CASE(15) TK_TTM4_CASE(16)
+#undef TK_TTM4_CASE
+      default: fail(TK_ERR_UNSUPPORTED, "four-mode TTM: rank above 16");
+    }
     TK_CHECK_LAUNCH();
   } else if (s.exact) {
     if (s.mode == 2 && s.KA == 10) launch_ttm<10, 10, 2, true>(c, a, pl, s.ntiles, tw);
