@@ -20,6 +20,7 @@
 namespace tk {
 
 typedef float floatx4_t __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 struct TtmArgs {
   const int64_t* bin_ptr;
@@ -202,30 +203,36 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
 //   sum_e (val_e F_a[l_a(e)]) F_b[l_b(e)]^T,
 // a contraction over the slice's elements: v_mfma_f32_16x16x4_f32 with lane l
 // supplying A[i = l%16][k = l/16] = val_k F_a[l_a(k)][i] and
-// B[k = l/16][j = l%16] = F_b[l_b(k)][j] (factor rows padded to 16 floats, so
-// a 16-lane group reads one 64-byte row).  The result D[4*(l/16)+r][l%16] is
-// Y[row][i + K_a j].
+// B[k = l/16][j = l%16] = F_b[l_b(k)][j] (factor rows padded to 16 floats).
+// The result D[4*(l/16)+r][l%16] is Y[row][i + K_a j].
+//
+// Gathers: the address unit takes a fixed number of lanes per cycle whatever
+// the width of each lane's load, so the rows of a block of 16 elements are
+// fetched with 16-byte loads (four lanes per 64-byte row, one instruction per
+// factor) and turned into the operand layout through a 2 KB LDS tile per wave
+// (one 16-byte write and four 4-byte reads per lane and factor).
 //
 // The layout this kernel streams pads every slice segment to a multiple of 4
 // elements (zero values), so one MFMA step (4 consecutive elements) lies in one
 // slice: a slice change is a scalar compare per step, with no masking.  Each of
 // the four waves streams a contiguous quarter of the bin in blocks of 16
-// elements (four steps) from the LDS copy of the bin, stored so that one
-// 16-byte read gives lane group k the elements g+k, g+4+k, g+8+k, g+12+k.
-// When a slice ends its accumulator goes straight to Y (or to the bin's partial
-// slot for a slice split over bins); the at most two slices a wave shares with
-// its neighbours are parked in LDS and added in wave order after a barrier.
+// elements from the LDS copy of the bin.  When a slice ends its accumulator
+// goes to the bin's LDS rows; the at most two slices a wave shares with its
+// neighbours are parked in LDS and added in wave order after a barrier.
 // No atomics: the result is deterministic.
 constexpr int TTM3_SLOT = 256;
-constexpr int TTM3_DEPTH = 2;  // blocks of 16 elements with gathers in flight per wave
+constexpr int TTM3_RING = 4;   // blocks of 16 elements with gathers in flight per wave
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
-// position of padded element i inside the bin's LDS copy (4x4 transpose inside each block of 16)
-__device__ __forceinline__ int ttm3_lds_pos(int i) { return (i & ~15) | ((i & 3) << 2) | ((i >> 2) & 3); }
+__device__ __forceinline__ float4 bf16x2_lo_hi(uint32_t x, uint32_t y) {
+  return make_float4(__uint_as_float(x << 16), __uint_as_float(x & 0xffff0000u), __uint_as_float(y << 16),
+                     __uint_as_float(y & 0xffff0000u));
+}
 
-// BF: the factor rows are gathered from the BF16 copies (32-byte rows) and
-// widened to FP32 in registers; the contraction and the accumulation stay FP32.
+// BF: the factor rows are gathered from the BF16 copies (32-byte rows, two
+// lanes per row, lanes 0-31 for F_a and 32-63 for F_b) and widened to FP32
+// before the LDS tile; the contraction and the accumulation stay FP32.
 template <bool BF>
 __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -241,7 +248,8 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   int* sia = srow + nseg_pad;                               // Epad
   int* sib = sia + Epad;                                    // Epad
   float* sv = reinterpret_cast<float*>(sib + Epad);         // Epad
-  float* slots = sv + Epad;                                 // 4 waves x 2 x 256
+  float* tiles = sv + Epad;                                 // 4 waves x 512: F_a and F_b rows of one block
+  float* slots = tiles + 4 * 512;                           // 4 waves x 2 x 256
   int* winfo = reinterpret_cast<int*>(slots + 8 * TTM3_SLOT);  // 4 waves x 2
   float* rows = reinterpret_cast<float*>(winfo + 8);        // nseg x khat: the bin's rows of Y
   const int khat = A.khat;
@@ -253,15 +261,19 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
     srow[i] = A.seg_row[s0 + i];
   }
   const int Ep = (E + 15) & ~15;
-  const int32_t* __restrict__ la = A.lay[0];
-  const int32_t* __restrict__ lb = A.lay[1];
-  for (int i = tid; i < Ep; i += 256) {
-    const bool ok = i < E;
-    const int q = ttm3_lds_pos(i);
-    // the layout is read once: non-temporal loads keep it from evicting factor rows in L2
-    sia[q] = ok ? __builtin_nontemporal_load(la + e0 + i) : 0;
-    sib[q] = ok ? __builtin_nontemporal_load(lb + e0 + i) : 0;
-    sv[q] = ok ? __builtin_nontemporal_load(A.val + e0 + i) : 0.f;
+  // the layout is read once, four elements per lane (bins start at multiples
+  // of four): non-temporal loads keep it from evicting factor rows in L2
+  {
+    const u32x4* la4 = reinterpret_cast<const u32x4*>(A.lay[0] + e0);
+    const u32x4* lb4 = reinterpret_cast<const u32x4*>(A.lay[1] + e0);
+    const u32x4* v4 = reinterpret_cast<const u32x4*>(A.val + e0);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int i = tid; 4 * i < Ep; i += 256) {
+      const bool ok = 4 * i < E;
+      reinterpret_cast<u32x4*>(sia)[i] = ok ? __builtin_nontemporal_load(la4 + i) : z;
+      reinterpret_cast<u32x4*>(sib)[i] = ok ? __builtin_nontemporal_load(lb4 + i) : z;
+      reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
+    }
   }
   if (lane == 0) {
     winfo[2 * wave] = -1;
@@ -274,10 +286,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   const int cs = min(wave * Q, E), ce = min(cs + Q, E);
   const int k = lane >> 4, cix = lane & 15;
   const bool bok = cix < kb;
-  const float* __restrict__ Fa = A.F[0];
-  const float* __restrict__ Fb = A.F[1];
-  const uint16_t* __restrict__ Ha = A.H[0];
-  const uint16_t* __restrict__ Hb = A.H[1];
+  float* tile = tiles + wave * 512;
   if (cs < ce) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -310,27 +319,53 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
       }
       C = floatx4_t{0.f, 0.f, 0.f, 0.f};
     };
-    float rx[TTM3_DEPTH][4], rb[TTM3_DEPTH][4];
-    auto fetch = [&](int g, float (&x)[4], float (&b)[4]) {
-      const int4 ia4 = *reinterpret_cast<const int4*>(sia + g + 4 * k);
-      const int4 ib4 = *reinterpret_cast<const int4*>(sib + g + 4 * k);
-      const float4 v4 = *reinterpret_cast<const float4*>(sv + g + 4 * k);
-      const int ia[4] = {ia4.x, ia4.y, ia4.z, ia4.w}, ib[4] = {ib4.x, ib4.y, ib4.z, ib4.w};
-      const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
-      // all 16 lanes load: the factor copies are zero beyond column K, so no
-      // predicate (a predicated load would make the in-flight count path dependent)
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        if (BF) {
-          x[u] = vv[u] * __uint_as_float((uint32_t)Ha[(uint32_t)(ia[u] * 16 + cix)] << 16);
-          b[u] = __uint_as_float((uint32_t)Hb[(uint32_t)(ib[u] * 16 + cix)] << 16);
-        } else {
-          x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
-          b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
-        }
+    // Gather of block g.  FP32: lane l takes element g + l/4, 16-byte quarter
+    // l%4 of its F_a and F_b rows.  BF16: lane l takes element g + (l/2)%16,
+    // half l%2 of the F_a (l < 32) or F_b row.  All lanes load: the factor
+    // copies are zero beyond column K, so no predicate (a predicated load would
+    // make the in-flight count path dependent).
+    struct Blk { u32x4 x, y; float v; };
+    const uintptr_t hbase = reinterpret_cast<uintptr_t>(A.H[0]);
+    const uintptr_t hdiff = reinterpret_cast<uintptr_t>(A.H[1]) - hbase;
+    auto fetch = [&](int g, Blk& r) {
+      if constexpr (BF) {
+        const int e = g + ((lane >> 1) & 15);
+        const bool fa = lane < 32;
+        const int ix = fa ? sia[e] : sib[e];
+        r.v = fa ? sv[e] : 1.f;
+        // select a distance, not one of two pointers: a select of two
+        // argument loads becomes a per-lane load of the chosen pointer
+        const uintptr_t h = hbase + (fa ? 0 : hdiff) + 2 * (uintptr_t)(uint32_t)(ix * 16 + 8 * (lane & 1));
+        r.x = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(h);
+      } else {
+        const int e = g + (lane >> 2);
+        const int ia = sia[e], ib = sib[e];
+        r.v = sv[e];
+        r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + 4 * (lane & 3)));
+        r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + 4 * (lane & 3)));
       }
     };
-    auto consume = [&](int g, const float (&x)[4], const float (&b)[4]) {
+    auto consume = [&](int g, const Blk& r) {
+      // the rows of the block into the wave's tile: F_a (times val) at 0, F_b at 256
+      if constexpr (BF) {
+        const float4 w0 = bf16x2_lo_hi(r.x.x, r.x.y), w1 = bf16x2_lo_hi(r.x.z, r.x.w);
+        float4* t = reinterpret_cast<float4*>(tile + 8 * lane);
+        t[0] = make_float4(w0.x * r.v, w0.y * r.v, w0.z * r.v, w0.w * r.v);
+        t[1] = make_float4(w1.x * r.v, w1.y * r.v, w1.z * r.v, w1.w * r.v);
+      } else {
+        reinterpret_cast<float4*>(tile)[lane] =
+            make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
+                        __uint_as_float(r.x.w) * r.v);
+        reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
+            __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
+      }
+      // operand layout: step u, lane l reads element 4u + l/16, column l%16
+      float xa[4], xb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        xa[u] = tile[(4 * u + k) * 16 + cix];
+        xb[u] = tile[256 + (4 * u + k) * 16 + cix];
+      }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int gu = g + 4 * u;
@@ -341,21 +376,29 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
           seg_lo = seg_hi;
           seg_hi = uni(send[sg]);
         }
-        C = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u], b[u], C, 0, 0, 0);
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
       }
     };
     // Refills are unconditional (clamped to the last staged block): every path
     // then has the same loads in flight and the compiler waits only for the
     // oldest block instead of draining the ring.
     const int last = Ep - 16;
+    Blk ring[TTM3_RING];
 #pragma unroll
-    for (int d = 0; d < TTM3_DEPTH; ++d) fetch(min(cs + 16 * d, last), rx[d], rb[d]);
-    for (int g = cs; g < ce; g += 16 * TTM3_DEPTH) {
+    for (int d = 0; d < TTM3_RING; ++d) {
+      fetch(min(cs + 16 * d, last), ring[d]);
+      __builtin_amdgcn_sched_barrier(0);  // issue order = consumption order
+    }
+    for (int g = cs; g < ce; g += 16 * TTM3_RING) {
 #pragma unroll
-      for (int d = 0; d < TTM3_DEPTH; ++d) {
+      for (int d = 0; d < TTM3_RING; ++d) {
         const int gg = g + 16 * d;
-        consume(gg, rx[d], rb[d]);
-        fetch(min(gg + 16 * TTM3_DEPTH, last), rx[d], rb[d]);
+        consume(gg, ring[d]);
+        // keep the refill behind the consumption of its slot: hoisted above it,
+        // the refill takes fresh registers and the wait at the loop head
+        // drains every load in flight
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(min(gg + 16 * TTM3_RING, last), ring[d]);
       }
     }
     flush();  // the slice open at the end of this wave's quarter
@@ -395,12 +438,14 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
 //   sum_e val_e F_a[l_a(e)] (x) F_b[l_b(e)] (x) F_c[l_c(e)],
 // and for each c-index q its K_a x K_b slab is the contraction
 //   sum_e (val_e F_c[l_c(e)][q] F_a[l_a(e)]) F_b[l_b(e)]^T:
-// the 3-mode MFMA step with the A operand scaled by the element's F_c entry.
-// KC MFMAs per 4-element step; lane group k reads the whole F_c row of its
-// element (64 bytes, the same address across the group).  Column of Y:
-// i + K_a (j + K_b q).  A wave's slices that continue into a neighbouring
-// wave keep their partial rows in registers and are added to the bin's LDS
-// rows in wave order after the main loop (no atomics, deterministic).
+// the three-mode MFMA step with the A operand scaled by the element's F_c
+// entry, KC MFMAs per 4-element step.  Column of Y: i + K_a (j + K_b q).
+// The three rows of each element are gathered with 16-byte loads into a 3 KB
+// LDS tile per wave, as in the three-mode kernel; the F_c row of the step's
+// element is then read back whole by its 16-lane group (a broadcast read).
+// A wave's slices that continue into a neighbouring wave keep their partial
+// rows in registers and are added to the bin's LDS rows in wave order after
+// the main loop (no atomics, deterministic).
 template <int KC>
 __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -417,7 +462,8 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   int* sib = sia + Epad;
   int* sic = sib + Epad;
   float* sv = reinterpret_cast<float*>(sic + Epad);
-  float* rows = sv + Epad;                                  // nseg x khat
+  float* tiles = sv + Epad;                                 // 4 waves x 768: F_a, F_b, F_c rows of one block
+  float* rows = tiles + 4 * 768;                            // nseg x khat
   const int khat = A.khat;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uni(tid >> 6);
@@ -428,22 +474,26 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   }
   for (int i = tid; i < nseg * khat; i += 256) rows[i] = 0.f;   // shared rows are summed into
   const int Ep = (E + 15) & ~15;
-  for (int i = tid; i < Ep; i += 256) {
-    const bool ok = i < E;
-    const int q = ttm3_lds_pos(i);
-    sia[q] = ok ? __builtin_nontemporal_load(A.lay[0] + e0 + i) : 0;
-    sib[q] = ok ? __builtin_nontemporal_load(A.lay[1] + e0 + i) : 0;
-    sic[q] = ok ? __builtin_nontemporal_load(A.lay[2] + e0 + i) : 0;
-    sv[q] = ok ? __builtin_nontemporal_load(A.val + e0 + i) : 0.f;
+  {
+    const u32x4* la4 = reinterpret_cast<const u32x4*>(A.lay[0] + e0);
+    const u32x4* lb4 = reinterpret_cast<const u32x4*>(A.lay[1] + e0);
+    const u32x4* lc4 = reinterpret_cast<const u32x4*>(A.lay[2] + e0);
+    const u32x4* v4 = reinterpret_cast<const u32x4*>(A.val + e0);
+    const u32x4 z = {0u, 0u, 0u, 0u};
+    for (int i = tid; 4 * i < Ep; i += 256) {
+      const bool ok = 4 * i < E;
+      reinterpret_cast<u32x4*>(sia)[i] = ok ? __builtin_nontemporal_load(la4 + i) : z;
+      reinterpret_cast<u32x4*>(sib)[i] = ok ? __builtin_nontemporal_load(lb4 + i) : z;
+      reinterpret_cast<u32x4*>(sic)[i] = ok ? __builtin_nontemporal_load(lc4 + i) : z;
+      reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
+    }
   }
   __syncthreads();
 
   const int Q = (((E + 3) >> 2) + 15) & ~15;
   const int cs = min(wave * Q, E), ce = min(cs + Q, E);
   const int k = lane >> 4, cix = lane & 15;
-  const float* __restrict__ Fa = A.F[0];
-  const float* __restrict__ Fb = A.F[1];
-  const float* __restrict__ Fc = A.F[2];
+  float* tile = tiles + wave * 768;
   floatx4_t C[KC], Lp[KC];
   bool has_left = false, has_right = false;
   int left_sg = 0, right_sg = 0;
@@ -483,26 +533,30 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     };
     constexpr int NC4 = (KC + 3) / 4;
-    float rx[TTM3_DEPTH][4], rb[TTM3_DEPTH][4];
-    float4 rc[TTM3_DEPTH][4][NC4];
-    auto fetch = [&](int g, float (&x)[4], float (&b)[4], float4 (&cc)[4][NC4]) {
-      const int4 ia4 = *reinterpret_cast<const int4*>(sia + g + 4 * k);
-      const int4 ib4 = *reinterpret_cast<const int4*>(sib + g + 4 * k);
-      const int4 ic4 = *reinterpret_cast<const int4*>(sic + g + 4 * k);
-      const float4 v4 = *reinterpret_cast<const float4*>(sv + g + 4 * k);
-      const int ia[4] = {ia4.x, ia4.y, ia4.z, ia4.w}, ib[4] = {ib4.x, ib4.y, ib4.z, ib4.w};
-      const int ic[4] = {ic4.x, ic4.y, ic4.z, ic4.w};
-      const float vv[4] = {v4.x, v4.y, v4.z, v4.w};
+    // gather of block g: lane l takes element g + l/4, 16-byte quarter l%4 of
+    // its three rows (all lanes load: the copies are zero beyond column K)
+    struct Blk { u32x4 x, y, z; float v; };
+    auto fetch = [&](int g, Blk& r) {
+      const int e = g + (lane >> 2);
+      const int ia = sia[e], ib = sib[e], ic = sic[e];
+      r.v = sv[e];
+      const uint32_t o = 4 * (lane & 3);
+      r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + o));
+      r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + o));
+      r.z = *reinterpret_cast<const u32x4*>(A.F[2] + (uint32_t)(ic * 16 + o));
+    };
+    auto consume = [&](int g, const Blk& r) {
+      reinterpret_cast<float4*>(tile)[lane] =
+          make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
+                      __uint_as_float(r.x.w) * r.v);
+      reinterpret_cast<u32x4*>(tile + 256)[lane] = r.y;
+      reinterpret_cast<u32x4*>(tile + 512)[lane] = r.z;
+      float xa[4], xb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        x[u] = vv[u] * Fa[(uint32_t)(ia[u] * 16 + cix)];
-        b[u] = Fb[(uint32_t)(ib[u] * 16 + cix)];
-        const float4* crow = reinterpret_cast<const float4*>(Fc + (uint32_t)(ic[u] * 16));
-#pragma unroll
-        for (int h = 0; h < NC4; ++h) cc[u][h] = crow[h];
+        xa[u] = tile[(4 * u + k) * 16 + cix];
+        xb[u] = tile[256 + (4 * u + k) * 16 + cix];
       }
-    };
-    auto consume = [&](int g, const float (&x)[4], const float (&b)[4], const float4 (&cc)[4][NC4]) {
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int gu = g + 4 * u;
@@ -513,20 +567,30 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
           seg_lo = seg_hi;
           seg_hi = uni(send[sg]);
         }
-        const float* cv = reinterpret_cast<const float*>(&cc[u][0]);
+        float4 c4[NC4];
 #pragma unroll
-        for (int q = 0; q < KC; ++q) C[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[u] * cv[q], b[u], C[q], 0, 0, 0);
+        for (int h = 0; h < NC4; ++h) c4[h] = reinterpret_cast<const float4*>(tile + 512 + (4 * u + k) * 16)[h];
+        const float* cv = reinterpret_cast<const float*>(c4);
+#pragma unroll
+        for (int q = 0; q < KC; ++q) C[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u] * cv[q], xb[u], C[q], 0, 0, 0);
       }
     };
+    // refills unconditional (clamped to the last staged block) and kept in
+    // issue order, so the wait before each block is for its own loads only
     const int last = Ep - 16;
+    Blk ring[TTM3_RING];
 #pragma unroll
-    for (int d = 0; d < TTM3_DEPTH; ++d) fetch(min(cs + 16 * d, last), rx[d], rb[d], rc[d]);
-    for (int g = cs; g < ce; g += 16 * TTM3_DEPTH) {
+    for (int d = 0; d < TTM3_RING; ++d) {
+      fetch(min(cs + 16 * d, last), ring[d]);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    for (int g = cs; g < ce; g += 16 * TTM3_RING) {
 #pragma unroll
-      for (int d = 0; d < TTM3_DEPTH; ++d) {
+      for (int d = 0; d < TTM3_RING; ++d) {
         const int gg = g + 16 * d;
-        consume(gg, rx[d], rb[d], rc[d]);
-        fetch(min(gg + 16 * TTM3_DEPTH, last), rx[d], rb[d], rc[d]);
+        consume(gg, ring[d]);
+        __builtin_amdgcn_sched_barrier(0);
+        fetch(min(gg + 16 * TTM3_RING, last), ring[d]);
       }
     }
     flush();
@@ -710,7 +774,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   if (ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
-    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * 8 * TTM3_SLOT +
+    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * (4 * 512 + 8 * TTM3_SLOT) +
                        sizeof(int) * 8 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     if (H16)
@@ -721,7 +785,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   } else if (ttm_uses_mfma4(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
-    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 16 * (size_t)Epad +
+    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 16 * (size_t)Epad + sizeof(float) * 4 * 768 +
                        sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     const dim3 g((unsigned)pl.P), b(256);
