@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <algorithm>
 
 #include <cstdint>
 #include <cstdio>
@@ -38,7 +39,7 @@ struct Error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int FIX_CHUNK = 32;  // partial rows summed per first-level fixup block
+constexpr int FIX_CHUNK = 32;  // partial rows summed per fixup block
 
 struct Ctx;
 
@@ -97,9 +98,13 @@ struct ModePlan {
   Buf order_pad;          // uint32[m_pad] element index at each padded position (0xffffffff = padding)
   Buf bad_row;            // int32[n_bad]
   Buf bad_slot;           // int32[n_bad+1] slots of bad slice k: [bad_slot[k], bad_slot[k+1])
-  int64_t n_chunks = 0;   // fixup level 1: chunks of at most FIX_CHUNK consecutive slots of one bad slice
-  Buf chunk_slot;         // int32[n_chunks+1] first slot of each chunk (last entry = n_slots)
-  Buf chunk_ptr;          // int32[n_bad+1] chunks of bad slice k: [chunk_ptr[k], chunk_ptr[k+1])
+  // Fixup tree over the rows of the partial buffer (rows [0, n_slots) are the
+  // slots; each level appends the sums of runs of at most FIX_CHUNK rows of
+  // one slice, until every slice has at most FIX_CHUNK rows left).
+  std::vector<int64_t> fix_n;   // rows added by each level
+  Buf fix_lohi;                 // int32 per level: [lo | hi] row ranges summed by that level's rows
+  Buf fix_fin;                  // int32[2 n_bad]: [lo | hi] rows summed into Y for bad slice k
+  int64_t fix_rows = 0;         // n_slots + all level rows
   Buf lay_idx[7];         // int32[m_pad] other modes' coordinates in padded layout order (modes ascending)
   Buf lay_val;            // float[m_pad]
   Buf lay_val_bf16;       // bf16[m] (precision form)

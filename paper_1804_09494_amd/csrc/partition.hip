@@ -460,6 +460,8 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   pl.n_slots = S > 0 ? (int64_t)fetch(c, slot_scan.as<int32_t>() + S - 1) + fetch(c, bad.as<int32_t>() + S - 1) : 0;
   // bad slices
   int64_t nbad = 0;
+  pl.fix_n.clear();
+  pl.fix_rows = pl.n_slots;
   if (n2 > 0) {
     Buf bflag(c, 4 * (size_t)n2), bscan(c, 4 * (size_t)n2);
     hipLaunchKernelGGL(k_is_bad_slice, dim3(grid_for(n2, B)), dim3(B), 0, c->stream, first_seg.as<int64_t>(),
@@ -476,21 +478,47 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
                        bscan.as<int32_t>(), n2, pl.bad_row.as<int32_t>(), pl.bad_slot.as<int32_t>());
     TK_CHECK_LAUNCH();
     c->sync();
-    // fixup chunk table: each bad slice's slots cut into runs of at most FIX_CHUNK
-    std::vector<int32_t> bs((size_t)nbad + 1), cs, cp((size_t)nbad + 1);
+    // fixup tree: each level sums runs of at most FIX_CHUNK consecutive rows
+    // of one slice (fixed shape, so the order of every sum is fixed)
+    std::vector<int32_t> bs((size_t)nbad + 1);
     d2h(c, bs.data(), pl.bad_slot.as<int32_t>(), (size_t)nbad + 1);
     c->sync();
-    for (int64_t k = 0; k < nbad; ++k) {
-      cp[k] = (int32_t)cs.size();
-      for (int32_t a = bs[k]; a < bs[k + 1]; a += FIX_CHUNK) cs.push_back(a);
+    std::vector<int64_t> lo(bs.begin(), bs.end() - 1), hi(bs.begin() + 1, bs.end());
+    std::vector<int32_t> lohi;
+    int64_t rows = pl.n_slots;
+    for (;;) {
+      std::vector<int32_t> l0, h0;
+      int64_t next = rows;
+      for (int64_t k = 0; k < nbad; ++k) {
+        if (hi[k] - lo[k] <= FIX_CHUNK) continue;
+        const int64_t first = next;
+        for (int64_t a = lo[k]; a < hi[k]; a += FIX_CHUNK) {
+          l0.push_back((int32_t)a);
+          h0.push_back((int32_t)std::min<int64_t>(a + FIX_CHUNK, hi[k]));
+          ++next;
+        }
+        lo[k] = first;
+        hi[k] = next;
+      }
+      if (l0.empty()) break;
+      TK_REQUIRE(next < ((int64_t)1 << 31), TK_ERR_UNSUPPORTED, "fixup tree too large");
+      pl.fix_n.push_back((int64_t)l0.size());
+      lohi.insert(lohi.end(), l0.begin(), l0.end());
+      lohi.insert(lohi.end(), h0.begin(), h0.end());
+      rows = next;
     }
-    cp[nbad] = (int32_t)cs.size();
-    cs.push_back(bs[nbad]);
-    pl.n_chunks = (int64_t)cs.size() - 1;
-    pl.chunk_slot.alloc(c, 4 * cs.size());
-    pl.chunk_ptr.alloc(c, 4 * cp.size());
-    h2d(c, pl.chunk_slot.as<int32_t>(), cs.data(), cs.size());
-    h2d(c, pl.chunk_ptr.as<int32_t>(), cp.data(), cp.size());
+    pl.fix_rows = rows;
+    std::vector<int32_t> fin((size_t)2 * nbad);
+    for (int64_t k = 0; k < nbad; ++k) {
+      fin[k] = (int32_t)lo[k];
+      fin[nbad + k] = (int32_t)hi[k];
+    }
+    pl.fix_fin.alloc(c, 4 * fin.size());
+    h2d(c, pl.fix_fin.as<int32_t>(), fin.data(), fin.size());
+    if (!lohi.empty()) {
+      pl.fix_lohi.alloc(c, 4 * lohi.size());
+      h2d(c, pl.fix_lohi.as<int32_t>(), lohi.data(), lohi.size());
+    }
     c->sync();
   }
   pl.n_bad = nbad;

@@ -626,28 +626,30 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   }
 }
 
-// Sum the partial rows of every split slice in bin order, in two fixed-order
-// levels: chunks of at most FIX_CHUNK consecutive slots, then the chunks of
-// each slice (deterministic, and parallel for slices split over many bins).
-__global__ void k_fixup_chunks(const int32_t* __restrict__ chunk_slot, const float* __restrict__ partial, int khat,
-                               float* __restrict__ csum) {
-  const int k = blockIdx.x;
-  const int a = chunk_slot[k], b = chunk_slot[k + 1];
+// Sum the partial rows of every split slice in bin order, along a tree of
+// fixed shape: each level adds runs of at most FIX_CHUNK consecutive rows of
+// one slice into new rows, then each slice's last rows go to Y (deterministic,
+// and parallel however many bins a slice is split over).
+__global__ void k_fixup_level(const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, int64_t first,
+                              float* __restrict__ buf, int khat) {
+  const int64_t t = blockIdx.x;
+  const int a = lo[t], b = hi[t];
+  float* out = buf + (first + t) * khat;
   for (int c = threadIdx.x; c < khat; c += blockDim.x) {
     float s = 0.f;
-    for (int t = a; t < b; ++t) s += partial[(int64_t)t * khat + c];
-    csum[(int64_t)k * khat + c] = s;
+    for (int r = a; r < b; ++r) s += buf[(int64_t)r * khat + c];
+    out[c] = s;
   }
 }
 
-__global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ chunk_ptr,
-                        const float* __restrict__ csum, int khat, float* __restrict__ Y) {
-  const int k = blockIdx.x;
-  const int a = chunk_ptr[k], b = chunk_ptr[k + 1];
+__global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ fin, int64_t nbad,
+                        const float* __restrict__ buf, int khat, float* __restrict__ Y) {
+  const int64_t k = blockIdx.x;
+  const int a = fin[k], b = fin[nbad + k];
   const int64_t row = bad_row[k];
   for (int c = threadIdx.x; c < khat; c += blockDim.x) {
     float s = 0.f;
-    for (int t = a; t < b; ++t) s += csum[(int64_t)t * khat + c];
+    for (int r = a; r < b; ++r) s += buf[(int64_t)r * khat + c];
     Y[row * khat + c] = s;
   }
 }
@@ -761,8 +763,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   a.khat = (int)pl.khat;
   a.val = lay_val;
   a.Y = Y;
-  ensure(c, c->partial,
-         sizeof(float) * (size_t)((pl.n_slots > 0 ? pl.n_slots : 1) + pl.n_chunks) * (size_t)pl.khat);
+  ensure(c, c->partial, sizeof(float) * (size_t)std::max<int64_t>(pl.fix_rows, 1) * (size_t)pl.khat);
   a.partial = c->partial.as<float>();
   a.P = pl.P;
   if (m == 0) {
@@ -815,13 +816,19 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   if (c->ev_ttm[1]) TK_HIP(hipEventRecord(c->ev_ttm[1], c->stream));
   if (pl.n_bad > 0) {
-    const size_t nps = (size_t)(pl.n_slots > 0 ? pl.n_slots : 1) * (size_t)pl.khat;
-    float* csum = c->partial.as<float>() + nps;
-    hipLaunchKernelGGL(k_fixup_chunks, dim3((unsigned)pl.n_chunks), dim3(128), 0, c->stream,
-                       pl.chunk_slot.as<int32_t>(), c->partial.as<float>(), (int)pl.khat, csum);
-    TK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_fixup, dim3((unsigned)pl.n_bad), dim3(128), 0, c->stream, pl.bad_row.as<int32_t>(),
-                       pl.chunk_ptr.as<int32_t>(), csum, (int)pl.khat, Y);
+    const int thr = pl.khat > 128 ? 256 : 128;
+    float* buf = c->partial.as<float>();
+    int64_t first = pl.n_slots, off = 0;
+    for (int64_t nl : pl.fix_n) {
+      const int32_t* lohi = pl.fix_lohi.as<int32_t>() + off;
+      hipLaunchKernelGGL(k_fixup_level, dim3((unsigned)nl), dim3(thr), 0, c->stream, lohi, lohi + nl, first, buf,
+                         (int)pl.khat);
+      TK_CHECK_LAUNCH();
+      first += nl;
+      off += 2 * nl;
+    }
+    hipLaunchKernelGGL(k_fixup, dim3((unsigned)pl.n_bad), dim3(thr), 0, c->stream, pl.bad_row.as<int32_t>(),
+                       pl.fix_fin.as<int32_t>(), pl.n_bad, buf, (int)pl.khat, Y);
     TK_CHECK_LAUNCH();
   }
 }
