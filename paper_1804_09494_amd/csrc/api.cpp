@@ -22,7 +22,8 @@ namespace tk {
 void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16);
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode);
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
-                 int* flag_dev, bool check_flag);
+                 int* flag_dev, bool deferred);
+void complete_factor(Ctx* c, int n);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
 void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk_mem mem);
 void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* F, float* dcore, float* const* dF,
@@ -65,7 +66,8 @@ struct EventPool {
   hipEvent_t next() {
     if (used == ev.size()) {
       hipEvent_t e;
-      TK_HIP(hipEventCreate(&e));
+      // timing only: no system-scope fence (its cache write-back costs ~5 us of GPU time per event)
+      TK_HIP(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
       ev.push_back(e);
     }
     return ev[used++];
@@ -114,7 +116,13 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
     float* Y = c->Y.as<float>();
     // precision form: BF16 Gram operands, except in the refining last invocation
     const bool low = c->opt.prec == TK_BF16 && !(c->opt.refine && it == iters - 1);
-    for (int n = 0; n < N; ++n) {
+    // Gauss-Seidel sweeps check for a failed (rank-deficient) factor once, at
+    // the end of the invocation, instead of stopping the stream after every
+    // mode; a failure skips the later modes' factor writes and those modes are
+    // run again below, after the failed factor is completed
+    const bool defer = c->opt.sweep == TK_SWEEP_GAUSS_SEIDEL;
+    if (defer) TK_HIP(hipMemsetAsync(c->flag.as<int>() + 1, 0, sizeof(int), c->stream));
+    auto run_mode = [&](int n, bool deferred) {
       ModePlan& pl = c->plan[n];
       const int khat = (int)pl.khat;
       const int K = c->K[n];
@@ -135,8 +143,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       } else {
         // the precision form keeps the Kronecker tiles in FP32 here: BF16 factor
         // rows perturb ||G||^2 by ~1e-3, more than the residual of a
-        // well-fitting decomposition, and gave no speed-up (the TTM-chain is
-        // bound by gather latency, not bytes)
+        // well-fitting decomposition, and gave no speed-up
         ttm_chain(c, n, Y, false);
       }
       c->ev_ttm[0] = c->ev_ttm[1] = nullptr;
@@ -151,8 +158,21 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       double* VK = lam_k + 64;
       eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK, n);
       hipEvent_t t3 = mark("eig", t2);
-      form_factor(c, n, Y, pl.L_nz, khat, lam_k, VK, c->flag.as<int>(), true);
+      form_factor(c, n, Y, pl.L_nz, khat, lam_k, VK, c->flag.as<int>(), deferred);
       mark("factor", t3);
+    };
+    for (int n = 0; n < N; ++n) run_mode(n, defer);
+    if (defer) {
+      int failed = 0;
+      d2h(c, &failed, c->flag.as<int>() + 1, 1);
+      c->sync();
+      if (failed > 0) {
+        const int n0 = failed - 1;
+        if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
+        complete_factor(c, n0);
+        TK_HIP(hipMemsetAsync(c->flag.as<int>() + 1, 0, sizeof(int), c->stream));
+        for (int n = n0 + 1; n < N; ++n) run_mode(n, false);
+      }
     }
     // core and fit from the last mode (valid for Gauss-Seidel: Y_(N) used the final factors)
     hipEvent_t t4 = pool.next();

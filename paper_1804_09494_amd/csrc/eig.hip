@@ -86,6 +86,19 @@ __device__ __forceinline__ double row16_sum(double x) {
   return x;
 }
 
+// row16_sum of several independent values, stage by stage (the DPP chains overlap)
+template <int NV>
+__device__ __forceinline__ void row16_sum_n(double (&x)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_mov<0xB1>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_mov<0x4E>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_mov<0x141>(x[v]);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) x[v] += dpp_mov<0x140>(x[v]);
+}
+
 __device__ __forceinline__ double lane_val(double x, int l) {   // x of lane l (l wave-uniform)
   const long long b = __double_as_longlong(x);
   const int lo = __builtin_amdgcn_readlane((int)(unsigned)(b & 0xffffffffLL), l);
@@ -517,32 +530,9 @@ __device__ __forceinline__ void reflector(const double (&x)[2], int j0, int n, d
   }
 }
 
-// Eigenvalues of (d, e) below four points: q <- d_i - x - e_i^2 / q with a
-// Newton-refined hardware reciprocal (two FMAs after the estimate).
-__device__ __forceinline__ void sturm_count4(const double* d, const double* e2, int n, const double (&x)[4],
-                                             double pivmin, int (&cnt)[4]) {
-  double q[4];
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    q[u] = d[0] - x[u];
-    if (fabs(q[u]) < pivmin) q[u] = -pivmin;
-    cnt[u] = q[u] < 0.0;
-  }
-  for (int i = 1; i < n; ++i) {
-    const double di = d[i], ei = e2[i - 1];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      double r = __builtin_amdgcn_rcp(q[u]);
-      r = fma(fma(-q[u], r, 1.0), r, r);
-      r = fma(fma(-q[u], r, 1.0), r, r);
-      q[u] = fma(-ei, r, di - x[u]);
-      if (fabs(q[u]) < pivmin) q[u] = -pivmin;
-      cnt[u] += q[u] < 0.0;
-    }
-  }
-}
-
-// One Sturm count with the same arithmetic as sturm_count4.
+// Sturm counts for the small kernel: q <- d_i - x - e_i^2 / q with a
+// Newton-refined hardware reciprocal (two steps after the estimate).
+// One Sturm count.
 __device__ __forceinline__ int sturm_count1(const double* d, const double* e2, int n, double x, double pivmin) {
   double q = d[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
@@ -556,6 +546,31 @@ __device__ __forceinline__ int sturm_count1(const double* d, const double* e2, i
     cnt += q < 0.0;
   }
   return cnt;
+}
+
+// Two Sturm counts, interleaved, with the same arithmetic as sturm_count1.
+__device__ __forceinline__ void sturm_count2r(const double* d, const double* e2, int n, double x0, double x1,
+                                              double pivmin, int& c0, int& c1) {
+  double q0 = d[0] - x0, q1 = d[0] - x1;
+  if (fabs(q0) < pivmin) q0 = -pivmin;
+  if (fabs(q1) < pivmin) q1 = -pivmin;
+  c0 = q0 < 0.0;
+  c1 = q1 < 0.0;
+#pragma unroll 4
+  for (int i = 1; i < n; ++i) {
+    const double di = d[i], ei = e2[i - 1];
+    double r0 = __builtin_amdgcn_rcp(q0), r1 = __builtin_amdgcn_rcp(q1);
+    r0 = fma(fma(-q0, r0, 1.0), r0, r0);
+    r1 = fma(fma(-q1, r1, 1.0), r1, r1);
+    r0 = fma(fma(-q0, r0, 1.0), r0, r0);
+    r1 = fma(fma(-q1, r1, 1.0), r1, r1);
+    q0 = fma(-ei, r0, di - x0);
+    q1 = fma(-ei, r1, di - x1);
+    if (fabs(q0) < pivmin) q0 = -pivmin;
+    if (fabs(q1) < pivmin) q1 = -pivmin;
+    c0 += q0 < 0.0;
+    c1 += q1 < 0.0;
+  }
 }
 
 __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __restrict__ G, int n, int K, int Kout,
@@ -758,17 +773,20 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
   glo -= widen;
   ghi += widen;
 
-  // 2. multisection, 16 lanes x 4 points per eigenvalue (65 sub-intervals per
+  // 2. multisection, 16 lanes x 2 points per eigenvalue (33 sub-intervals per
   // round) until the interval is below 1e-11 of the spectrum's scale: inverse
-  // iteration needs no more, and the eigenvalues only scale U's columns
+  // iteration needs no more, and the eigenvalues only scale U's columns.  Two
+  // interleaved recurrences per lane: a Sturm step is a chain of dependent
+  // FP64 operations, so four points per lane cost twice the time of two for
+  // one more bit per round.
   {
-    const int MS = 16, NP = 64;
     const int g = tid >> 4, q = tid & 15;
     const int gbase = lane & ~15;
     const unsigned long long gmask = 0xFFFFULL << gbase;
     const double tol = 1e-11 * fmax(tnorm, pivmin);
     const bool act = g < K;
     const int idx = n - 1 - g;
+    constexpr int NP = 32;
     // joint first round: one point per thread over the whole interval serves
     // every eigenvalue at once (the partial-product buffer is free by now)
     int* cnt0 = reinterpret_cast<int*>(part);
@@ -782,29 +800,28 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     }
     double a = t0 < 0 ? glo : glo + h0 * (double)(t0 + 1);
     double b = t0 >= EIG_THREADS - 1 ? ghi : glo + h0 * (double)(t0 + 2);
-    int rounds = 1;
-    for (double wd = h0; wd > tol && rounds < 24; wd /= (double)(NP + 1)) ++rounds;
+    int rounds = 0;
+    for (double wd = h0; wd > tol && rounds < 32; wd /= (double)(NP + 1)) ++rounds;
     for (int r = 0; r < rounds; ++r) {
       const double h = (b - a) / (double)(NP + 1);
-      double x[4];
-      int cnt[4] = {0, 0, 0, 0};
-#pragma unroll
-      for (int u = 0; u < 4; ++u) x[u] = a + h * (double)(4 * q + u + 1);
-      if (act) sturm_count4(d, e2, n, x, pivmin, cnt);
-      int P = 0;
-#pragma unroll
-      for (int u = 0; u < 4; ++u) P += __popcll(__ballot(cnt[u] <= idx) & gmask);
+      const double x0 = a + h * (double)(2 * q + 1), x1 = a + h * (double)(2 * q + 2);
+      int c0 = 0, c1 = 0;
+      if (act) sturm_count2r(d, e2, n, x0, x1, pivmin, c0, c1);
+      const int P = __popcll(__ballot(c0 <= idx) & gmask) + __popcll(__ballot(c1 <= idx) & gmask);
       const double na = P == 0 ? a : a + h * (double)P;
       const double nb = P == NP ? b : a + h * (double)(P + 1);
       a = na;
       b = nb;
     }
-    (void)MS;
     if (act && q == 0) lam[g] = 0.5 * (a + b);
   }
   __syncthreads();
 
-  // 3. inverse iteration (as in the general kernel)
+  // 3. inverse iteration (as in the general kernel), one lane per vector.  The
+  // recurrences are sequential, so their operands are loaded in chunks of
+  // eight steps ahead of use (one LDS round trip per chunk instead of one
+  // per step), the pivot choice is a select, and divisions are a
+  // Newton-refined reciprocal.
   const double tiny = eps * fmax(tnorm, pivmin);
   for (int j = tid; j < K; j += EIG_THREADS) {
     double lj = lam[j];
@@ -816,68 +833,88 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
     double* ml = u2 + n;
     double* pv = ml + n;
     double* z = Z + (int64_t)j * n;
-    // operands of step i+1 are loaded while step i computes (one lane per
-    // vector: nothing else hides the LDS latency)
+    constexpr int CH = 8;
+    auto rcp = [](double x) {
+      double r = __builtin_amdgcn_rcp(x);
+      r = fma(fma(-x, r, 1.0), r, r);
+      return fma(fma(-x, r, 1.0), r, r);
+    };
+    // LU factorisation with partial pivoting of T - lj I
     double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
-    double c_n = e[0], nd_n = n > 1 ? d[1] : 0.0, ns_n = n > 2 ? e[1] : 0.0;
-    for (int i = 0; i < n - 1; ++i) {
-      const double c = c_n, nd = nd_n - lj, ns = i + 1 < n - 1 ? ns_n : 0.0;
-      if (i + 1 < n - 1) {
-        c_n = e[i + 1];
-        nd_n = d[i + 2];
-        ns_n = i + 2 < n - 1 ? e[i + 2] : 0.0;
+    for (int i0 = 0; i0 < n - 1; i0 += CH) {
+      double ce[CH], cd[CH], cs[CH];
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = min(i0 + u, n - 2);
+        ce[u] = e[i];
+        cd[u] = d[i + 1];
+        cs[u] = i + 1 < n - 1 ? e[i + 1] : 0.0;
       }
-      if (fabs(c) > fabs(a0)) {
-        const double mlt = a0 / c;
-        ui[i] = 1.0 / c; u1[i] = nd; u2[i] = ns; ml[i] = mlt; pv[i] = 1.0;
-        a0 = a1 - mlt * nd;
-        a1 = a2 - mlt * ns;
-      } else {
-        if (a0 == 0.0) a0 = tiny;
-        const double mlt = c / a0;
-        ui[i] = 1.0 / a0; u1[i] = a1; u2[i] = a2; ml[i] = mlt; pv[i] = 0.0;
-        a0 = nd - mlt * a1;
-        a1 = ns - mlt * a2;
+#pragma unroll
+      for (int u = 0; u < CH; ++u) {
+        const int i = i0 + u;
+        if (i >= n - 1) break;
+        const double c = ce[u], nd = cd[u] - lj, ns = cs[u];
+        const bool sw = fabs(c) > fabs(a0);
+        const double p0 = sw ? c : (a0 == 0.0 ? tiny : a0);
+        const double r = rcp(p0);
+        const double mlt = (sw ? a0 : c) * r;
+        const double y1 = sw ? nd : a1, y2 = sw ? ns : a2;   // the pivot row's entries
+        const double x1 = sw ? a1 : nd, x2 = sw ? a2 : ns;   // the other row's
+        ui[i] = r; u1[i] = y1; u2[i] = y2; ml[i] = mlt; pv[i] = sw ? 1.0 : 0.0;
+        a0 = x1 - mlt * y1;
+        a1 = x2 - mlt * y2;
+        a2 = 0.0;
       }
-      a2 = 0.0;
     }
     if (a0 == 0.0) a0 = tiny;
-    ui[n - 1] = 1.0 / a0; u1[n - 1] = 0.0; u2[n - 1] = 0.0; ml[n - 1] = 0.0; pv[n - 1] = 0.0;
+    ui[n - 1] = rcp(a0); u1[n - 1] = 0.0; u2[n - 1] = 0.0; ml[n - 1] = 0.0; pv[n - 1] = 0.0;
     for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
     for (int it = 0; it < 2; ++it) {
+      // forward elimination with the row interchanges
       double cur = z[0];
-      double nx_n = n > 1 ? z[1] : 0.0, ml_n = ml[0], pv_n = pv[0];
-      for (int i = 0; i < n - 1; ++i) {
-        const double nx = nx_n, mi = ml_n, pi = pv_n;
-        if (i + 2 < n) {
-          nx_n = z[i + 2];
-          ml_n = ml[i + 1];
-          pv_n = pv[i + 1];
+      for (int i0 = 0; i0 < n - 1; i0 += CH) {
+        double cz[CH], cm[CH], cp[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = min(i0 + u, n - 2);
+          cz[u] = z[i + 1];
+          cm[u] = ml[i];
+          cp[u] = pv[i];
         }
-        if (pi != 0.0) {
-          z[i] = nx;
-          cur = cur - mi * nx;
-        } else {
-          z[i] = cur;
-          cur = nx - mi * cur;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = i0 + u;
+          if (i >= n - 1) break;
+          const double nx = cz[u], mi = cm[u];
+          const bool sw = cp[u] != 0.0;
+          z[i] = sw ? nx : cur;
+          cur = sw ? fma(-mi, nx, cur) : fma(-mi, cur, nx);
         }
       }
       z[n - 1] = cur;
+      // back substitution with U (three diagonals), then normalise
       double z1 = 0.0, z2 = 0.0, nrm = 0.0;
-      double zi_n = z[n - 1], u1_n = u1[n - 1], u2_n = u2[n - 1], ui_n = ui[n - 1];
-      for (int i = n - 1; i >= 0; --i) {
-        const double zi = zi_n, a = u1_n, b = u2_n, r = ui_n;
-        if (i > 0) {
-          zi_n = z[i - 1];
-          u1_n = u1[i - 1];
-          u2_n = u2[i - 1];
-          ui_n = ui[i - 1];
+      for (int i0 = n - 1; i0 >= 0; i0 -= CH) {
+        double cz[CH], c1[CH], c2[CH], cr[CH];
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = max(i0 - u, 0);
+          cz[u] = z[i];
+          c1[u] = u1[i];
+          c2[u] = u2[i];
+          cr[u] = ui[i];
         }
-        const double s = (zi - a * z1 - b * z2) * r;
-        z[i] = s;
-        z2 = z1;
-        z1 = s;
-        nrm += s * s;
+#pragma unroll
+        for (int u = 0; u < CH; ++u) {
+          const int i = i0 - u;
+          if (i < 0) break;
+          const double sv = (cz[u] - c1[u] * z1 - c2[u] * z2) * cr[u];
+          z[i] = sv;
+          z2 = z1;
+          z1 = sv;
+          nrm += sv * sv;
+        }
       }
       nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
       for (int i = 0; i < n; ++i) z[i] *= nrm;
@@ -885,45 +922,83 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
   }
   __syncthreads();
 
-  // 4. back-transformation: half a wave per vector, the vector in registers
+  // 4. back-transformation: half a wave per vector, every half-wave's vectors
+  // (K <= 16: at most two) in registers and reduced together, so the
+  // latency of one reflector's reductions is paid once for both; the next
+  // reflector's row is loaded while the current one is applied
   {
     const int half = lane >> 5, hl = lane & 31;
-    for (int j0 = 0; j0 < K; j0 += 2 * EIG_WAVES) {
-      const int j = j0 + 2 * wave + half;
-      const bool on = j < K;
-      double* zr = Z + (int64_t)(on ? j : 0) * n;
-      double z[4];
+    constexpr int NV = 2;
+    double z[NV][4];
+    bool on[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const int j = 2 * wave + half + 2 * EIG_WAVES * v;
+      on[v] = j < K;
+      const double* zr = Z + (int64_t)(on[v] ? j : 0) * n;
 #pragma unroll
       for (int c = 0; c < 4; ++c) {
         const int i = hl + 32 * c;
-        z[c] = (on && i < n) ? zr[i] : 0.0;
+        z[v][c] = (on[v] && i < n) ? zr[i] : 0.0;
       }
-      for (int k = n - 3; k >= 0; --k) {
-        const double t = tau[k];
-        if (t == 0.0) continue;
-        const double sc = scl[k];
-        const double* rowk = A + k * S;
-        double vv[4], s = 0.0;
+    }
+    int ic[4];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int i = hl + 32 * c;
-          const double x = rowk[i < n ? i : n - 1];
-          vv[c] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? x * sc : 0.0);
-          s += vv[c] * z[c];
-        }
-        // sum over this half-wave: rows of 16 lanes, then the half's two rows
-        s = row16_sum(s);
-        const double s0 = lane_val(s, 0) + lane_val(s, 16), s1 = lane_val(s, 32) + lane_val(s, 48);
-        s = t * (half ? s1 : s0);
+    for (int c = 0; c < 4; ++c) ic[c] = min(hl + 32 * c, n - 1);
+    // reflector k's row, tau and scale are loaded one step ahead: LDS returns
+    // in order, so a wait for this step's operands never waits for the next
+    double xn[4], tn = 0.0, sn = 0.0;
+    if (n >= 3) {
 #pragma unroll
-        for (int c = 0; c < 4; ++c) z[c] -= s * vv[c];
+      for (int c = 0; c < 4; ++c) xn[c] = A[(n - 3) * S + ic[c]];
+      tn = tau[n - 3];
+      sn = scl[n - 3];
+    }
+    for (int k = n - 3; k >= 0; --k) {
+      double x[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) x[c] = xn[c];
+      const double t = tn, sc = sn;
+      if (k > 0) {
+#pragma unroll
+        for (int c = 0; c < 4; ++c) xn[c] = A[(k - 1) * S + ic[c]];
+        tn = tau[k - 1];
+        sn = scl[k - 1];
       }
-      if (on)
+      if (t == 0.0) continue;
+      double vv[4], sv[NV];
 #pragma unroll
-        for (int c = 0; c < 4; ++c) {
-          const int i = hl + 32 * c;
-          if (i < n) zr[i] = z[c];
-        }
+      for (int c = 0; c < 4; ++c) {
+        const int i = hl + 32 * c;
+        vv[c] = i == k + 1 ? 1.0 : ((i > k + 1 && i < n) ? x[c] * sc : 0.0);
+      }
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc += vv[c] * z[v][c];
+        sv[v] = acc;
+      }
+      // the vectors' row sums stage by stage, interleaved
+      row16_sum_n<NV>(sv);
+      // each half-wave's sum: its two rows of 16 lanes
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const double s0 = lane_val(sv[v], 0) + lane_val(sv[v], 16), s1 = lane_val(sv[v], 32) + lane_val(sv[v], 48);
+        const double sh = t * (half ? s1 : s0);
+#pragma unroll
+        for (int c = 0; c < 4; ++c) z[v][c] -= sh * vv[c];
+      }
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      if (!on[v]) continue;
+      double* zr = Z + (int64_t)(2 * wave + half + 2 * EIG_WAVES * v) * n;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const int i = hl + 32 * c;
+        if (i < n) zr[i] = z[v][c];
+      }
     }
   }
   __syncthreads();

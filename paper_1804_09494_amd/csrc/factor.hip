@@ -156,7 +156,9 @@ __global__ __launch_bounds__(256) void k_rinv_mfma(double* __restrict__ U, int64
                                                    const int32_t* __restrict__ row_slice,
                                                    const int32_t* __restrict__ label, double* __restrict__ F64,
                                                    float* __restrict__ F32, int kp32, uint16_t* __restrict__ F16,
-                                                   int kp16) {
+                                                   int kp16, const int* __restrict__ abort) {
+  // FINAL: an earlier mode of this invocation failed; keep this factor as it was
+  if (FINAL && abort && *abort) return;
   __shared__ double red[256];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i16 = lane & 15, q = lane >> 4;
@@ -381,7 +383,8 @@ __global__ void k_make_w(const double* __restrict__ VK, const double* __restrict
 // same rows at their storage labels.
 __global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
                                  const int32_t* __restrict__ label, double* __restrict__ F64, float* __restrict__ F32,
-                                 int kp32, uint16_t* __restrict__ F16, int kp16) {
+                                 int kp32, uint16_t* __restrict__ F16, int kp16, const int* __restrict__ abort) {
+  if (abort && *abort) return;   // an earlier mode of this invocation failed
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R * K; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / K;
     const int k = (int)(i - r * K);
@@ -472,10 +475,33 @@ static void complete_on_host(Ctx* c, int n) {
   c->sync();
 }
 
+void complete_factor(Ctx* c, int n);
+
+// zero a buffer (2-byte units) unless an earlier mode of this invocation failed
+__global__ void k_clear_unless(uint16_t* __restrict__ p, int64_t n16, const int* __restrict__ abort) {
+  if (*abort) return;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0;
+}
+
+// flag[0]: this mode's failure flag; flag[1]: 1 + the first failed mode of the invocation
+__global__ void k_flag_record(int* flag, int n) {
+  if (flag[0] && !flag[1]) flag[1] = n + 1;
+}
+
 // New factor n from Y (R x khat) and the leading eigenpairs (lam_k, VK).
 // Returns true when the completion path ran.
+// deferred = false: the failure check reads flag_dev[0] on the host and
+// completes the factor at once.
+// deferred = true (a Gauss-Seidel invocation that checks once at its end):
+// flag_dev[1] = 1 + the first failed mode of the invocation, or 0.  Once it is
+// set, this call leaves factor n as it was (the caller runs the mode again
+// after completing the failed factor); a failure of this mode sets it when
+// R >= K, and is completed at once when R < K.
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
-                 int* flag_dev, bool check_flag) {
+                 int* flag_dev, bool deferred) {
+  const int* abort = deferred ? flag_dev + 1 : nullptr;
+  const bool check_flag = !deferred || R < c->K[n];
   const int K = c->K[n];
   TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "factor step: rank above 32");
   const bool mfma = K <= 16;
@@ -498,9 +524,19 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   // only when something else may have written them (tk_set_factor, completion)
   auto clear_factor = [&]() {
     if (!c->fac_dirty[n]) return;
-    TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
-    TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
-    TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+    if (abort) {
+      // deferred check: a later pass may have to keep this factor as it was
+      for (Buf* b : {&c->F64[n], &c->F32[n], &c->F16[n]}) {
+        const int64_t n16 = (int64_t)(b->bytes() / 2);
+        hipLaunchKernelGGL(k_clear_unless, dim3(grid_for(n16, 256, 4096)), dim3(256), 0, c->stream,
+                           b->as<uint16_t>(), n16, abort);
+        TK_CHECK_LAUNCH();
+      }
+    } else {
+      TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
+      TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
+      TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
+    }
     c->fac_dirty[n] = false;
   };
   auto reduce_chol = [&]() {
@@ -524,13 +560,13 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     TK_CHECK_LAUNCH();
     reduce_chol();
     hipLaunchKernelGGL(k_rinv_mfma<false>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part, nullptr, nullptr,
-                       nullptr, nullptr, 0, nullptr, 0);
+                       nullptr, nullptr, 0, nullptr, 0, nullptr);
     TK_CHECK_LAUNCH();
     reduce_chol();
     clear_factor();
     hipLaunchKernelGGL(k_rinv_mfma<true>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part,
                        pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
-                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
+                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n], abort);
     TK_CHECK_LAUNCH();
   } else if (R > 0) {
     size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
@@ -546,22 +582,32 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     clear_factor();
     hipLaunchKernelGGL(k_scatter_factor, dim3(grid_for(R * K, 256)), dim3(256), 0, c->stream, U, R, K,
                        pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
-                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n]);
+                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n], abort);
     TK_CHECK_LAUNCH();
   } else {
     clear_factor();
   }
-  if (!check_flag && R >= K) return false;
-  int hflag = 0;
-  d2h(c, &hflag, flag_dev, 1);
+  if (!check_flag) {
+    hipLaunchKernelGGL(k_flag_record, dim3(1), dim3(1), 0, c->stream, flag_dev, n);
+    TK_CHECK_LAUNCH();
+    return false;
+  }
+  int hflag[2] = {0, 0};
+  d2h(c, hflag, flag_dev, deferred ? 2 : 1);
   c->sync();
-  if (hflag || R < K) {
+  if (hflag[1]) return false;   // an earlier mode failed: this mode runs again later
+  if (hflag[0] || R < K) {
     if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
-    complete_on_host(c, n);
-    c->fac_dirty[n] = true;   // completion may use rows of empty slices
+    complete_factor(c, n);
     return true;
   }
   return false;
+}
+
+// Complete factor n (rank-deficient penultimate matrix) on the host.
+void complete_factor(Ctx* c, int n) {
+  complete_on_host(c, n);
+  c->fac_dirty[n] = true;   // completion may use rows of empty slices
 }
 
 }  // namespace tk

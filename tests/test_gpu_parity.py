@@ -291,6 +291,33 @@ def test_rank_deficient_completion(tk):
     np.testing.assert_allclose(F.T @ F, np.eye(4), atol=1e-12)
 
 
+def test_rank_deficient_mid_sweep_matches_oracle(tk):
+    # mode-0 unfolding of rank 1 with 8 nonempty slices and K_0 = 3: the failure
+    # is found at the end of the invocation, mode 0 is completed and modes 1
+    # and 2 run again with it.  Completed columns are orthogonal to the range of
+    # T_(0), so modes 1 and 2 (and the fit) are unique and must match the oracle.
+    rng = np.random.default_rng(5)
+    a = rng.uniform(0.5, 1.5, 8)
+    B = rng.standard_normal((6, 5))
+    i0, i1, i2 = np.meshgrid(np.arange(8), np.arange(6), np.arange(5), indexing="ij")
+    idx = [i0.ravel().astype(np.int32), i1.ravel().astype(np.int32), i2.ravel().astype(np.int32)]
+    vals = (a[i0] * B[i1, i2]).ravel().astype(np.float32)
+    dims, ranks = (8, 6, 5), (3, 2, 2)
+    ctx = _load(tk, idx, vals, dims, ranks)
+    F0 = synth.orthonormal_init(11, dims, ranks)
+    for n in range(3):
+        ctx.set_factor(n, F0[n])
+    fits = ctx.hooi_iterate(2)
+    o = hooi.hooi(idx, vals.astype(np.float64), dims, F0, ranks, 2)
+    for n in range(3):
+        F = ctx.get_factor(n)
+        np.testing.assert_allclose(F.T @ F, np.eye(ranks[n]), atol=1e-12)
+    assert hooi.projector_distance(ctx.get_factor(0)[:, :1], o["factors"][0][:, :1]) <= 1e-5
+    for n in (1, 2):
+        assert hooi.projector_distance(ctx.get_factor(n), o["factors"][n]) <= 1e-5, n
+    np.testing.assert_allclose(fits, o["fits"], atol=1e-6)
+
+
 # ---- completion (differentiation form) ----------------------------------------------------------
 
 def test_completion_eval_and_adjoint_match_oracle(tk):
