@@ -218,9 +218,9 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
 // the four waves streams a contiguous quarter of the bin in blocks of 16
 // elements from the LDS copy of the bin.  When a slice ends its accumulator
 // goes to the bin's LDS rows; the at most two slices a wave shares with its
-// neighbours are parked in LDS and added in wave order after a barrier.
-// No atomics: the result is deterministic.
-constexpr int TTM3_SLOT = 256;
+// neighbours keep their partial rows in registers and are added to the
+// (zeroed) LDS rows in wave order after the main loop.  No atomics: the result
+// is deterministic.
 constexpr int TTM3_RING = 4;   // blocks of 16 elements with gathers in flight per wave
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -249,9 +249,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   int* sib = sia + Epad;                                    // Epad
   float* sv = reinterpret_cast<float*>(sib + Epad);         // Epad
   float* tiles = sv + Epad;                                 // 4 waves x 512: F_a and F_b rows of one block
-  float* slots = tiles + 4 * 512;                           // 4 waves x 2 x 256
-  int* winfo = reinterpret_cast<int*>(slots + 8 * TTM3_SLOT);  // 4 waves x 2
-  float* rows = reinterpret_cast<float*>(winfo + 8);        // nseg x khat: the bin's rows of Y
+  float* rows = tiles + 4 * 512;                            // nseg x khat: the bin's rows of Y
   const int khat = A.khat;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = uni(tid >> 6);
@@ -275,10 +273,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
       reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
     }
   }
-  if (lane == 0) {
-    winfo[2 * wave] = -1;
-    winfo[2 * wave + 1] = -1;
-  }
+  for (int i = tid; i < nseg * khat; i += 256) rows[i] = 0.f;   // shared rows are summed into
   __syncthreads();
 
   // per-wave state below is uniform (scalar registers, scalar branches)
@@ -287,6 +282,11 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   const int k = lane >> 4, cix = lane & 15;
   const bool bok = cix < kb;
   float* tile = tiles + wave * 512;
+  // slices a wave shares with a neighbour keep their partial rows in
+  // registers (Lp: begun by an earlier wave; C: continued by a later one)
+  floatx4_t C = {0.f, 0.f, 0.f, 0.f}, Lp = {0.f, 0.f, 0.f, 0.f};
+  bool has_left = false, has_right = false;
+  int left_sg = 0, right_sg = 0;
   if (cs < ce) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -296,7 +296,6 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
     int sg = lo;
     int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
     int seg_hi = uni(send[sg]);
-    floatx4_t C = {0.f, 0.f, 0.f, 0.f};
     auto flush = [&]() {
       const bool left = seg_lo < cs, right = seg_hi > ce;
       if (!left && !right) {
@@ -308,14 +307,14 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
           for (int r = 0; r < 4; ++r)
             if (4 * k + r < ka) dst[4 * k + r + ka * cix] = C[r];
         }
-      } else {
-        float* sl = slots + (wave * 2 + (left ? 0 : 1)) * TTM3_SLOT;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sl[r * 64 + lane] = C[r];
-        if (lane == 0) {
-          if (left) winfo[2 * wave] = sg;
-          if (right) winfo[2 * wave + 1] = sg;
-        }
+      } else if (right) {   // the last slice of the quarter: stays in C
+        has_right = true;
+        right_sg = sg;
+        return;
+      } else {              // the first slice of the quarter, begun by an earlier wave
+        Lp = C;
+        has_left = true;
+        left_sg = sg;
       }
       C = floatx4_t{0.f, 0.f, 0.f, 0.f};
     };
@@ -403,23 +402,22 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
     }
     flush();  // the slice open at the end of this wave's quarter
   }
-  __syncthreads();
-  // add the parked partials of shared slices in wave order
-  {
-    const int r = tid >> 6, ln = tid & 63;
-    const int i = 4 * (ln >> 4) + r, j = ln & 15;
-    const bool valid = i < ka && j < kb;
-    float acc = 0.f;
-    for (int w = 0; w < 4; ++w) {
-      const int fl = winfo[2 * w], fr = winfo[2 * w + 1];
-      if (fl >= 0) {
-        acc += slots[(w * 2 + 0) * TTM3_SLOT + tid];
-        if (fr != fl) {
-          if (valid) rows[fl * khat + i + ka * j] = acc;
-          acc = 0.f;
-        }
+  // partial rows of slices shared between waves, added in wave order
+  for (int w = 0; w < 4; ++w) {
+    __syncthreads();
+    if (wave == w && bok) {
+      if (has_left) {
+        float* dst = rows + left_sg * khat;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k + r < ka) dst[4 * k + r + ka * cix] += Lp[r];
       }
-      if (fr >= 0 && fr != fl) acc = slots[(w * 2 + 1) * TTM3_SLOT + tid];
+      if (has_right) {
+        float* dst = rows + right_sg * khat;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k + r < ka) dst[4 * k + r + ka * cix] += C[r];
+      }
     }
   }
   __syncthreads();
@@ -775,8 +773,8 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   if (ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
-    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * (4 * 512 + 8 * TTM3_SLOT) +
-                       sizeof(int) * 8 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
+    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * 4 * 512 +
+                       sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     if (H16)
       hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
