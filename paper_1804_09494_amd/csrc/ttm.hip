@@ -225,6 +225,16 @@ constexpr int TTM3_RING = 4;   // blocks of 16 elements with gathers in flight p
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Order LDS writes of some lanes before reads of others in the same wave.  The
+// hardware keeps a wave's LDS operations in order; this stops the compiler
+// from treating the lanes as independent threads (it could otherwise forward
+// a lane's own earlier read past another lane's write).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float4 bf16x2_lo_hi(uint32_t x, uint32_t y) {
   return make_float4(__uint_as_float(x << 16), __uint_as_float(x & 0xffff0000u), __uint_as_float(y << 16),
                      __uint_as_float(y & 0xffff0000u));
@@ -358,6 +368,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
         reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
             __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
       }
+      wave_lds_sync();
       // operand layout: step u, lane l reads element 4u + l/16, column l%16
       float xa[4], xb[4];
 #pragma unroll
@@ -377,6 +388,7 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
         }
         C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
       }
+      wave_lds_sync();   // the next block's write follows these reads
     };
     // Refills are unconditional (clamped to the last staged block): every path
     // then has the same loads in flight and the compiler waits only for the
@@ -549,6 +561,7 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
                       __uint_as_float(r.x.w) * r.v);
       reinterpret_cast<u32x4*>(tile + 256)[lane] = r.y;
       reinterpret_cast<u32x4*>(tile + 512)[lane] = r.z;
+      wave_lds_sync();
       float xa[4], xb[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -572,6 +585,7 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
 #pragma unroll
         for (int q = 0; q < KC; ++q) C[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u] * cv[q], xb[u], C[q], 0, 0, 0);
       }
+      wave_lds_sync();   // the next block's write follows these reads
     };
     // refills unconditional (clamped to the last staged block) and kept in
     // issue order, so the wait before each block is for its own loads only
