@@ -117,6 +117,37 @@ def summarize_profile(d):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
+    # further counter passes of the same command (pmc_*/ directories): the
+    # average per TTM launch and per 2 GiB copy of each counter
+    lines = []
+    for sub in sorted(glob.glob(os.path.join(d, "pmc_*"))):
+        files = glob.glob(os.path.join(sub, "*counter_collection.csv"))
+        if not files:
+            continue
+        acc = {}
+        for r in csv.DictReader(open(files[0])):
+            kern = "ttm" if TTM_KERNEL in r["Kernel_Name"] else ("copy" if r["Kernel_Name"] == COPY_KERNEL else None)
+            if kern is None:
+                continue
+            key = (r["Counter_Name"], kern, int(r["Dispatch_Id"]))
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        names = sorted({k[0] for k in acc})
+        cmd = open(os.path.join(sub, "command.txt")).read().strip() if os.path.exists(
+            os.path.join(sub, "command.txt")) else ""
+        lines.append(f"pass {os.path.basename(sub)}: {cmd}")
+        for nm in names:
+            for kern in ("ttm", "copy"):
+                vals = [v for (c, k, _), v in acc.items() if c == nm and k == kern]
+                if kern == "copy":
+                    vals = [v for v in vals if v > 0.5 * max(vals, default=0)]   # the 2 GiB copies
+                if vals:
+                    lines.append(f"  {nm:36s} {kern:5s} mean {sum(vals) / len(vals):16.1f} over {len(vals)} launches")
+    if lines:
+        hdr = [f"{TTM_KERNEL} counters, c2 (68,154,792 merged nonzeros, ranks 10); 'ttm' = one launch per mode",
+               f"(mean over the launches), 'copy' = the bench's 2 GiB device copy.  source sha256 "
+               f"{_sha256(TTM_SOURCE)}", ""]
+        with open(os.path.join(out_dir, "ttm3_mfma_c2_counters.txt"), "w") as f:
+            f.write("\n".join(hdr + lines) + "\n")
 
 
 def algorithmic_bytes(m, N, R, khat, dims, ranks, n):
