@@ -25,76 +25,146 @@ constexpr int KR_S = 6;     // blocks per cycle (subspace KR_S * KR_B = 96: the 
 constexpr int KR_M = KR_B * KR_S;
 constexpr int KR_CYCLES = 4;
 
-// D[r][c] (=, or -= when SUB) sum_{i<J} A[r*lda + i] * C[i*ldc + c], c < nc
+typedef double doublex4_k __attribute__((ext_vector_type(4)));
+
+// The tall-skinny products run on the FP64 matrix cores (v_mfma_f64_16x16x4_f64:
+// lane l supplies A[i = l%16][k = l/16] and B[k = l/16][j = l%16]; register r
+// of the result holds D[l/16 + 4r][l%16]).  The k range is split over the four
+// waves of a workgroup and their tiles are summed in LDS in wave order, so
+// every result is deterministic.
+__device__ __forceinline__ doublex4_k kr_wave_sum(doublex4_k acc, double* red) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) red[r * 64 + lane] = (w == 0 ? 0.0 : red[r * 64 + lane]) + acc[r];
+    __syncthreads();
+  }
+  doublex4_k out;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[r] = red[r * 64 + lane];
+  return out;
+}
+
+// D (n x nc, ldd) = A (n x J, lda) C (J x nc, ldc), or D = S - A C when SUB
+// (S may be D itself); nc <= 16.  One workgroup per 16-row block.
 template <bool SUB>
 __global__ __launch_bounds__(256) void k_kr_nn(const double* __restrict__ A, int lda, int J,
-                                               const double* __restrict__ C, int ldc, double* __restrict__ D,
-                                               int ldd, int n, int nc) {
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (int64_t)n * nc) return;
-  const int r = (int)(idx / nc), cc = (int)(idx - (int64_t)r * nc);
-  const double* a = A + (int64_t)r * lda;
-  double s = 0.0;
-  for (int i = 0; i < J; ++i) s += a[i] * C[(int64_t)i * ldc + cc];
-  double* d = D + (int64_t)r * ldd + cc;
-  *d = SUB ? *d - s : s;
+                                               const double* __restrict__ C, int ldc, const double* S, int lds,
+                                               double* D, int ldd, int n, int nc) {
+  __shared__ double red[256];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i16 = lane & 15, q = lane >> 4;
+  const int r0 = blockIdx.x * 16;
+  const int row = r0 + i16;
+  const int Jw = ((J + 15) / 16) * 4;   // k per wave, a multiple of 4
+  const int k0 = wave * Jw, k1 = min(k0 + Jw, J);
+  doublex4_k acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int k = k0; k < k1; k += 4) {
+    const int kk = k + q;
+    const double a = (row < n && kk < k1) ? A[(int64_t)row * lda + kk] : 0.0;
+    const double b = (kk < k1 && i16 < nc) ? C[(int64_t)kk * ldc + i16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  acc = kr_wave_sum(acc, red);
+  if (wave == 0 && i16 < nc) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int rr = r0 + q + 4 * r;
+      if (rr < n) D[(int64_t)rr * ldd + i16] = SUB ? S[(int64_t)rr * lds + i16] - acc[r] : acc[r];
+    }
+  }
 }
 
-// part[wg][i*nc + c] = sum over the workgroup's rows of A[r*lda + i] * B[r*ldb + c]
+// out (J x nc, row-major) = A^T B over n rows (A: n x J, lda; B: n x nc, ldb).
+// One workgroup per 16 x 16 output tile (blockIdx.x: rows of out, blockIdx.y: columns).
 __global__ __launch_bounds__(256) void k_kr_tn(const double* __restrict__ A, int lda, int J,
-                                               const double* __restrict__ B, int ldb, int nc, int n, int rows_per_wg,
-                                               double* __restrict__ part) {
-  const int r0 = blockIdx.x * rows_per_wg, r1 = min(r0 + rows_per_wg, n);
-  const int nout = J * nc;
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-    const int i = o / nc, cc = o - i * nc;
-    double s = 0.0;
-    for (int r = r0; r < r1; ++r) s += A[(int64_t)r * lda + i] * B[(int64_t)r * ldb + cc];
-    part[(int64_t)blockIdx.x * nout + o] = s;
+                                               const double* __restrict__ B, int ldb, int nc, int n,
+                                               double* __restrict__ out) {
+  __shared__ double red[256];
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int i16 = lane & 15, q = lane >> 4;
+  const int i0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
+  const int nw = ((n + 15) / 16) * 4;   // rows per wave, a multiple of 4
+  const int s0 = wave * nw, s1 = min(s0 + nw, n);
+  const bool aok = i0 + i16 < J, bok = c0 + i16 < nc;
+  doublex4_k acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int r = s0; r < s1; r += 4) {
+    const int rr = r + q;
+    const bool rok = rr < s1;
+    const double a = (rok && aok) ? A[(int64_t)rr * lda + i0 + i16] : 0.0;
+    const double b = (rok && bok) ? B[(int64_t)rr * ldb + c0 + i16] : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+  }
+  acc = kr_wave_sum(acc, red);
+  if (wave == 0 && bok) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int ii = i0 + q + 4 * r;
+      if (ii < J) out[(int64_t)ii * nc + c0 + i16] = acc[r];
+    }
   }
 }
 
-__global__ void k_kr_sum(const double* __restrict__ part, int nparts, int cnt, double* __restrict__ out) {
-  const int o = blockIdx.x * blockDim.x + threadIdx.x;
-  if (o >= cnt) return;
-  double s = 0.0;
-  for (int p = 0; p < nparts; ++p) s += part[(int64_t)p * cnt + o];
-  out[o] = s;
-}
-
-// Cholesky of the b x b Gram A = R^T R and Rinv = R^-1; a pivot that is not
-// safely positive (no independent direction left) zeroes Rinv, and so the block.
-__global__ void k_kr_chol(const double* __restrict__ A, int b, double* __restrict__ Rinv) {
-  __shared__ double R[KR_B * KR_B], Ri[KR_B * KR_B];
-  if (threadIdx.x != 0) return;
+// Cholesky of the b x b Gram A = R^T R (b <= 16) and Rinv = R^-1, one wave; a
+// pivot that is not safely positive (no independent direction left) zeroes
+// Rinv, and so the block.
+__global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, int b, double* __restrict__ Rinv) {
+  __shared__ double R[KR_B * KR_B], X[KR_B * KR_B];
+  __shared__ int okf;
+  const int l = threadIdx.x;
+  for (int i = l; i < KR_B * KR_B; i += 64) {
+    const int r = i / KR_B, cc = i % KR_B;
+    R[i] = (r < b && cc < b) ? A[r * b + cc] : 0.0;
+  }
+  if (l == 0) okf = 1;
+  __syncthreads();
   double dmax = 0.0;
-  for (int i = 0; i < b; ++i) dmax = fmax(dmax, A[i * b + i]);
-  bool ok = dmax > 0.0;
-  for (int i = 0; i < b * b; ++i) R[i] = 0.0;
-  for (int j = 0; j < b && ok; ++j) {
-    double d = A[j * b + j];
-    for (int k = 0; k < j; ++k) d -= R[k * b + j] * R[k * b + j];
-    if (!(d > 1e-14 * dmax)) { ok = false; break; }
-    const double rjj = sqrt(d);
-    R[j * b + j] = rjj;
-    for (int i = j + 1; i < b; ++i) {
-      double s = A[j * b + i];
-      for (int k = 0; k < j; ++k) s -= R[k * b + j] * R[k * b + i];
-      R[j * b + i] = s / rjj;
+  for (int i = 0; i < b; ++i) dmax = fmax(dmax, R[i * KR_B + i]);
+  if (!(dmax > 0.0) && l == 0) okf = 0;
+  __syncthreads();
+  // R in the upper triangle, row j: R[j][j..b-1]
+  for (int j = 0; j < b && okf; ++j) {
+    const double d = R[j * KR_B + j];
+    __syncthreads();
+    if (!(d > 1e-14 * dmax)) {
+      if (l == 0) okf = 0;
+      __syncthreads();
+      break;
+    }
+    const double rjj = sqrt(d), ri = 1.0 / rjj;
+    if (l > j && l < b) R[j * KR_B + l] *= ri;
+    if (l == 0) R[j * KR_B + j] = rjj;
+    __syncthreads();
+    for (int t = l; t < KR_B * KR_B; t += 64) {
+      const int i = t / KR_B, k = t % KR_B;
+      if (i > j && k >= i && k < b) R[i * KR_B + k] -= R[j * KR_B + i] * R[j * KR_B + k];
+    }
+    __syncthreads();
+  }
+  if (!okf) {
+    for (int i = l; i < b * b; i += 64) Rinv[i] = 0.0;
+    return;
+  }
+  // column c of R^-1 by back substitution, one lane per column
+  if (l < b) {
+    const int c = l;
+    double* x = X + c * KR_B;
+    for (int i = 0; i < b; ++i) x[i] = 0.0;
+    x[c] = 1.0 / R[c * KR_B + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double s = 0.0;
+      for (int k = i + 1; k <= c; ++k) s += R[i * KR_B + k] * x[k];
+      x[i] = -s / R[i * KR_B + i];
     }
   }
-  for (int i = 0; i < b * b; ++i) Ri[i] = 0.0;
-  if (ok) {
-    for (int j = 0; j < b; ++j) {
-      Ri[j * b + j] = 1.0 / R[j * b + j];
-      for (int i = j - 1; i >= 0; --i) {
-        double s = 0.0;
-        for (int k = i + 1; k <= j; ++k) s += R[i * b + k] * Ri[k * b + j];
-        Ri[i * b + j] = -s / R[i * b + i];
-      }
-    }
+  __syncthreads();
+  for (int t = l; t < b * b; t += 64) {
+    const int i = t / b, c = t % b;
+    Rinv[t] = X[c * KR_B + i];
   }
-  for (int i = 0; i < b * b; ++i) Rinv[i] = Ri[i];
 }
 
 // Start block: columns 0..kw-1 from the warm vectors (n x kw, row-major), the
@@ -140,36 +210,39 @@ __global__ __launch_bounds__(256) void k_kr_resid(const double* __restrict__ GV,
 
 namespace {
 struct KrBufs {
-  double *Q, *GQ, *W, *part, *small, *H, *lamH, *S, *GV, *res;
-  int nwg, rows_per_wg;
+  double *Q, *GQ, *W, *W2, *small, *H, *lamH, *S, *GV, *res;
 };
 
 unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
+unsigned g16(int64_t n) { return (unsigned)((n + 15) / 16); }
 
 // out (J x nc) = A^T B over n rows
-void tn(Ctx* c, const KrBufs& b, const double* A, int lda, int J, const double* B, int ldb, int nc, int n,
-        double* out) {
-  hipLaunchKernelGGL(k_kr_tn, dim3(b.nwg), dim3(256), 0, c->stream, A, lda, J, B, ldb, nc, n, b.rows_per_wg, b.part);
-  TK_CHECK_LAUNCH();
-  hipLaunchKernelGGL(k_kr_sum, dim3(g1((int64_t)J * nc)), dim3(256), 0, c->stream, b.part, b.nwg, J * nc, out);
+void tn(Ctx* c, const double* A, int lda, int J, const double* B, int ldb, int nc, int n, double* out) {
+  hipLaunchKernelGGL(k_kr_tn, dim3(g16(J), g16(nc)), dim3(256), 0, c->stream, A, lda, J, B, ldb, nc, n, out);
   TK_CHECK_LAUNCH();
 }
 
-// Q[:, q0:q0+B] = orthonormal basis of W (three CholeskyQR passes in place, then copied)
+// D = A C (SUB: D = S - A C); nc <= 16
+template <bool SUB>
+void nn(Ctx* c, const double* A, int lda, int J, const double* C, int ldc, const double* S, int lds, double* D,
+        int ldd, int n, int nc) {
+  hipLaunchKernelGGL(k_kr_nn<SUB>, dim3(g16(n)), dim3(256), 0, c->stream, A, lda, J, C, ldc, S, lds, D, ldd, n, nc);
+  TK_CHECK_LAUNCH();
+}
+
+// Q[:, q0:q0+B] = orthonormal basis of W (three CholeskyQR passes, W and W2
+// alternating, the last one written into Q)
 void cholqr(Ctx* c, const KrBufs& b, int n, int q0) {
   double* A = b.small;              // B x B Gram
   double* Ri = b.small + KR_B * KR_B;
+  double* src = b.W;
   for (int pass = 0; pass < 3; ++pass) {
-    tn(c, b, b.W, KR_B, KR_B, b.W, KR_B, KR_B, n, A);
+    tn(c, src, KR_B, KR_B, src, KR_B, KR_B, n, A);
     hipLaunchKernelGGL(k_kr_chol, dim3(1), dim3(64), 0, c->stream, A, KR_B, Ri);
     TK_CHECK_LAUNCH();
-    double* dst = pass == 2 ? b.Q + q0 : b.GV;   // GV doubles as scratch here
-    const int ldd = pass == 2 ? KR_M : KR_B;
-    hipLaunchKernelGGL(k_kr_nn<false>, dim3(g1((int64_t)n * KR_B)), dim3(256), 0, c->stream, b.W, KR_B, KR_B, Ri,
-                       KR_B, dst, ldd, n, KR_B);
-    TK_CHECK_LAUNCH();
-    if (pass < 2) TK_HIP(hipMemcpyAsync(b.W, b.GV, sizeof(double) * (size_t)n * KR_B, hipMemcpyDeviceToDevice,
-                                        c->stream));
+    double* dst = pass == 2 ? b.Q + q0 : (src == b.W ? b.W2 : b.W);
+    nn<false>(c, src, KR_B, KR_B, Ri, KR_B, nullptr, 0, dst, pass == 2 ? KR_M : KR_B, n, KR_B);
+    src = dst;
   }
 }
 }  // namespace
@@ -179,17 +252,15 @@ void cholqr(Ctx* c, const KrBufs& b, int n, int q0) {
 void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* lam_k, double* VK, int mode) {
   TK_REQUIRE(K <= KR_B, TK_ERR_UNSUPPORTED, "Krylov eigensolve: more than 16 eigenpairs");
   KrBufs b{};
-  b.rows_per_wg = std::max(64, (int)ceil_div(n, 256));
-  b.nwg = (int)ceil_div(n, b.rows_per_wg);
   const size_t nQ = (size_t)n * KR_M;
-  const size_t need = 2 * nQ + (size_t)n * KR_B + (size_t)b.nwg * KR_M * KR_M + 4 * KR_B * KR_B + KR_M * KR_M +
-                      64 + (size_t)KR_M * KR_B + (size_t)n * KR_B + 8;
+  const size_t need = 2 * nQ + 2 * (size_t)n * KR_B + 4 * KR_B * KR_B + KR_M * KR_M + 64 + (size_t)KR_M * KR_B +
+                      (size_t)n * KR_B + 8;
   ensure(c, c->kr_work, sizeof(double) * need);
   double* p = c->kr_work.as<double>();
   b.Q = p; p += nQ;
   b.GQ = p; p += nQ;
   b.W = p; p += (size_t)n * KR_B;
-  b.part = p; p += (size_t)b.nwg * KR_M * KR_M;
+  b.W2 = p; p += (size_t)n * KR_B;
   b.small = p; p += 4 * KR_B * KR_B;
   b.H = p; p += KR_M * KR_M;
   b.lamH = p; p += 64;
@@ -218,32 +289,25 @@ void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* la
     for (int j = 0; j < KR_S; ++j) {
       const int q0 = j * KR_B, J = q0 + KR_B;
       // GQ_j = G Q_j
-      hipLaunchKernelGGL(k_kr_nn<false>, dim3(g1((int64_t)n * KR_B)), dim3(256), 0, c->stream, G, n, n, b.Q + q0,
-                         KR_M, b.GQ + q0, KR_M, n, KR_B);
-      TK_CHECK_LAUNCH();
+      nn<false>(c, G, n, n, b.Q + q0, KR_M, nullptr, 0, b.GQ + q0, KR_M, n, KR_B);
       if (j == KR_S - 1) break;
-      TK_HIP(hipMemcpy2DAsync(b.W, sizeof(double) * KR_B, b.GQ + q0, sizeof(double) * KR_M,
-                              sizeof(double) * KR_B, n, hipMemcpyDeviceToDevice, c->stream));
+      // W = GQ_j - Q_{0..j} (Q_{0..j}^T GQ_j), then once more on W (full re-orthogonalisation)
       for (int rep = 0; rep < 2; ++rep) {
         double* Cm = b.H;   // J x B coefficients; H is free until the Rayleigh-Ritz step
-        tn(c, b, b.Q, KR_M, J, b.W, KR_B, KR_B, n, Cm);
-        hipLaunchKernelGGL(k_kr_nn<true>, dim3(g1((int64_t)n * KR_B)), dim3(256), 0, c->stream, b.Q, KR_M, J, Cm,
-                           KR_B, b.W, KR_B, n, KR_B);
-        TK_CHECK_LAUNCH();
+        const double* src = rep == 0 ? b.GQ + q0 : b.W;
+        const int ls = rep == 0 ? KR_M : KR_B;
+        tn(c, b.Q, KR_M, J, src, ls, KR_B, n, Cm);
+        nn<true>(c, b.Q, KR_M, J, Cm, KR_B, src, ls, b.W, KR_B, n, KR_B);
       }
       cholqr(c, b, n, J);
     }
     // Rayleigh-Ritz on span(Q)
-    tn(c, b, b.Q, KR_M, KR_M, b.GQ, KR_M, KR_M, n, b.H);
+    tn(c, b.Q, KR_M, KR_M, b.GQ, KR_M, KR_M, n, b.H);
     eig_topk(c, b.H, KR_M, K, b.lamH, b.S, -1);
-    hipLaunchKernelGGL(k_kr_nn<false>, dim3(g1((int64_t)n * K)), dim3(256), 0, c->stream, b.Q, KR_M, KR_M, b.S, K,
-                       VK, Kout, n, K);
-    TK_CHECK_LAUNCH();
+    nn<false>(c, b.Q, KR_M, KR_M, b.S, K, nullptr, 0, VK, Kout, n, K);
     TK_HIP(hipMemcpyAsync(lam_k, b.lamH, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
     // residual check
-    hipLaunchKernelGGL(k_kr_nn<false>, dim3(g1((int64_t)n * K)), dim3(256), 0, c->stream, G, n, n, VK, Kout, b.GV, K,
-                       n, K);
-    TK_CHECK_LAUNCH();
+    nn<false>(c, G, n, n, VK, Kout, nullptr, 0, b.GV, K, n, K);
     hipLaunchKernelGGL(k_kr_resid, dim3(1), dim3(256), 0, c->stream, b.GV, VK, Kout, lam_k, n, K, b.res);
     TK_CHECK_LAUNCH();
     double res = 0.0;
