@@ -213,6 +213,7 @@ def main():
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--share", type=int, default=1, help="one GPU's share of the workload's draws (dims kept)")
     ap.add_argument("--wg-nnz", type=int, default=0, help="elements per Lite bin (0 = library default)")
+    ap.add_argument("--rows-cap", type=int, default=0, help="LDS rows per Lite bin (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profile", metavar="DIR")
     args = ap.parse_args()
@@ -239,7 +240,12 @@ def main():
 
     idx_d = [torch.from_numpy(i).cuda() for i in w["idx"]]
     vals_d = torch.from_numpy(w["vals"]).cuda()
-    ctx = P.TuckerContext(0, **({"wg_nnz_target": args.wg_nnz} if args.wg_nnz else {}))
+    opts = {}
+    if args.wg_nnz:
+        opts["wg_nnz_target"] = args.wg_nnz
+    if args.rows_cap:
+        opts["lds_rows_cap"] = args.rows_cap
+    ctx = P.TuckerContext(0, **opts)
     torch.cuda.synchronize()
     t = time.perf_counter()
     ctx.load_coo(idx_d, vals_d, dims)

@@ -222,6 +222,7 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
 // (zeroed) LDS rows in wave order after the main loop.  No atomics: the result
 // is deterministic.
 constexpr int TTM3_RING = 4;   // blocks of 16 elements with gathers in flight per wave
+constexpr int TTM4_RING = 3;   // the same for the four-mode kernel (three 16-byte loads per lane per block)
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
@@ -504,9 +505,9 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   const int cs = min(wave * Q, E), ce = min(cs + Q, E);
   const int k = lane >> 4, cix = lane & 15;
   float* tile = tiles + wave * 768;
-  floatx4_t C[KC], Lp[KC];
-  bool has_left = false, has_right = false;
-  int left_sg = 0, right_sg = 0;
+  floatx4_t C[KC];
+  bool has_right = false;
+  int right_sg = 0;
   if (cs < ce) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -518,7 +519,7 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
     int seg_hi = uni(send[sg]);
 #pragma unroll
     for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    auto flush = [&]() {
+    auto flush = [&]() __attribute__((always_inline)) {
       const bool left = seg_lo < cs, right = seg_hi > ce;
       if (!left && !right) {
         float* dst = rows + sg * khat;
@@ -533,11 +534,19 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
         has_right = true;
         right_sg = sg;
         return;
-      } else {              // the first slice of the quarter, begun by an earlier wave
+      } else {
+        // the first slice of the quarter, begun by an earlier wave and ending
+        // here: added to its (zeroed) row at once.  No other wave adds to this
+        // row before the barrier (the earlier waves add theirs after it), so
+        // the order of the sum is fixed.
+        float* dst = rows + sg * khat;
+        if (cix < kb) {
 #pragma unroll
-        for (int q = 0; q < KC; ++q) Lp[q] = C[q];
-        has_left = true;
-        left_sg = sg;
+          for (int q = 0; q < KC; ++q)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+              if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
+        }
       }
 #pragma unroll
       for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
@@ -546,7 +555,7 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
     // gather of block g: lane l takes element g + l/4, 16-byte quarter l%4 of
     // its three rows (all lanes load: the copies are zero beyond column K)
     struct Blk { u32x4 x, y, z; float v; };
-    auto fetch = [&](int g, Blk& r) {
+    auto fetch = [&](int g, Blk& r) __attribute__((always_inline)) {
       const int e = g + (lane >> 2);
       const int ia = sia[e], ib = sib[e], ic = sic[e];
       r.v = sv[e];
@@ -555,7 +564,7 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + o));
       r.z = *reinterpret_cast<const u32x4*>(A.F[2] + (uint32_t)(ic * 16 + o));
     };
-    auto consume = [&](int g, const Blk& r) {
+    auto consume = [&](int g, const Blk& r) __attribute__((always_inline)) {
       reinterpret_cast<float4*>(tile)[lane] =
           make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
                       __uint_as_float(r.x.w) * r.v);
@@ -590,46 +599,37 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
     // refills unconditional (clamped to the last staged block) and kept in
     // issue order, so the wait before each block is for its own loads only
     const int last = Ep - 16;
-    Blk ring[TTM3_RING];
+    Blk ring[TTM4_RING];
 #pragma unroll
-    for (int d = 0; d < TTM3_RING; ++d) {
+    for (int d = 0; d < TTM4_RING; ++d) {
       fetch(min(cs + 16 * d, last), ring[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
-    for (int g = cs; g < ce; g += 16 * TTM3_RING) {
+    for (int g = cs; g < ce; g += 16 * TTM4_RING) {
 #pragma unroll
-      for (int d = 0; d < TTM3_RING; ++d) {
+      for (int d = 0; d < TTM4_RING; ++d) {
         const int gg = g + 16 * d;
         consume(gg, ring[d]);
         __builtin_amdgcn_sched_barrier(0);
-        fetch(min(gg + 16 * TTM3_RING, last), ring[d]);
+        fetch(min(gg + 16 * TTM4_RING, last), ring[d]);
       }
     }
     flush();
   }
   __syncthreads();
-  // partial rows of slices shared between waves, added in wave order
+  // partial rows of slices continued by a later wave, added in wave order
   for (int w = 0; w < 4; ++w) {
-    if (wave == w && cix < kb) {
-      if (has_left) {
-        float* dst = rows + left_sg * khat;
-#pragma unroll
-        for (int q = 0; q < KC; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += Lp[q][r];
-      }
-      if (has_right) {
-        float* dst = rows + right_sg * khat;
-#pragma unroll
-        for (int q = 0; q < KC; ++q)
-#pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
-      }
-    }
     __syncthreads();
+    if (wave == w && cix < kb && has_right) {
+      float* dst = rows + right_sg * khat;
+#pragma unroll
+      for (int q = 0; q < KC; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
+    }
   }
+  __syncthreads();
   for (int q = tid; q < nseg * khat; q += 256) {
     const int sgi = q / khat, col = q - sgi * khat;
     const int slot = sslot[sgi];
@@ -728,8 +728,11 @@ int ttm_tile_width(int N, const int32_t* K, int n) {
 }
 
 int ttm_rows_cap(Ctx* c, int64_t tile_w) {
-  // LDS budget per bin: about 40 KB so three bins share a CU, never past the hardware limit
-  int64_t budget = 40960;
+  // LDS budget for a bin's rows: about 40 KB so three bins share a CU, never
+  // past the hardware limit.  Wide rows (the four-mode matrix-core kernel,
+  // Khat >= 512) leave room for that kernel's staging (16 bytes per element)
+  // and tiles (12 KB): 24 KB of rows keep three of its bins on a CU.
+  int64_t budget = tile_w >= 512 ? 24576 : 40960;
   if ((int64_t)c->lds_per_block < budget) budget = (int64_t)c->lds_per_block;
   int64_t cap = budget / (4 * tile_w + 4);
   if (cap > 512) cap = 512;
