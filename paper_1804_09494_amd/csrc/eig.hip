@@ -520,8 +520,16 @@ __device__ __forceinline__ void reflector(const double (&x)[2], int j0, int n, d
     scale = 0.0;
   } else {
     beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-    t = (beta - alpha) / beta;
-    scale = 1.0 / (alpha - beta);
+    // Newton-refined reciprocals: the two divisions sit on every step's critical path
+    double rb = __builtin_amdgcn_rcp(beta);
+    rb = fma(fma(-beta, rb, 1.0), rb, rb);
+    rb = fma(fma(-beta, rb, 1.0), rb, rb);
+    const double am = alpha - beta;
+    double ra = __builtin_amdgcn_rcp(am);
+    ra = fma(fma(-am, ra, 1.0), ra, ra);
+    ra = fma(fma(-am, ra, 1.0), ra, ra);
+    t = (beta - alpha) * rb;
+    scale = ra;
   }
 #pragma unroll
   for (int c = 0; c < 2; ++c) {
@@ -839,83 +847,84 @@ __global__ __launch_bounds__(EIG_THREADS) void k_syev_small(const double* __rest
       r = fma(fma(-x, r, 1.0), r, r);
       return fma(fma(-x, r, 1.0), r, r);
     };
-    // LU factorisation with partial pivoting of T - lj I
+    // LU factorisation with partial pivoting of T - lj I; full chunks of CH
+    // steps carry no bounds checks (a branch per step costs more than the
+    // step), the remainder goes one step at a time
     double a0 = d[0] - lj, a1 = n > 1 ? e[0] : 0.0, a2 = 0.0;
-    for (int i0 = 0; i0 < n - 1; i0 += CH) {
+    auto lu_step = [&](int i, double c, double ndl, double ns) __attribute__((always_inline)) {
+      const double nd = ndl - lj;
+      const bool sw = fabs(c) > fabs(a0);
+      const double p0 = sw ? c : (a0 == 0.0 ? tiny : a0);
+      const double r = rcp(p0);
+      const double mlt = (sw ? a0 : c) * r;
+      const double y1 = sw ? nd : a1, y2 = sw ? ns : a2;   // the pivot row's entries
+      const double x1 = sw ? a1 : nd, x2 = sw ? a2 : ns;   // the other row's
+      ui[i] = r; u1[i] = y1; u2[i] = y2; ml[i] = mlt; pv[i] = sw ? 1.0 : 0.0;
+      a0 = x1 - mlt * y1;
+      a1 = x2 - mlt * y2;
+      a2 = 0.0;
+    };
+    const int nl = n - 1;                  // LU steps
+    const int nfull = nl / CH * CH;
+    for (int i0 = 0; i0 < nfull; i0 += CH) {
       double ce[CH], cd[CH], cs[CH];
 #pragma unroll
       for (int u = 0; u < CH; ++u) {
-        const int i = min(i0 + u, n - 2);
-        ce[u] = e[i];
-        cd[u] = d[i + 1];
-        cs[u] = i + 1 < n - 1 ? e[i + 1] : 0.0;
+        ce[u] = e[i0 + u];
+        cd[u] = d[i0 + u + 1];
+        cs[u] = i0 + u + 1 < nl ? e[i0 + u + 1] : 0.0;
       }
 #pragma unroll
-      for (int u = 0; u < CH; ++u) {
-        const int i = i0 + u;
-        if (i >= n - 1) break;
-        const double c = ce[u], nd = cd[u] - lj, ns = cs[u];
-        const bool sw = fabs(c) > fabs(a0);
-        const double p0 = sw ? c : (a0 == 0.0 ? tiny : a0);
-        const double r = rcp(p0);
-        const double mlt = (sw ? a0 : c) * r;
-        const double y1 = sw ? nd : a1, y2 = sw ? ns : a2;   // the pivot row's entries
-        const double x1 = sw ? a1 : nd, x2 = sw ? a2 : ns;   // the other row's
-        ui[i] = r; u1[i] = y1; u2[i] = y2; ml[i] = mlt; pv[i] = sw ? 1.0 : 0.0;
-        a0 = x1 - mlt * y1;
-        a1 = x2 - mlt * y2;
-        a2 = 0.0;
-      }
+      for (int u = 0; u < CH; ++u) lu_step(i0 + u, ce[u], cd[u], cs[u]);
     }
+    for (int i = nfull; i < nl; ++i) lu_step(i, e[i], d[i + 1], i + 1 < nl ? e[i + 1] : 0.0);
     if (a0 == 0.0) a0 = tiny;
     ui[n - 1] = rcp(a0); u1[n - 1] = 0.0; u2[n - 1] = 0.0; ml[n - 1] = 0.0; pv[n - 1] = 0.0;
     for (int i = 0; i < n; ++i) z[i] = start_entry(j, i);
     for (int it = 0; it < 2; ++it) {
       // forward elimination with the row interchanges
       double cur = z[0];
-      for (int i0 = 0; i0 < n - 1; i0 += CH) {
+      auto fw_step = [&](int i, double nx, double mi, double p) __attribute__((always_inline)) {
+        const bool sw = p != 0.0;
+        z[i] = sw ? nx : cur;
+        cur = sw ? fma(-mi, nx, cur) : fma(-mi, cur, nx);
+      };
+      for (int i0 = 0; i0 < nfull; i0 += CH) {
         double cz[CH], cm[CH], cp[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-          const int i = min(i0 + u, n - 2);
-          cz[u] = z[i + 1];
-          cm[u] = ml[i];
-          cp[u] = pv[i];
+          cz[u] = z[i0 + u + 1];
+          cm[u] = ml[i0 + u];
+          cp[u] = pv[i0 + u];
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int i = i0 + u;
-          if (i >= n - 1) break;
-          const double nx = cz[u], mi = cm[u];
-          const bool sw = cp[u] != 0.0;
-          z[i] = sw ? nx : cur;
-          cur = sw ? fma(-mi, nx, cur) : fma(-mi, cur, nx);
-        }
+        for (int u = 0; u < CH; ++u) fw_step(i0 + u, cz[u], cm[u], cp[u]);
       }
+      for (int i = nfull; i < nl; ++i) fw_step(i, z[i + 1], ml[i], pv[i]);
       z[n - 1] = cur;
       // back substitution with U (three diagonals), then normalise
       double z1 = 0.0, z2 = 0.0, nrm = 0.0;
-      for (int i0 = n - 1; i0 >= 0; i0 -= CH) {
+      auto bw_step = [&](int i, double zi, double a, double b, double r) __attribute__((always_inline)) {
+        const double sv = (zi - a * z1 - b * z2) * r;
+        z[i] = sv;
+        z2 = z1;
+        z1 = sv;
+        nrm += sv * sv;
+      };
+      const int bfull = n / CH * CH;       // steps n-1 .. n-bfull in full chunks
+      for (int i0 = n - 1; i0 > n - 1 - bfull; i0 -= CH) {
         double cz[CH], c1[CH], c2[CH], cr[CH];
 #pragma unroll
         for (int u = 0; u < CH; ++u) {
-          const int i = max(i0 - u, 0);
-          cz[u] = z[i];
-          c1[u] = u1[i];
-          c2[u] = u2[i];
-          cr[u] = ui[i];
+          cz[u] = z[i0 - u];
+          c1[u] = u1[i0 - u];
+          c2[u] = u2[i0 - u];
+          cr[u] = ui[i0 - u];
         }
 #pragma unroll
-        for (int u = 0; u < CH; ++u) {
-          const int i = i0 - u;
-          if (i < 0) break;
-          const double sv = (cz[u] - c1[u] * z1 - c2[u] * z2) * cr[u];
-          z[i] = sv;
-          z2 = z1;
-          z1 = sv;
-          nrm += sv * sv;
-        }
+        for (int u = 0; u < CH; ++u) bw_step(i0 - u, cz[u], c1[u], c2[u], cr[u]);
       }
+      for (int i = n - 1 - bfull; i >= 0; --i) bw_step(i, z[i], u1[i], u2[i], ui[i]);
       nrm = nrm > 0.0 ? 1.0 / sqrt(nrm) : 0.0;
       for (int i = 0; i < n; ++i) z[i] *= nrm;
     }
