@@ -242,7 +242,7 @@ tk_status tk_default_options(tk_options* o) {
   std::memset(o, 0, sizeof(*o));
   o->prec = TK_FP32;
   o->sweep = TK_SWEEP_GAUSS_SEIDEL;
-  o->wg_nnz_target = 1024;
+  o->wg_nnz_target = 0;
   o->lds_rows_cap = 0;
   o->refine = 1;
   o->mem_limit_bytes = 0;
@@ -380,7 +380,7 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
     for (int n = 0; n < N; ++n) {
       const int tw = ttm_tile_width(N, K, n);
       build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
-                 c->opt.keep_elem_order != 0);
+                 ttm_default_bin_nnz(N, K, n), c->opt.keep_elem_order != 0);
     }
     for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);
     for (int n = 0; n < N; ++n) {

@@ -271,12 +271,13 @@ void reduce_min_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx, const float* vals,
               tk_mem mem);
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
-                int64_t khat, int tile_w, bool keep_order);
+                int64_t khat, int tile_w, int64_t wg_default, bool keep_order);
 void relabel_layout(Ctx* c, ModePlan& pl, int N, int n, const ModePlan* plans, int64_t m);
 void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t* elem_order, int32_t* seg_bin,
                       int32_t* seg_slice, int64_t* seg_begin, uint8_t* seg_bad, tk_mem mem);
 int ttm_rows_cap(Ctx* c, int64_t tile_w);
 int ttm_tile_width(int N, const int32_t* K, int n);
+int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n);
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);

@@ -56,7 +56,7 @@ void load_obs(Ctx* c, int N, const int64_t* dims, const int32_t* ranks, int64_t 
     int64_t khat = 1;
     for (int j = 0; j < N; ++j)
       if (j != n) khat *= ranks[j];
-    build_plan(c, o.plan[n], N, n, dims, n_obs, o.idx, nullptr, khat, ttm_tile_width(N, ranks, n), true);
+    build_plan(c, o.plan[n], N, n, dims, n_obs, o.idx, nullptr, khat, ttm_tile_width(N, ranks, n), 1024, true);
     maxY = std::max(maxY, o.plan[n].L_nz * khat);
   }
   for (int j = 0; j < N; ++j) {

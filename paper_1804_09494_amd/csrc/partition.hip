@@ -313,7 +313,7 @@ static T fetch(Ctx* c, const T* d) {
 }
 
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
-                int64_t khat, int tile_w, bool keep_order) {
+                int64_t khat, int tile_w, int64_t wg_default, bool keep_order) {
   const int B = 256;
   const int64_t L = dims[n];
   pl = ModePlan();
@@ -372,7 +372,7 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   // 3. number of bins and the limit
   const int cap = c->opt.lds_rows_cap >= 3 ? std::min(c->opt.lds_rows_cap, ttm_rows_cap(c, tile_w))
                                             : ttm_rows_cap(c, tile_w);
-  int64_t wg = c->opt.wg_nnz_target > 0 ? c->opt.wg_nnz_target : 4096;
+  const int64_t wg = c->opt.wg_nnz_target > 0 ? c->opt.wg_nnz_target : wg_default;
   int64_t P = std::max<int64_t>(1, std::max(ceil_div(m, wg), ceil_div(Lnz, cap - 2)));
   const int64_t limit = m > 0 ? ceil_div(m, P) : 0;
   pl.P = P;

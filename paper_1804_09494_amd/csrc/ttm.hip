@@ -226,6 +226,10 @@ constexpr int TTM4_RING = 3;   // the same for the four-mode kernel (three 16-by
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// s_waitcnt immediate that waits for vector memory only (vmcnt 0; expcnt and
+// lgkmcnt at their maxima, gfx9 encoding)
+constexpr int kVmcnt0 = 0x0F70;
+
 // Order LDS writes of some lanes before reads of others in the same wave.  The
 // hardware keeps a wave's LDS operations in order; this stops the compiler
 // from treating the lanes as independent threads (it could otherwise forward
@@ -241,11 +245,26 @@ __device__ __forceinline__ float4 bf16x2_lo_hi(uint32_t x, uint32_t y) {
                      __uint_as_float(y & 0xffff0000u));
 }
 
+// Three-mode TTM-chain on the matrix cores, one wave per Lite bin.
+//
+// The bin's layout (coordinates of the two other modes and values) is staged
+// in LDS.  The wave streams it in blocks of 16 elements with a ring of
+// TTM3_RING blocks of gathers in flight: four lanes fetch one 64-byte factor
+// row with a 16-byte load, the block's F_a (times the value) and F_b rows go
+// through a 2 KB LDS tile into the MFMA operand layout, and each 4-element step
+// is one v_mfma_f32_16x16x4f32 accumulating (val F_a)^T F_b of the current
+// slice (a K_a x K_b block of its row of Y, column i + K_a j).  When a slice
+// ends its row goes to the bin's LDS rows; at the end the rows are written to
+// Y (or to the partial slots of slices split across bins) with 16-byte stores.
+// All slices of a bin belong to its one wave: no barriers and no merging of
+// partial rows between waves.  The slice table (end, partial slot, row) is
+// held across the lanes, lane i for slice base + i, and read with readlane.
+//
 // BF: the factor rows are gathered from the BF16 copies (32-byte rows, two
 // lanes per row, lanes 0-31 for F_a and 32-63 for F_b) and widened to FP32
 // before the LDS tile; the contraction and the accumulation stay FP32.
 template <bool BF>
-__global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg_pad) {
+__global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.KA, kb = A.KW;
   const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
@@ -253,22 +272,24 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
   const int E = (int)(A.bin_ptr[bin + 1] - e0);   // multiple of 4
   const int s0 = A.seg_ptr[bin];
   const int nseg = A.seg_ptr[bin + 1] - s0;
-  int* send = reinterpret_cast<int*>(smem);                 // nseg_pad
-  int* sslot = send + nseg_pad;                             // nseg_pad
-  int* srow = sslot + nseg_pad;                             // nseg_pad
-  int* sia = srow + nseg_pad;                               // Epad
+  if (nseg == 0) return;
+  int* sia = reinterpret_cast<int*>(smem);                  // Epad
   int* sib = sia + Epad;                                    // Epad
   float* sv = reinterpret_cast<float*>(sib + Epad);         // Epad
-  float* tiles = sv + Epad;                                 // 4 waves x 512: F_a and F_b rows of one block
-  float* rows = tiles + 4 * 512;                            // nseg x khat: the bin's rows of Y
+  float* tile = sv + Epad;                                  // 512: F_a and F_b rows of one block
+  float* rows = tile + 512;                                 // nseg x khat: the bin's rows of Y
   const int khat = A.khat;
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wave = uni(tid >> 6);
-  for (int i = tid; i < nseg; i += 256) {
-    send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
-    sslot[i] = A.seg_slot[s0 + i];
-    srow[i] = A.seg_row[s0 + i];
-  }
+  const int lane = threadIdx.x;
+  int base = 0, v_end = 0, v_slot = 0, v_row = 0;
+  auto load_segs = [&](int b) __attribute__((always_inline)) {
+    const int i = min(b + lane, nseg - 1);
+    v_end = (int)(A.seg_begin[s0 + i + 1] - e0);
+    v_slot = A.seg_slot[s0 + i];
+    v_row = A.seg_row[s0 + i];
+    // wait here: the table is then known to be in registers, and the waits
+    // inside the ring count only its gathers
+    __builtin_amdgcn_s_waitcnt(kVmcnt0);
+  };
   const int Ep = (E + 15) & ~15;
   // the layout is read once, four elements per lane (bins start at multiples
   // of four): non-temporal loads keep it from evicting factor rows in L2
@@ -277,169 +298,163 @@ __global__ __launch_bounds__(256) void k_ttm3_mfma(TtmArgs A, int Epad, int nseg
     const u32x4* lb4 = reinterpret_cast<const u32x4*>(A.lay[1] + e0);
     const u32x4* v4 = reinterpret_cast<const u32x4*>(A.val + e0);
     const u32x4 z = {0u, 0u, 0u, 0u};
-    for (int i = tid; 4 * i < Ep; i += 256) {
+    for (int i = lane; 4 * i < Ep; i += 64) {
       const bool ok = 4 * i < E;
       reinterpret_cast<u32x4*>(sia)[i] = ok ? __builtin_nontemporal_load(la4 + i) : z;
       reinterpret_cast<u32x4*>(sib)[i] = ok ? __builtin_nontemporal_load(lb4 + i) : z;
       reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
     }
   }
-  for (int i = tid; i < nseg * khat; i += 256) rows[i] = 0.f;   // shared rows are summed into
-  __syncthreads();
-
-  // per-wave state below is uniform (scalar registers, scalar branches)
-  const int Q = (((E + 3) >> 2) + 15) & ~15;
-  const int cs = min(wave * Q, E), ce = min(cs + Q, E);
+  load_segs(0);
+  wave_lds_sync();
   const int k = lane >> 4, cix = lane & 15;
   const bool bok = cix < kb;
-  float* tile = tiles + wave * 512;
-  // slices a wave shares with a neighbour keep their partial rows in
-  // registers (Lp: begun by an earlier wave; C: continued by a later one)
-  floatx4_t C = {0.f, 0.f, 0.f, 0.f}, Lp = {0.f, 0.f, 0.f, 0.f};
-  bool has_left = false, has_right = false;
-  int left_sg = 0, right_sg = 0;
-  if (cs < ce) {
-    int lo = 0, hi = nseg - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi) >> 1;
-      if (uni(send[mid]) > cs) hi = mid; else lo = mid + 1;
+  floatx4_t C = {0.f, 0.f, 0.f, 0.f};
+  int sg = 0;
+  int seg_hi = __builtin_amdgcn_readlane(v_end, 0);
+  auto flush = [&]() __attribute__((always_inline)) {
+    if (bok) {
+      float* dst = rows + sg * khat + 4 * k + ka * cix;
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        if (4 * k + r < ka) dst[r] = C[r];
     }
-    int sg = lo;
-    int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
-    int seg_hi = uni(send[sg]);
-    auto flush = [&]() {
-      const bool left = seg_lo < cs, right = seg_hi > ce;
-      if (!left && !right) {
-        // LDS only inside the loop: global stores would share the load counter
-        // with the gathers in flight and serialise the prefetch ring
-        float* dst = rows + sg * khat;
-        if (bok) {
+    C = floatx4_t{0.f, 0.f, 0.f, 0.f};
+  };
+  // Gather of block g.  FP32: lane l takes element g + l/4, 16-byte quarter
+  // l%4 of its F_a and F_b rows.  BF16: lane l takes element g + (l/2)%16,
+  // half l%2 of the F_a (l < 32) or F_b row.  All lanes load: the factor
+  // copies are zero beyond column K, so no predicate (a predicated load would
+  // make the in-flight count path dependent).
+  struct Blk { u32x4 x, y; float v; };
+  const uintptr_t hbase = reinterpret_cast<uintptr_t>(A.H[0]);
+  const uintptr_t hdiff = reinterpret_cast<uintptr_t>(A.H[1]) - hbase;
+  auto fetch = [&](int g, Blk& r) __attribute__((always_inline)) {
+    if constexpr (BF) {
+      const int e = g + ((lane >> 1) & 15);
+      const bool fa = lane < 32;
+      const int ix = fa ? sia[e] : sib[e];
+      r.v = fa ? sv[e] : 1.f;
+      // select a distance, not one of two pointers: a select of two
+      // argument loads becomes a per-lane load of the chosen pointer
+      const uintptr_t h = hbase + (fa ? 0 : hdiff) + 2 * (uintptr_t)(uint32_t)(ix * 16 + 8 * (lane & 1));
+      r.x = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(h);
+    } else {
+      const int e = g + (lane >> 2);
+      const int ia = sia[e], ib = sib[e];
+      r.v = sv[e];
+      r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + 4 * (lane & 3)));
+      r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + 4 * (lane & 3)));
+    }
+  };
+  auto consume = [&](int g, const Blk& r) __attribute__((always_inline)) {
+    // the rows of the block into the tile: F_a (times val) at 0, F_b at 256
+    if constexpr (BF) {
+      const float4 w0 = bf16x2_lo_hi(r.x.x, r.x.y), w1 = bf16x2_lo_hi(r.x.z, r.x.w);
+      float4* t = reinterpret_cast<float4*>(tile + 8 * lane);
+      t[0] = make_float4(w0.x * r.v, w0.y * r.v, w0.z * r.v, w0.w * r.v);
+      t[1] = make_float4(w1.x * r.v, w1.y * r.v, w1.z * r.v, w1.w * r.v);
+    } else {
+      reinterpret_cast<float4*>(tile)[lane] =
+          make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
+                      __uint_as_float(r.x.w) * r.v);
+      reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
+          __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
+    }
+    wave_lds_sync();
+    // operand layout: step u, lane l reads element 4u + l/16, column l%16
+    float xa[4], xb[4];
 #pragma unroll
-          for (int r = 0; r < 4; ++r)
-            if (4 * k + r < ka) dst[4 * k + r + ka * cix] = C[r];
+    for (int u = 0; u < 4; ++u) {
+      xa[u] = tile[(4 * u + k) * 16 + cix];
+      xb[u] = tile[256 + (4 * u + k) * 16 + cix];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int gu = g + 4 * u;
+      if (gu >= E) break;
+      if (gu >= seg_hi) {  // a new slice starts at this step
+        flush();
+        ++sg;
+        if (sg - base == 64) {
+          base = sg;
+          load_segs(base);
         }
-      } else if (right) {   // the last slice of the quarter: stays in C
-        has_right = true;
-        right_sg = sg;
-        return;
-      } else {              // the first slice of the quarter, begun by an earlier wave
-        Lp = C;
-        has_left = true;
-        left_sg = sg;
+        seg_hi = __builtin_amdgcn_readlane(v_end, sg - base);
       }
-      C = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    };
-    // Gather of block g.  FP32: lane l takes element g + l/4, 16-byte quarter
-    // l%4 of its F_a and F_b rows.  BF16: lane l takes element g + (l/2)%16,
-    // half l%2 of the F_a (l < 32) or F_b row.  All lanes load: the factor
-    // copies are zero beyond column K, so no predicate (a predicated load would
-    // make the in-flight count path dependent).
-    struct Blk { u32x4 x, y; float v; };
-    const uintptr_t hbase = reinterpret_cast<uintptr_t>(A.H[0]);
-    const uintptr_t hdiff = reinterpret_cast<uintptr_t>(A.H[1]) - hbase;
-    auto fetch = [&](int g, Blk& r) {
-      if constexpr (BF) {
-        const int e = g + ((lane >> 1) & 15);
-        const bool fa = lane < 32;
-        const int ix = fa ? sia[e] : sib[e];
-        r.v = fa ? sv[e] : 1.f;
-        // select a distance, not one of two pointers: a select of two
-        // argument loads becomes a per-lane load of the chosen pointer
-        const uintptr_t h = hbase + (fa ? 0 : hdiff) + 2 * (uintptr_t)(uint32_t)(ix * 16 + 8 * (lane & 1));
-        r.x = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(h);
-      } else {
-        const int e = g + (lane >> 2);
-        const int ia = sia[e], ib = sib[e];
-        r.v = sv[e];
-        r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + 4 * (lane & 3)));
-        r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + 4 * (lane & 3)));
-      }
-    };
-    auto consume = [&](int g, const Blk& r) {
-      // the rows of the block into the wave's tile: F_a (times val) at 0, F_b at 256
-      if constexpr (BF) {
-        const float4 w0 = bf16x2_lo_hi(r.x.x, r.x.y), w1 = bf16x2_lo_hi(r.x.z, r.x.w);
-        float4* t = reinterpret_cast<float4*>(tile + 8 * lane);
-        t[0] = make_float4(w0.x * r.v, w0.y * r.v, w0.z * r.v, w0.w * r.v);
-        t[1] = make_float4(w1.x * r.v, w1.y * r.v, w1.z * r.v, w1.w * r.v);
-      } else {
-        reinterpret_cast<float4*>(tile)[lane] =
-            make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
-                        __uint_as_float(r.x.w) * r.v);
-        reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
-            __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
-      }
-      wave_lds_sync();
-      // operand layout: step u, lane l reads element 4u + l/16, column l%16
-      float xa[4], xb[4];
+      C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
+    }
+    wave_lds_sync();   // the next block's write follows these reads
+  };
+  // Refills are unconditional (clamped to the last staged block): every path
+  // then has the same loads in flight and the compiler waits only for the
+  // oldest block instead of draining the ring.
+  const int last = Ep - 16;
+  Blk ring[TTM3_RING];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        xa[u] = tile[(4 * u + k) * 16 + cix];
-        xb[u] = tile[256 + (4 * u + k) * 16 + cix];
-      }
-#pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gu = g + 4 * u;
-        if (gu >= ce) break;
-        if (gu >= seg_hi) {  // a new slice starts at this step
-          flush();
-          ++sg;
-          seg_lo = seg_hi;
-          seg_hi = uni(send[sg]);
-        }
-        C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
-      }
-      wave_lds_sync();   // the next block's write follows these reads
-    };
-    // Refills are unconditional (clamped to the last staged block): every path
-    // then has the same loads in flight and the compiler waits only for the
-    // oldest block instead of draining the ring.
-    const int last = Ep - 16;
-    Blk ring[TTM3_RING];
+  for (int d = 0; d < TTM3_RING; ++d) {
+    fetch(min(16 * d, last), ring[d]);
+    __builtin_amdgcn_sched_barrier(0);  // issue order = consumption order
+  }
+  for (int g = 0; g < E; g += 16 * TTM3_RING) {
 #pragma unroll
     for (int d = 0; d < TTM3_RING; ++d) {
-      fetch(min(cs + 16 * d, last), ring[d]);
-      __builtin_amdgcn_sched_barrier(0);  // issue order = consumption order
-    }
-    for (int g = cs; g < ce; g += 16 * TTM3_RING) {
-#pragma unroll
-      for (int d = 0; d < TTM3_RING; ++d) {
-        const int gg = g + 16 * d;
-        consume(gg, ring[d]);
-        // keep the refill behind the consumption of its slot: hoisted above it,
-        // the refill takes fresh registers and the wait at the loop head
-        // drains every load in flight
-        __builtin_amdgcn_sched_barrier(0);
-        fetch(min(gg + 16 * TTM3_RING, last), ring[d]);
-      }
-    }
-    flush();  // the slice open at the end of this wave's quarter
-  }
-  // partial rows of slices shared between waves, added in wave order
-  for (int w = 0; w < 4; ++w) {
-    __syncthreads();
-    if (wave == w && bok) {
-      if (has_left) {
-        float* dst = rows + left_sg * khat;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * k + r < ka) dst[4 * k + r + ka * cix] += Lp[r];
-      }
-      if (has_right) {
-        float* dst = rows + right_sg * khat;
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * k + r < ka) dst[4 * k + r + ka * cix] += C[r];
-      }
+      const int gg = g + 16 * d;
+      consume(gg, ring[d]);
+      // keep the refill behind the consumption of its slot: hoisted above it,
+      // the refill takes fresh registers and the wait at the loop head
+      // drains every load in flight
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(min(gg + 16 * TTM3_RING, last), ring[d]);
     }
   }
-  __syncthreads();
-  // the bin's rows out, coalesced: owned slices to Y, split slices to their partial slot
-  for (int q = tid; q < nseg * khat; q += 256) {
-    const int sgi = q / khat, col = q - sgi * khat;
-    const int slot = sslot[sgi];
-    float* dst = slot < 0 ? A.Y + (int64_t)srow[sgi] * khat : A.partial + (int64_t)slot * khat;
-    __builtin_nontemporal_store(rows[q], dst + col);
+  flush();  // the bin's last slice
+  wave_lds_sync();
+  // The rows out: owned slices to Y, split slices to their partial slot.  The
+  // destination is an offset from Y (a select of two pointers would become a
+  // private-memory table).
+  const uintptr_t ybase = reinterpret_cast<uintptr_t>(A.Y);
+  const uintptr_t pdiff = reinterpret_cast<uintptr_t>(A.partial) - ybase;
+  if ((khat & 3) == 0) {
+    // 16-byte stores, two rows at a time when a row fits half a wave
+    const int kq = khat >> 2;
+    const bool two = kq <= 32;
+    const int half = two ? lane >> 5 : 0, cl = two ? lane & 31 : lane;
+    for (int g0 = 0; g0 < nseg; g0 += 64) {
+      if (g0 != base) {
+        base = g0;
+        load_segs(base);
+      }
+      const int cnt = min(64, nseg - g0);
+      for (int i = 0; i < cnt; i += two ? 2 : 1) {
+        const int s0i = __builtin_amdgcn_readlane(v_slot, i), r0i = __builtin_amdgcn_readlane(v_row, i);
+        const int i1 = min(i + 1, 63);
+        const int s1i = __builtin_amdgcn_readlane(v_slot, i1), r1i = __builtin_amdgcn_readlane(v_row, i1);
+        const int ii = i + half;
+        if (ii >= cnt) continue;
+        const int slot = half ? s1i : s0i;
+        const int64_t r64 = slot < 0 ? (half ? r1i : r0i) : slot;
+        auto* dst = reinterpret_cast<__attribute__((address_space(1))) floatx4_t*>(
+            ybase + (slot < 0 ? 0 : pdiff) + (uintptr_t)(r64 * khat) * 4);
+        const floatx4_t* src = reinterpret_cast<const floatx4_t*>(rows + (g0 + ii) * khat);
+        for (int c4 = cl; c4 < kq; c4 += two ? 32 : 64) __builtin_nontemporal_store(src[c4], dst + c4);
+      }
+    }
+  } else {
+    for (int g0 = 0; g0 < nseg; g0 += 64) {
+      if (g0 != base) {
+        base = g0;
+        load_segs(base);
+      }
+      const int cnt = min(64, nseg - g0);
+      for (int i = 0; i < cnt; ++i) {
+        const int slot = __builtin_amdgcn_readlane(v_slot, i);
+        const int64_t r64 = slot < 0 ? __builtin_amdgcn_readlane(v_row, i) : slot;
+        auto* dst = reinterpret_cast<__attribute__((address_space(1))) float*>(
+            ybase + (slot < 0 ? 0 : pdiff) + (uintptr_t)(r64 * khat) * 4);
+        for (int c = lane; c < khat; c += 64) __builtin_nontemporal_store(rows[(g0 + i) * khat + c], dst + c);
+      }
+    }
   }
 }
 
@@ -727,6 +742,19 @@ int ttm_tile_width(int N, const int32_t* K, int n) {
   return kmax * s.TW;
 }
 
+// Default elements per Lite bin for the kernel mode n takes: the one-wave
+// three-mode kernel wants small bins (one bin's start-up latency is covered by
+// the others on the CU; 512 elements measured best), the four-mode kernel's
+// four waves share 1024, and the vector-ALU kernel amortises its row tiles
+// over 4096.
+int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n) {
+  int kp16[8];
+  for (int j = 0; j < N; ++j) kp16[j] = K[j] <= 16 ? 16 : 0;
+  if (ttm_uses_mfma(N, K, n, kp16)) return 512;
+  if (ttm_uses_mfma4(N, K, n, kp16)) return 1024;
+  return 4096;
+}
+
 int ttm_rows_cap(Ctx* c, int64_t tile_w) {
   // LDS budget for a bin's rows: about 40 KB so three bins share a CU, never
   // past the hardware limit.  Wide rows (the four-mode matrix-core kernel,
@@ -789,14 +817,12 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
   if (ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
-    const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
-    const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 12 * (size_t)Epad + sizeof(float) * 4 * 512 +
-                       sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
+    const size_t lds = 12 * (size_t)Epad + sizeof(float) * 512 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     if (H16)
-      hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+      hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
     else
-      hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(256), lds, c->stream, a, Epad, nseg_pad);
+      hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
     TK_CHECK_LAUNCH();
   } else if (ttm_uses_mfma4(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);

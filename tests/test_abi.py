@@ -38,7 +38,7 @@ def test_status_strings_and_default_options():
     assert lib.tk_status_string(1) == b"invalid argument"
     o = L.tk_options()
     assert lib.tk_default_options(ctypes.byref(o)) == 0
-    assert o.wg_nnz_target == 1024 and o.refine == 1 and o.complete_rank_deficient == 1
+    assert o.wg_nnz_target == 0 and o.refine == 1 and o.complete_rank_deficient == 1
     assert lib.tk_default_options(None) == 1
 
 
