@@ -523,6 +523,29 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   floatx4_t C[KC];
   bool has_right = false;
   int right_sg = 0;
+  // row += this lane's part of C, for the merge after the main loop.  Even
+  // K_a: the lane's entries of a c-slab pair up into two 8-byte words, read
+  // together and then written (one LDS round trip per slab instead of one per
+  // entry).
+  auto row_acc = [&](float* dst) __attribute__((always_inline)) {
+    if (cix >= kb) return;
+    float* p = dst + 4 * k + ka * cix;
+    const int qs = ka * kb;
+    const bool h0 = 4 * k < ka, h1 = 4 * k + 2 < ka;
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      if ((ka & 1) == 0) {
+        float2* w = reinterpret_cast<float2*>(p + q * qs);
+        const float2 o0 = h0 ? w[0] : float2{0.f, 0.f}, o1 = h1 ? w[1] : float2{0.f, 0.f};
+        if (h0) w[0] = float2{o0.x + C[q][0], o0.y + C[q][1]};
+        if (h1) w[1] = float2{o1.x + C[q][2], o1.y + C[q][3]};
+      } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          if (4 * k + r < ka) p[q * qs + r] += C[q][r];
+      }
+    }
+  };
   if (cs < ce) {
     int lo = 0, hi = nseg - 1;
     while (lo < hi) {
@@ -635,21 +658,26 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   // partial rows of slices continued by a later wave, added in wave order
   for (int w = 0; w < 4; ++w) {
     __syncthreads();
-    if (wave == w && cix < kb && has_right) {
-      float* dst = rows + right_sg * khat;
-#pragma unroll
-      for (int q = 0; q < KC; ++q)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
-    }
+    if (wave == w && has_right) row_acc(rows + right_sg * khat);
   }
   __syncthreads();
-  for (int q = tid; q < nseg * khat; q += 256) {
-    const int sgi = q / khat, col = q - sgi * khat;
-    const int slot = sslot[sgi];
-    float* dst = slot < 0 ? A.Y + (int64_t)srow[sgi] * khat : A.partial + (int64_t)slot * khat;
-    __builtin_nontemporal_store(rows[q], dst + col);
+  // the bin's rows out, one row per wave at a time, 16-byte stores when the
+  // row length allows; the destination is an offset from Y (a select of two
+  // pointers would become a private-memory table)
+  const uintptr_t ybase = reinterpret_cast<uintptr_t>(A.Y);
+  const uintptr_t pdiff = reinterpret_cast<uintptr_t>(A.partial) - ybase;
+  for (int sgi = wave; sgi < nseg; sgi += 4) {
+    const int slot = uni(sslot[sgi]);
+    const int64_t r64 = slot < 0 ? uni(srow[sgi]) : slot;
+    const uintptr_t rowp = ybase + (slot < 0 ? 0 : pdiff) + (uintptr_t)(r64 * khat) * 4;
+    if ((khat & 3) == 0) {
+      const floatx4_t* src = reinterpret_cast<const floatx4_t*>(rows + sgi * khat);
+      auto* dst = reinterpret_cast<__attribute__((address_space(1))) floatx4_t*>(rowp);
+      for (int c4 = lane; c4 < (khat >> 2); c4 += 64) __builtin_nontemporal_store(src[c4], dst + c4);
+    } else {
+      auto* dst = reinterpret_cast<__attribute__((address_space(1))) float*>(rowp);
+      for (int c = lane; c < khat; c += 64) __builtin_nontemporal_store(rows[sgi * khat + c], dst + c);
+    }
   }
 }
 
