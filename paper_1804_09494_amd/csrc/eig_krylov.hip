@@ -6,11 +6,13 @@
 //   Q_0 = orthonormal start block (the previous invocation's eigenvectors of
 //         this mode when there are any, seeded directions otherwise);
 //   for j < KR_S:  GQ_j = G Q_j;  W = GQ_j - Q_{0..j} (Q_{0..j}^T GQ_j), twice
-//         (full re-orthogonalisation);  Q_{j+1} = W R^-1 by CholeskyQR, three
-//         passes (a block that has no independent directions left is zeroed);
+//         (full re-orthogonalisation);  Q_{j+1} = W R^-1 by shifted
+//         CholeskyQR3 (the first pass on the shifted Gram; an exactly zero
+//         block is zeroed);
 //   Rayleigh-Ritz: H = Q^T (G Q)  (KR_S*KR_B square), its leading K eigenpairs by
 //         the dense solver, V = Q S;
-//   the largest residual ||G v - theta v|| / theta_1 decides a restart from V.
+//   the largest residual ||G v - theta v|| / theta_1 decides a restart from V
+//   (up to KR_CYCLES cycles, ending early once a restart stops improving it).
 // The tall-skinny products are plain FP64 kernels with fixed-order partial sums.
 #include <cmath>
 
@@ -108,19 +110,41 @@ __global__ __launch_bounds__(256) void k_kr_tn(const double* __restrict__ A, int
   }
 }
 
-// Cholesky of the b x b Gram A = R^T R (b <= 16) and Rinv = R^-1, one wave; a
-// pivot that is not safely positive (no independent direction left) zeroes
-// Rinv, and so the block.
-__global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, int b, double* __restrict__ Rinv) {
+// Cholesky of the b x b Gram A = R^T R (b <= 16) and Rinv = R^-1, one wave.
+// shift_rows > 0: the shifted form for the first of the three CholeskyQR
+// passes (Fukaya et al., shifted CholeskyQR3): A + s I with
+// s = 11 (m b + b (b + 1)) u tr(A), m = shift_rows, u = 2^-53, which is safely
+// positive definite whatever the condition of the block, so a block whose
+// directions are nearly spanned already still yields its remaining (tiny or
+// noise) directions, normalised by the next two passes.  Without the shift a
+// restart from converged vectors fails the pivot test on every later block
+// and the Krylov space stops growing.  A column whose pivot is not safely
+// positive in a later pass (a direction at rounding level) is dropped alone:
+// its row of R is set to e_j and its column of Rinv to zero, so it adds
+// nothing to the other columns and comes out zero.  An all-zero block zeroes
+// Rinv.
+__global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, int b, double* __restrict__ Rinv,
+                                               int shift_rows) {
   __shared__ double R[KR_B * KR_B], X[KR_B * KR_B];
-  __shared__ int okf;
+  __shared__ int okf, dead;
   const int l = threadIdx.x;
   for (int i = l; i < KR_B * KR_B; i += 64) {
     const int r = i / KR_B, cc = i % KR_B;
     R[i] = (r < b && cc < b) ? A[r * b + cc] : 0.0;
   }
-  if (l == 0) okf = 1;
+  if (l == 0) {
+    okf = 1;
+    dead = 0;
+  }
   __syncthreads();
+  if (shift_rows > 0) {
+    double tr = 0.0;
+    for (int i = 0; i < b; ++i) tr += R[i * KR_B + i];
+    const double sh = 11.0 * ((double)shift_rows * b + (double)b * (b + 1)) * 0x1p-53 * tr;
+    __syncthreads();
+    if (l < b) R[l * KR_B + l] += sh;
+    __syncthreads();
+  }
   double dmax = 0.0;
   for (int i = 0; i < b; ++i) dmax = fmax(dmax, R[i * KR_B + i]);
   if (!(dmax > 0.0) && l == 0) okf = 0;
@@ -129,10 +153,14 @@ __global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, in
   for (int j = 0; j < b && okf; ++j) {
     const double d = R[j * KR_B + j];
     __syncthreads();
-    if (!(d > 1e-14 * dmax)) {
-      if (l == 0) okf = 0;
+    if (!(d > 1e-14 * dmax)) {   // dependent column: dropped
+      if (l == 0) {
+        R[j * KR_B + j] = 1.0;
+        dead |= 1 << j;
+      }
+      if (l > j && l < b) R[j * KR_B + l] = 0.0;
       __syncthreads();
-      break;
+      continue;
     }
     const double rjj = sqrt(d), ri = 1.0 / rjj;
     if (l > j && l < b) R[j * KR_B + l] *= ri;
@@ -163,7 +191,7 @@ __global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, in
   __syncthreads();
   for (int t = l; t < b * b; t += 64) {
     const int i = t / b, c = t % b;
-    Rinv[t] = X[c * KR_B + i];
+    Rinv[t] = (dead >> c) & 1 ? 0.0 : X[c * KR_B + i];
   }
 }
 
@@ -238,7 +266,7 @@ void cholqr(Ctx* c, const KrBufs& b, int n, int q0) {
   double* src = b.W;
   for (int pass = 0; pass < 3; ++pass) {
     tn(c, src, KR_B, KR_B, src, KR_B, KR_B, n, A);
-    hipLaunchKernelGGL(k_kr_chol, dim3(1), dim3(64), 0, c->stream, A, KR_B, Ri);
+    hipLaunchKernelGGL(k_kr_chol, dim3(1), dim3(64), 0, c->stream, A, KR_B, Ri, pass == 0 ? n : 0);
     TK_CHECK_LAUNCH();
     double* dst = pass == 2 ? b.Q + q0 : (src == b.W ? b.W2 : b.W);
     nn<false>(c, src, KR_B, KR_B, Ri, KR_B, nullptr, 0, dst, pass == 2 ? KR_M : KR_B, n, KR_B);
@@ -269,6 +297,7 @@ void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* la
   b.res = p;
   Buf* warm = mode >= 0 ? &c->eig_warm[mode] : nullptr;
   int kw = (warm && c->eig_warm_k[mode] == K && warm->bytes() >= sizeof(double) * (size_t)n * K) ? K : 0;
+  double prev_res = 0.0;
   for (int cycle = 0; cycle < KR_CYCLES; ++cycle) {
     // start block: the warm vectors (first cycle) or the last Ritz vectors (restart), then seeded directions
     const double* wsrc = nullptr;
@@ -313,7 +342,9 @@ void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* la
     double res = 0.0;
     TK_HIP(hipMemcpyAsync(&res, b.res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     c->sync();
-    if (res <= 1e-10) break;
+    // converged, or a restart that no longer improves (rounding floor)
+    if (res <= 1e-10 || (cycle > 0 && res > 0.5 * prev_res)) break;
+    prev_res = res;
   }
   if (warm) {
     ensure(c, *warm, sizeof(double) * (size_t)n * K);
