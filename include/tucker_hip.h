@@ -73,7 +73,7 @@ typedef struct {
                                      gathers BF16 factor rows.  The eigensolve, CholeskyQR2, core and
                                      fit stay FP64 */
   int32_t sweep;                  /* tk_sweep (default Gauss-Seidel: mode n uses factors refined earlier in the invocation) */
-  int64_t wg_nnz_target;          /* target elements per bin; 0 (default) = per kernel: 512 for the
+  int64_t wg_nnz_target;          /* target elements per bin; 0 (default) = per kernel: 448 for the
                                      three-mode matrix-core TTM-chain, 1024 for the four-mode one and
                                      for the completion adjoint, 4096 otherwise */
   int32_t lds_rows_cap;           /* max slices per bin; 0 = from the LDS budget */

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
 // neighbours keep their partial rows in registers and are added to the
 // (zeroed) LDS rows in wave order after the main loop.  No atomics: the result
 // is deterministic.
-constexpr int TTM3_RING = 4;   // blocks of 16 elements with gathers in flight per wave
+constexpr int TTM3_RING = 3;   // blocks of 16 elements with gathers in flight per wave
 constexpr int TTM4_RING = 3;   // the same for the four-mode kernel (three 16-byte loads per lane per block)
 
 __device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
@@ -772,13 +772,13 @@ int ttm_tile_width(int N, const int32_t* K, int n) {
 
 // Default elements per Lite bin for the kernel mode n takes: the one-wave
 // three-mode kernel wants small bins (one bin's start-up latency is covered by
-// the others on the CU; 512 elements measured best), the four-mode kernel's
-// four waves share 1024, and the vector-ALU kernel amortises its row tiles
-// over 4096.
+// the others on the CU; 384-512 elements measured best, 448 by a little), the
+// four-mode kernel's four waves share 1024, and the vector-ALU kernel
+// amortises its row tiles over 4096.
 int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n) {
   int kp16[8];
   for (int j = 0; j < N; ++j) kp16[j] = K[j] <= 16 ? 16 : 0;
-  if (ttm_uses_mfma(N, K, n, kp16)) return 512;
+  if (ttm_uses_mfma(N, K, n, kp16)) return 448;
   if (ttm_uses_mfma4(N, K, n, kp16)) return 1024;
   return 4096;
 }
