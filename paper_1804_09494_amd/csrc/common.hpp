@@ -172,6 +172,7 @@ struct Ctx {
   Buf work;               // general scratch
   Buf gram_part;          // float/double partial Grams
   Buf gram64;             // double[Khat x Khat]
+  Buf ybf;                // BF16 copy of Y in MFMA operand order (wide BF16 Gram)
   Buf eig_val;            // double[Khat]
   Buf U64;                // double[R_n x K_n]
   Buf small64;            // double scratch for K x K matrices, reductions

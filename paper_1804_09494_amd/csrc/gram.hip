@@ -15,6 +15,12 @@
 // their k values from the same rows, so the order of k inside a step does not
 // matter.
 //
+// Wide Grams (Khat > 128, several macro tile pairs) in the precision form
+// first write a BF16 copy of Y in that operand order (k_y_bf16_blocked), so
+// that each operand is one 16-byte load instead of eight 4-byte ones, and the
+// copy that every macro pair re-reads is half the bytes (k_gram_bf16b, same
+// tiles and order, same partials bit for bit).
+//
 // Each wave accumulates its share of 4-row steps for a set of 16x16 tiles;
 // the four waves of a workgroup are combined in LDS in fixed order and each
 // workgroup writes one FP32 partial; a second kernel sums the partials in
@@ -210,6 +216,104 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const float* __restrict__ Y, 
   for (int i = threadIdx.x; i < T * 256; i += blockDim.x) out[i] = red[i];
 }
 
+// BF16 copy of Y for the wide precision-form Gram, in the operand order of
+// v_mfma_f32_16x16x32_bf16: for each block of 32 rows and each column c (of
+// KP, Khat rounded up to 16) the 32 rows' values are contiguous, so lane l's
+// operand (column c, rows 8*(l/16) .. +7 of the block) is one 16-byte load.
+// Values are rounded to nearest even, as the direct kernel rounds them in
+// registers; rows past R and columns past Khat are zero.  One workgroup turns
+// a 32 x 64 tile around through LDS.
+__global__ __launch_bounds__(256) void k_y_bf16_blocked(const float* __restrict__ Y, int64_t R, int khat, int KP,
+                                                        __bf16* __restrict__ Yb) {
+  __shared__ float t[32][65];
+  const int64_t rb = blockIdx.x;
+  const int c0 = blockIdx.y * 64;
+  const int tid = threadIdx.x;
+  {
+    const int r = tid >> 3, cq = (tid & 7) * 8;
+    const int64_t row = rb * 32 + r;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int col = c0 + cq + q;
+      t[r][cq + q] = (row < R && col < khat) ? Y[row * khat + col] : 0.f;
+    }
+  }
+  __syncthreads();
+  const int c = tid >> 2, g = tid & 3;
+  if (c0 + c < KP) {
+    bf16x8 v;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) v[q] = (__bf16)t[8 * g + q][c];
+    *reinterpret_cast<bf16x8*>(Yb + ((rb * KP + c0 + c) * 32 + 8 * g)) = v;
+  }
+}
+
+// The precision-form Gram from the blocked BF16 copy: the tiles, steps and
+// order of k_gram_bf16 (so the same partials, bit for bit), with each operand
+// one 16-byte load instead of eight 4-byte ones.
+template <int NBA, int NBB, bool DIAG>
+__global__ __launch_bounds__(256) void k_gram_bf16b(const __bf16* __restrict__ Yb, int64_t R, int KP,
+                                                    int rows_per_wg, int MB, float* __restrict__ part) {
+  using TS = TileSet<NBA, NBB, DIAG>;
+  constexpr int T = TS::count;
+  constexpr int NL = DIAG ? NBA : NBA + NBB;   // column blocks loaded per step
+  extern __shared__ float red[];
+  const int pair = blockIdx.y;
+  int PI, PJ;
+  macro_pair(DIAG, pair, MB, PI, PJ);
+  const int I0 = PI * NBA, J0 = PJ * NBB;
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;   // a multiple of 128
+  const int64_t r1 = min(r0 + rows_per_wg, R);
+  floatx4 acc[T];
+#pragma unroll
+  for (int t = 0; t < T; ++t) acc[t] = floatx4{0.f, 0.f, 0.f, 0.f};
+  const int lr = lane >> 4, lc = lane & 15;
+  // the workgroup's row blocks form one buffer resource: steps past r1 read zeros
+  const int64_t nrb = (r1 - r0 + 31) / 32;
+  const __amdgpu_buffer_rsrc_t rs = buf_rsrc(Yb + (r0 / 32) * KP * 32, (uint32_t)(nrb * KP * 64));
+  uint32_t coff[NL];
+#pragma unroll
+  for (int b = 0; b < NL; ++b) {
+    const int blk = b < NBA ? I0 + b : J0 + b - NBA;   // blocks past the last one read zeros
+    coff[b] = blk * 16 < KP ? 2u * (uint32_t)((blk * 16 + lc) * 32 + 8 * lr) : BUF_OOB;
+  }
+  auto load = [&](int64_t r, bf16x8 (&x)[NL]) {
+    const uint32_t rb = 2u * (uint32_t)(((r - r0) >> 5) * KP * 32);
+#pragma unroll
+    for (int b = 0; b < NL; ++b)
+      x[b] = __builtin_bit_cast(bf16x8, __builtin_amdgcn_raw_buffer_load_b128(rs, rb + coff[b], 0, 0));
+  };
+  for (int64_t r = r0 + 32 * wave; r < r1; r += 256) {
+    bf16x8 x[2][NL];
+    load(r, x[0]);
+    load(r + 128, x[1]);
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      int t = 0;
+#pragma unroll
+      for (int a = 0; a < NBA; ++a)
+#pragma unroll
+        for (int bj = DIAG ? a : 0; bj < NBB; ++bj, ++t)
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x[d][a], x[d][DIAG ? bj : NBA + bj], acc[t], 0, 0, 0);
+    }
+  }
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+#pragma unroll
+      for (int t = 0; t < T; ++t)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float* dst = red + t * 256 + q * 64 + lane;
+          *dst = (w == 0) ? acc[t][q] : *dst + acc[t][q];
+        }
+    }
+    __syncthreads();
+  }
+  float* out = part + ((int64_t)blockIdx.x * gridDim.y + pair) * (int64_t)T * 256;
+  for (int i = threadIdx.x; i < T * 256; i += blockDim.x) out[i] = red[i];
+}
+
 // Level 1: sum groups of `group` consecutive chunk partials in FP64 (fixed order).
 __global__ void k_colsum_groups(const float* __restrict__ in, int64_t P, int64_t M, int group,
                                 double* __restrict__ out) {
@@ -252,7 +356,8 @@ __global__ void k_gram_reduce(const double* __restrict__ part, int nchunks, int 
 }
 
 template <int NBA, int NBB, bool DIAG, bool BF16>
-static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, int MB, double* G) {
+static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, int MB, double* G,
+                     const __bf16* Yb = nullptr, int KP = 0) {
   using TS = TileSet<NBA, NBB, DIAG>;
   constexpr int T = TS::count;
   if (npairs == 0) return;
@@ -271,7 +376,10 @@ static void run_gram(Ctx* c, const float* Y, int64_t R, int khat, int npairs, in
   float* part = c->gram_part.as<float>();
   double* part2 = reinterpret_cast<double*>(c->gram_part.as<char>() + ((b1 + 255) & ~(size_t)255));
   TK_REQUIRE(((b1 + 255) & ~(size_t)255) + b2 <= c->gram_part.bytes(), TK_ERR_DEVICE, "gram scratch");
-  if (BF16)
+  if (BF16 && Yb)
+    hipLaunchKernelGGL((k_gram_bf16b<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
+                       c->stream, Yb, R, KP, rows_per_wg, MB, part);
+  else if (BF16)
     hipLaunchKernelGGL((k_gram_bf16<NBA, NBB, DIAG>), dim3(nchunks, npairs), dim3(256), T * 256 * sizeof(float),
                        c->stream, Y, R, khat, rows_per_wg, MB, part);
   else
@@ -308,8 +416,21 @@ static void gram_impl(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
   }
   // macro blocks of 4 column blocks (64 columns): diagonal pairs and the upper off-diagonal pairs
   const int MB = (NB + 3) / 4;
-  run_gram<4, 4, true, BF16>(c, Y, R, khat, MB, MB, G);
-  run_gram<4, 4, false, BF16>(c, Y, R, khat, MB * (MB - 1) / 2, MB, G);
+  const __bf16* Yb = nullptr;
+  int KP = 0;
+  if (BF16) {
+    // Y is read once per macro pair: a BF16 copy in operand order first, so
+    // that every operand is one 16-byte load of half the bytes
+    KP = NB * 16;
+    const int64_t RB = ceil_div(R, 32);
+    ensure(c, c->ybf, sizeof(uint16_t) * (size_t)RB * KP * 32);
+    hipLaunchKernelGGL(k_y_bf16_blocked, dim3((unsigned)RB, (unsigned)ceil_div(KP, 64)), dim3(256), 0, c->stream, Y, R,
+                       khat, KP, c->ybf.as<__bf16>());
+    TK_CHECK_LAUNCH();
+    Yb = c->ybf.as<__bf16>();
+  }
+  run_gram<4, 4, true, BF16>(c, Y, R, khat, MB, MB, G, Yb, KP);
+  run_gram<4, 4, false, BF16>(c, Y, R, khat, MB * (MB - 1) / 2, MB, G, Yb, KP);
 }
 
 // G (khat x khat FP64, full) = Y^T Y; bf16 = operands rounded to BF16 (FP32 accumulation).

@@ -105,3 +105,32 @@ def test_bf16_run_final_fit_matches_oracle(tk, name, scale, iters):
     for n in range(len(w["dims"])):
         Fg = ctx.get_factor(n)
         np.testing.assert_allclose(Fg.T @ Fg, np.eye(w["ranks"][n]), atol=1e-12)
+
+
+def test_bf16_wide_khat_invocation_and_run(tk):
+    """The precision form's shape (4 modes, ranks 10: Y_(n) has 1000 columns),
+    where the BF16 Gram reads a blocked BF16 copy of Y: one BF16 invocation
+    within 1e-2 of the oracle, and a run of BF16 invocations closed by the
+    refining FP32 one at the oracle's final fit to 1e-5."""
+    dims, ranks = (400, 300, 200, 60), (10, 10, 10, 10)
+    idx, vals = synth.make_tensor(dims, 60_000, "zipf", (0.9, 1.1, 1.3, 0.7), "lognormal", seed=43)
+    w = {"dims": dims, "ranks": ranks, "idx": idx, "vals": vals, "F0": synth.orthonormal_init(43 + 7690, dims, ranks)}
+    ic, vc, _ = coo.coalesce_fast(w["idx"], w["vals"])
+    ctx = _ctx(tk, w, prec="bf16", refine=0)
+    for n, F in enumerate(w["F0"]):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    fits = ctx.hooi_iterate(1)
+    o1 = hooi.hooi(ic, vc, dims, w["F0"], ranks, 1)
+    print("bf16 fit", fits, "oracle", o1["fits"], flush=True)
+    assert abs(fits[0] - o1["fits"][0]) <= 1e-2
+    for n in range(4):
+        d = hooi.projector_distance(ctx.get_factor(n), o1["factors"][n])
+        print(f"mode {n}: BF16 projector distance {d:.2e}", flush=True)
+        assert d <= 1e-2
+    ctx2 = _ctx(tk, w, prec="bf16", refine=1)
+    for n, F in enumerate(w["F0"]):
+        ctx2.set_factor(n, np.ascontiguousarray(F))
+    fits = ctx2.hooi_iterate(3)
+    o3 = hooi.hooi(ic, vc, dims, w["F0"], ranks, 3)
+    print("bf16 run fits", fits, "oracle", o3["fits"], flush=True)
+    assert abs(fits[-1] - o3["fits"][-1]) <= 1e-5
