@@ -460,22 +460,22 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
 
 // ---- four-mode TTM-chain on the matrix cores ------------------------------------------------
 //
-// With remaining modes a, b, c (ascending), Y[row] viewed as K_a x K_b x K_c is
-//   sum_e val_e F_a[l_a(e)] (x) F_b[l_b(e)] (x) F_c[l_c(e)],
-// and for each c-index q its K_a x K_b slab is the contraction
-//   sum_e (val_e F_c[l_c(e)][q] F_a[l_a(e)]) F_b[l_b(e)]^T:
-// the three-mode MFMA step with the A operand scaled by the element's F_c
-// entry, KC MFMAs per 4-element step.  Column of Y: i + K_a (j + K_b q).
-// The three rows of each element are gathered with 16-byte loads into a 3 KB
-// LDS tile per wave, as in the three-mode kernel; the F_c row of the step's
-// element is then read back whole by its 16-lane group (a broadcast read).
+// With remaining modes a, b, c (ascending), Y[row] viewed as K_a x (K_b K_c) is
+//   sum_e (val_e F_a[l_a(e)])^T (F_b[l_b(e)] (x) F_c[l_c(e)]),
+// the three-mode MFMA step with B the Kronecker row of F_b and F_c: column
+// j + K_b q of B is F_b[l_b(e)][j] F_c[l_c(e)][q], formed per lane from the LDS
+// tile (two reads and a product), and the K_b K_c columns are covered by
+// NT = ceil(K_b K_c / 16) output tiles, NT MFMAs per 4-element step (7 for
+// ranks 10, against 10 with one tile per c-index).  Column of Y:
+// i + K_a (j + K_b q).  The three rows of each element are gathered with
+// 16-byte loads into a 3 KB LDS tile per wave, as in the three-mode kernel.
 // A wave's slices that continue into a neighbouring wave keep their partial
 // rows in registers and are added to the bin's LDS rows in wave order after
 // the main loop (no atomics, deterministic).
-template <int KC>
+template <int NT>
 __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int ka = A.Kj[0], kb = A.Kj[1];
+  const int ka = A.Kj[0], kb = A.Kj[1], kbc = A.Kj[1] * A.Kj[2];
   const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
   const int64_t e0 = A.bin_ptr[bin];
   const int E = (int)(A.bin_ptr[bin + 1] - e0);   // multiple of 4
@@ -520,7 +520,16 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   const int cs = min(wave * Q, E), ce = min(cs + Q, E);
   const int k = lane >> 4, cix = lane & 15;
   float* tile = tiles + wave * 768;
-  floatx4_t C[KC];
+  floatx4_t C[NT];
+  // column 16t + cix of the Kronecker row: tile offsets of its F_b and F_c
+  // entries (j = col % K_b, q = col / K_b), packed; columns past K_b K_c read
+  // entry 0 and are never written out
+  uint32_t pk[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int col = 16 * t + cix, okc = col < kbc;
+    pk[t] = (uint32_t)(256 + (okc ? col % kb : 0)) | ((uint32_t)(512 + (okc ? col / kb : 0)) << 16);
+  }
   bool has_right = false;
   int right_sg = 0;
   // row += this lane's part of C, for the merge after the main loop.  Even
@@ -528,21 +537,20 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
   // together and then written (one LDS round trip per slab instead of one per
   // entry).
   auto row_acc = [&](float* dst) __attribute__((always_inline)) {
-    if (cix >= kb) return;
-    float* p = dst + 4 * k + ka * cix;
-    const int qs = ka * kb;
     const bool h0 = 4 * k < ka, h1 = 4 * k + 2 < ka;
 #pragma unroll
-    for (int q = 0; q < KC; ++q) {
+    for (int t = 0; t < NT; ++t) {
+      if (16 * t + cix >= kbc) continue;
+      float* p = dst + 4 * k + ka * (16 * t + cix);
       if ((ka & 1) == 0) {
-        float2* w = reinterpret_cast<float2*>(p + q * qs);
+        float2* w = reinterpret_cast<float2*>(p);
         const float2 o0 = h0 ? w[0] : float2{0.f, 0.f}, o1 = h1 ? w[1] : float2{0.f, 0.f};
-        if (h0) w[0] = float2{o0.x + C[q][0], o0.y + C[q][1]};
-        if (h1) w[1] = float2{o1.x + C[q][2], o1.y + C[q][3]};
+        if (h0) w[0] = float2{o0.x + C[t][0], o0.y + C[t][1]};
+        if (h1) w[1] = float2{o1.x + C[t][2], o1.y + C[t][3]};
       } else {
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-          if (4 * k + r < ka) p[q * qs + r] += C[q][r];
+          if (4 * k + r < ka) p[r] += C[t][r];
       }
     }
   };
@@ -556,18 +564,18 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
     int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
     int seg_hi = uni(send[sg]);
 #pragma unroll
-    for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < NT; ++t) C[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     auto flush = [&]() __attribute__((always_inline)) {
       const bool left = seg_lo < cs, right = seg_hi > ce;
       if (!left && !right) {
         float* dst = rows + sg * khat;
-        if (cix < kb) {
 #pragma unroll
-          for (int q = 0; q < KC; ++q)
+        for (int t = 0; t < NT; ++t)
+          if (16 * t + cix < kbc) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] = C[q][r];
-        }
+              if (4 * k + r < ka) dst[4 * k + r + ka * (16 * t + cix)] = C[t][r];
+          }
       } else if (right) {   // the last slice of the quarter: stays in C
         has_right = true;
         right_sg = sg;
@@ -578,18 +586,17 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
         // row before the barrier (the earlier waves add theirs after it), so
         // the order of the sum is fixed.
         float* dst = rows + sg * khat;
-        if (cix < kb) {
 #pragma unroll
-          for (int q = 0; q < KC; ++q)
+        for (int t = 0; t < NT; ++t)
+          if (16 * t + cix < kbc) {
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-              if (4 * k + r < ka) dst[4 * k + r + ka * (cix + kb * q)] += C[q][r];
-        }
+              if (4 * k + r < ka) dst[4 * k + r + ka * (16 * t + cix)] += C[t][r];
+          }
       }
 #pragma unroll
-      for (int q = 0; q < KC; ++q) C[q] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+      for (int t = 0; t < NT; ++t) C[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
     };
-    constexpr int NC4 = (KC + 3) / 4;
     // gather of block g: lane l takes element g + l/4, 16-byte quarter l%4 of
     // its three rows (all lanes load: the copies are zero beyond column K)
     struct Blk { u32x4 x, y, z; float v; };
@@ -609,12 +616,9 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       reinterpret_cast<u32x4*>(tile + 256)[lane] = r.y;
       reinterpret_cast<u32x4*>(tile + 512)[lane] = r.z;
       wave_lds_sync();
-      float xa[4], xb[4];
+      float xa[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        xa[u] = tile[(4 * u + k) * 16 + cix];
-        xb[u] = tile[256 + (4 * u + k) * 16 + cix];
-      }
+      for (int u = 0; u < 4; ++u) xa[u] = tile[(4 * u + k) * 16 + cix];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int gu = g + 4 * u;
@@ -625,12 +629,10 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
           seg_lo = seg_hi;
           seg_hi = uni(send[sg]);
         }
-        float4 c4[NC4];
+        const float* te = tile + (4 * u + k) * 16;
 #pragma unroll
-        for (int h = 0; h < NC4; ++h) c4[h] = reinterpret_cast<const float4*>(tile + 512 + (4 * u + k) * 16)[h];
-        const float* cv = reinterpret_cast<const float*>(c4);
-#pragma unroll
-        for (int q = 0; q < KC; ++q) C[q] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u] * cv[q], xb[u], C[q], 0, 0, 0);
+        for (int t = 0; t < NT; ++t)
+          C[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], te[pk[t] & 0xffffu] * te[pk[t] >> 16], C[t], 0, 0, 0);
       }
       wave_lds_sync();   // the next block's write follows these reads
     };
@@ -859,9 +861,9 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
                        sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     const dim3 g((unsigned)pl.P), b(256);
-    switch (a.Kj[2]) {
-#define TK_TTM4_CASE(KC) \
-      case KC: hipLaunchKernelGGL(k_ttm4_mfma<KC>, g, b, lds, c->stream, a, Epad, nseg_pad); break;
+    switch ((a.Kj[1] * a.Kj[2] + 15) / 16) {
+#define TK_TTM4_CASE(NT) \
+      case NT: hipLaunchKernelGGL(k_ttm4_mfma<NT>, g, b, lds, c->stream, a, Epad, nseg_pad); break;
       TK_TTM4_CASE(1) TK_TTM4_CASE(2) TK_TTM4_CASE(3) TK_TTM4_CASE(4) TK_TTM4_CASE(5) TK_TTM4_CASE(6)
       TK_TTM4_CASE(7) TK_TTM4_CASE(8) TK_TTM4_CASE(9) TK_TTM4_CASE(10) TK_TTM4_CASE(11) TK_TTM4_CASE(12)
       TK_TTM4_CASE(13) TK_TTM4_CASE(14) TK_TTM4_CASE(15) TK_TTM4_CASE(16)
