@@ -122,6 +122,8 @@ TTM_CASES = {
     "4mode_k10": (lambda: zipf_tensor((600, 500, 200, 40), 40_000, s=(0.9, 1.1, 1.3, 0.7), seed=35),
                   (10, 10, 10, 10), 2048),
     "4mode_odd": (lambda: zipf_tensor((300, 200, 100, 30), 20_000, s=1.0, seed=36), (3, 4, 2, 5), 1024),
+    # K_b K_c = 256: sixteen output tiles per step in the four-mode kernel
+    "4mode_k16": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=40), (4, 16, 16, 16), 1024),
     "2mode": (lambda: zipf_tensor((2000, 1500), 40_000, s=1.1, seed=37), (8, 6), 1024),
     "5mode": (lambda: zipf_tensor((60, 50, 40, 30, 20), 20_000, s=1.0, seed=38), (3, 2, 4, 2, 3), 512),
     # one slice split over ~2,400 bins of 16: a three-level fixup tree
