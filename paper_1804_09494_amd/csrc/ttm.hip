@@ -687,28 +687,32 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
 // fixed shape: each level adds runs of at most FIX_CHUNK consecutive rows of
 // one slice into new rows, then each slice's last rows go to Y (deterministic,
 // and parallel however many bins a slice is split over).
+// Sum of the at most FIX_CHUNK partial rows [a, b) of buf, column c, in row
+// order: every load is issued before the first add (the rows are independent),
+// then the adds run in the fixed order.
+__device__ __forceinline__ float fix_sum(const float* __restrict__ buf, int a, int b, int khat, int c) {
+  float v[FIX_CHUNK];
+#pragma unroll
+  for (int i = 0; i < FIX_CHUNK; ++i) v[i] = a + i < b ? buf[(int64_t)(a + i) * khat + c] : 0.f;
+  float s = 0.f;
+#pragma unroll
+  for (int i = 0; i < FIX_CHUNK; ++i)
+    if (a + i < b) s += v[i];
+  return s;
+}
 __global__ void k_fixup_level(const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, int64_t first,
                               float* __restrict__ buf, int khat) {
   const int64_t t = blockIdx.x;
   const int a = lo[t], b = hi[t];
   float* out = buf + (first + t) * khat;
-  for (int c = threadIdx.x; c < khat; c += blockDim.x) {
-    float s = 0.f;
-    for (int r = a; r < b; ++r) s += buf[(int64_t)r * khat + c];
-    out[c] = s;
-  }
+  for (int c = threadIdx.x; c < khat; c += blockDim.x) out[c] = fix_sum(buf, a, b, khat, c);
 }
-
 __global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ fin, int64_t nbad,
                         const float* __restrict__ buf, int khat, float* __restrict__ Y) {
   const int64_t k = blockIdx.x;
   const int a = fin[k], b = fin[nbad + k];
   const int64_t row = bad_row[k];
-  for (int c = threadIdx.x; c < khat; c += blockDim.x) {
-    float s = 0.f;
-    for (int r = a; r < b; ++r) s += buf[(int64_t)r * khat + c];
-    Y[row * khat + c] = s;
-  }
+  for (int c = threadIdx.x; c < khat; c += blockDim.x) Y[row * khat + c] = fix_sum(buf, a, b, khat, c);
 }
 
 // ---- dispatch -----------------------------------------------------------------------------------
