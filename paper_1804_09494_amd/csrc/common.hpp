@@ -39,7 +39,7 @@ struct Error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-constexpr int FIX_CHUNK = 32;  // partial rows summed per fixup block
+constexpr int FIX_CHUNK = 128;  // partial rows summed per fixup block (one tree level for up to 16K)
 
 struct Ctx;
 

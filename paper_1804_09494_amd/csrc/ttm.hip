@@ -688,16 +688,18 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
 // one slice into new rows, then each slice's last rows go to Y (deterministic,
 // and parallel however many bins a slice is split over).
 // Sum of the at most FIX_CHUNK partial rows [a, b) of buf, column c, in row
-// order: every load is issued before the first add (the rows are independent),
-// then the adds run in the fixed order.
+// order: the loads of each batch of 32 rows are issued before its first add
+// (the rows are independent), then the adds run in the fixed order.
 __device__ __forceinline__ float fix_sum(const float* __restrict__ buf, int a, int b, int khat, int c) {
-  float v[FIX_CHUNK];
-#pragma unroll
-  for (int i = 0; i < FIX_CHUNK; ++i) v[i] = a + i < b ? buf[(int64_t)(a + i) * khat + c] : 0.f;
   float s = 0.f;
+  for (int a0 = a; a0 < b; a0 += 32) {
+    float v[32];
 #pragma unroll
-  for (int i = 0; i < FIX_CHUNK; ++i)
-    if (a + i < b) s += v[i];
+    for (int i = 0; i < 32; ++i) v[i] = a0 + i < b ? buf[(int64_t)(a0 + i) * khat + c] : 0.f;
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (a0 + i < b) s += v[i];
+  }
   return s;
 }
 __global__ void k_fixup_level(const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, int64_t first,

@@ -126,8 +126,8 @@ TTM_CASES = {
     "4mode_k16": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=40), (4, 16, 16, 16), 1024),
     "2mode": (lambda: zipf_tensor((2000, 1500), 40_000, s=1.1, seed=37), (8, 6), 1024),
     "5mode": (lambda: zipf_tensor((60, 50, 40, 30, 20), 20_000, s=1.0, seed=38), (3, 2, 4, 2, 3), 512),
-    # one slice split over ~2,400 bins of 16: a three-level fixup tree
-    "deep_fixup": (lambda: _giant_slice_tensor(40_000, 3_000, seed=39), (4, 4, 4), 16),
+    # one slice split over ~19,000 bins of 16: a fixup tree of two levels (runs of 128)
+    "deep_fixup": (lambda: _giant_slice_tensor(300_000, 3_000, seed=39), (4, 4, 4), 16),
 }
 
 
@@ -135,8 +135,8 @@ def _giant_slice_tensor(n_giant, n_rest, seed):
     rng = np.random.default_rng(seed)
     i0 = np.concatenate([np.zeros(n_giant, np.int32), rng.integers(1, 500, n_rest, dtype=np.int32)])
     j = np.arange(n_giant + n_rest)
-    i1 = (j % 311).astype(np.int32)
-    i2 = ((j * 7) % 97).astype(np.int32)
+    i1 = (j % 3001).astype(np.int32)
+    i2 = ((j * 7) % 997).astype(np.int32)
     return [i0, i1, i2], rng.standard_normal(n_giant + n_rest).astype(np.float32)
 
 
