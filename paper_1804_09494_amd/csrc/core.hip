@@ -11,48 +11,54 @@
 
 namespace tk {
 
-constexpr int CORE_TILE = 64;
+constexpr int CORE_ROWS = 64;   // rows per workgroup: many short workgroups hide the load latency
 
+// Workgroup partial of G_(N) over rows [r0, r1) (at most CORE_ROWS): thread t
+// owns column blockIdx.y * 256 + t and entries k0 .. k0 + KM - 1 of it
+// (k0 = blockIdx.z * KM), accumulated in row order.  The slices' factor rows
+// are staged in LDS (read back as broadcasts); Y is read straight from HBM,
+// coalesced along the row, sixteen rows' loads issued before their products.
+template <int KM>
 __global__ __launch_bounds__(256) void k_core_part(const float* __restrict__ Y, int64_t R, int khat,
                                                    const double* __restrict__ F, int K,
                                                    const int32_t* __restrict__ row_slice, int rows_per_wg,
-                                                   int tile, double* __restrict__ part) {
-  extern __shared__ double shc[];
-  double* ft = shc;                                      // tile x K
-  float* yt = reinterpret_cast<float*>(ft + tile * K);   // tile x khat
+                                                   double* __restrict__ part) {
+  __shared__ double ft[CORE_ROWS * KM];
   const int64_t r0 = (int64_t)blockIdx.x * rows_per_wg;
-  const int64_t r1 = min<int64_t>(r0 + rows_per_wg, R);
-  const int nent = K * khat;
-  // each thread owns entries i = tid, tid + 256, ... (at most 8 here; larger sets loop)
-  for (int base = 0; base < nent; base += 256 * 8) {
-    double acc[8];
+  const int nr = (int)min<int64_t>(rows_per_wg, R - r0);
+  const int col = blockIdx.y * 256 + threadIdx.x;
+  const bool ok = col < khat;
+  const int cl = ok ? col : 0;
+  const int k0 = blockIdx.z * KM, kn = min(KM, K - k0);
+  for (int i = threadIdx.x; i < nr * KM; i += 256) {
+    const int r = i / KM, k = i - r * KM;
+    ft[i] = k < kn ? F[(int64_t)row_slice[r0 + r] * K + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  double acc[KM];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc[u] = 0.0;
-    for (int64_t t0 = r0; t0 < r1; t0 += tile) {
-      const int nr = (int)min<int64_t>(tile, r1 - t0);
-      __syncthreads();
-      for (int i = threadIdx.x; i < nr * K; i += blockDim.x) {
-        const int r = i / K, k = i - r * K;
-        ft[i] = F[(int64_t)row_slice[t0 + r] * K + k];
-      }
-      for (int i = threadIdx.x; i < nr * khat; i += blockDim.x) yt[i] = Y[t0 * khat + i];
-      __syncthreads();
+  for (int k = 0; k < KM; ++k) acc[k] = 0.0;
+  const float* yb = Y + r0 * khat + cl;
+  int r = 0;
+  for (; r + 16 <= nr; r += 16) {
+    float y[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int i = base + u * 256 + threadIdx.x;
-        if (i < nent) {
-          const int k = i / khat, col = i - k * khat;
-          double s = acc[u];
-          for (int r = 0; r < nr; ++r) s += ft[r * K + k] * (double)yt[r * khat + col];
-          acc[u] = s;
-        }
-      }
-    }
+    for (int u = 0; u < 16; ++u) y[u] = yb[(int64_t)(r + u) * khat];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = base + u * 256 + threadIdx.x;
-      if (i < nent) part[(int64_t)blockIdx.x * nent + i] = acc[u];
-    }
+    for (int u = 0; u < 16; ++u)
+#pragma unroll
+      for (int k = 0; k < KM; ++k) acc[k] += ft[(r + u) * KM + k] * (double)y[u];
+  }
+  for (; r < nr; ++r) {
+    const double y = (double)yb[(int64_t)r * khat];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) acc[k] += ft[r * KM + k] * y;
+  }
+  if (ok) {
+    const int64_t nent = (int64_t)K * khat;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < kn) part[(int64_t)blockIdx.x * nent + (int64_t)(k0 + k) * khat + col] = acc[k];
   }
 }
 
@@ -105,7 +111,7 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   const int64_t R = pl.L_nz;
   const int khat = (int)pl.khat;
   const int K = c->K[n];
-  int rows_per_wg = (int)std::max<int64_t>(CORE_TILE, ceil_div(ceil_div(std::max<int64_t>(R, 1), 1024), CORE_TILE) * CORE_TILE);
+  const int rows_per_wg = CORE_ROWS;
   const int nwg = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
   const int nent = K * khat;
   const int ngroups = (nwg + CORE_GROUP - 1) / CORE_GROUP;
@@ -113,13 +119,9 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   double* part = c->gram_part.as<double>();
   double* gsum = part + (size_t)nwg * nent;
   if (R > 0) {
-    // rows staged per pass: CORE_TILE, fewer when Khat is wide
-    const int64_t per_row = sizeof(double) * K + sizeof(float) * (int64_t)khat;
-    const int tile = (int)std::min<int64_t>(CORE_TILE, ((int64_t)c->lds_per_block - 1024) / per_row);
-    TK_REQUIRE(tile >= 1, TK_ERR_UNSUPPORTED, "core: Khat too large for LDS");
-    const size_t lds = (size_t)per_row * tile;
-    hipLaunchKernelGGL(k_core_part, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
-                       pl.row_slice.as<int32_t>(), rows_per_wg, tile, part);
+    const dim3 g((unsigned)nwg, (unsigned)ceil_div(khat, 256), (unsigned)ceil_div(K, 16));
+    hipLaunchKernelGGL(k_core_part<16>, g, dim3(256), 0, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
+                       pl.row_slice.as<int32_t>(), rows_per_wg, part);
     TK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_core_group, dim3((unsigned)ceil_div(nent, 256), ngroups), dim3(256), 0, c->stream, part,
                        nwg, nent, gsum);
