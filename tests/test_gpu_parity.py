@@ -124,6 +124,10 @@ TTM_CASES = {
     "4mode_odd": (lambda: zipf_tensor((300, 200, 100, 30), 20_000, s=1.0, seed=36), (3, 4, 2, 5), 1024),
     # K_b K_c = 256: sixteen output tiles per step in the four-mode kernel
     "4mode_k16": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=40), (4, 16, 16, 16), 1024),
+    # ranks above 16: the vector-ALU kernel (K̂ = 340, 544, 640)
+    "k32_vector": (lambda: zipf_tensor((500, 400, 300), 30_000, s=1.0, seed=45), (32, 20, 17), 1024),
+    # the default bin size (448 elements for the three-mode matrix-core kernel)
+    "default_bins": (lambda: zipf_tensor((5000, 3000, 800), 200_000, s=1.1, seed=46), (10, 10, 10), 0),
     "2mode": (lambda: zipf_tensor((2000, 1500), 40_000, s=1.1, seed=37), (8, 6), 1024),
     "5mode": (lambda: zipf_tensor((60, 50, 40, 30, 20), 20_000, s=1.0, seed=38), (3, 2, 4, 2, 3), 512),
     # one slice split over ~19,000 bins of 16: a fixup tree of two levels (runs of 128)
@@ -254,6 +258,14 @@ def _wide_workload(dims, nnz, zipf, ranks, seed):
 def test_hooi_wide_khat_block_krylov(tk):
     """Khat = 216 (4 modes, ranks 6): the eigensolve takes the block-Krylov path."""
     w = _wide_workload((300, 200, 120, 60), 40_000, (0.9, 1.1, 1.3, 0.7), (6, 6, 6, 6), 41)
+    _hooi_compare(tk, w, 2)
+
+
+def test_hooi_ranks_above_16(tk):
+    """Ranks 20 / 18 / 17: the vector-ALU TTM-chain, the factor step without
+    matrix cores, the general Cholesky and the dense eigensolve for more than
+    16 pairs (K̂ = 306, 340, 360)."""
+    w = _wide_workload((300, 250, 200), 40_000, (1.0, 1.1, 1.2), (20, 18, 17), 44)
     _hooi_compare(tk, w, 2)
 
 
