@@ -269,6 +269,37 @@ def test_hooi_ranks_above_16(tk):
     _hooi_compare(tk, w, 2)
 
 
+def test_hooi_rank_one(tk):
+    """Ranks 1 / 1 / 1: one-column factors, a 1 x 1 Gram, one-column rows of Y."""
+    w = _wide_workload((400, 300, 200), 30_000, (1.0, 1.1, 1.2), (1, 1, 1), 47)
+    _hooi_compare(tk, w, 2)
+
+
+def test_hooi_full_rank_dense_reconstruction(tk):
+    """K_n = L_n on a dense-filled 6 x 5 x 4 tensor: the model reproduces T, so
+    the core carries all of ||T|| and every factor is square orthogonal.  The
+    fit 1 - sqrt(||T||^2 - ||G||^2)/||T|| takes the square root of a rounding
+    residual here, so it is held to 1e-3 while ||G|| is held to 1e-6."""
+    dims = (6, 5, 4)
+    g = np.indices(dims).reshape(3, -1).astype(np.int32)
+    idx = [np.ascontiguousarray(g[n]) for n in range(3)]
+    vals = synth.normal(91, 0, g.shape[1]).astype(np.float32)
+    ctx = _load(tk, idx, vals, dims, dims)
+    F0 = synth.orthonormal_init(4243, dims, dims)
+    for n, F in enumerate(F0):
+        ctx.set_factor(n, np.ascontiguousarray(F))
+    fits = ctx.hooi_iterate(2)
+    core, fit = ctx.core()
+    tn = np.linalg.norm(vals.astype(np.float64))
+    print("fits", fits, "||G||/||T||", np.linalg.norm(core) / tn, flush=True)
+    assert abs(np.linalg.norm(core) / tn - 1.0) <= 1e-6
+    assert fit >= 1.0 - 1e-3
+    for n in range(3):
+        Fg = ctx.get_factor(n)
+        np.testing.assert_allclose(Fg.T @ Fg, np.eye(dims[n]), atol=1e-12)
+        np.testing.assert_allclose(Fg @ Fg.T, np.eye(dims[n]), atol=1e-12)
+
+
 def test_hooi_khat_1000_precision_form_shape(tk):
     """The precision form's shape at small scale: 4 modes, ranks 10 (Y_(n) has
     1000 columns), Zipf 0.9/1.1/1.3/0.7; FP32 path against the oracle."""
