@@ -128,6 +128,9 @@ TTM_CASES = {
     "k32_vector": (lambda: zipf_tensor((500, 400, 300), 30_000, s=1.0, seed=45), (32, 20, 17), 1024),
     # the default bin size (448 elements for the three-mode matrix-core kernel)
     "default_bins": (lambda: zipf_tensor((5000, 3000, 800), 200_000, s=1.1, seed=46), (10, 10, 10), 0),
+    # four modes with a rank above 16: mode 0 on the four-mode matrix-core kernel,
+    # modes 1-3 on the vector-ALU kernel with K_a = 20
+    "4mode_k20": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=48), (20, 6, 5, 4), 1024),
     "2mode": (lambda: zipf_tensor((2000, 1500), 40_000, s=1.1, seed=37), (8, 6), 1024),
     "5mode": (lambda: zipf_tensor((60, 50, 40, 30, 20), 20_000, s=1.0, seed=38), (3, 2, 4, 2, 3), 512),
     # one slice split over ~19,000 bins of 16: a fixup tree of two levels (runs of 128)
