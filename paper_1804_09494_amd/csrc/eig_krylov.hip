@@ -26,6 +26,7 @@ constexpr int KR_B = 16;    // block width
 constexpr int KR_S = 6;     // blocks per cycle (subspace KR_S * KR_B = 96: the dense solver's LDS path)
 constexpr int KR_M = KR_B * KR_S;
 constexpr int KR_CYCLES = 4;
+constexpr int KR_TN_WAVES = 16;   // waves splitting the rows of one A^T B tile
 
 typedef double doublex4_k __attribute__((ext_vector_type(4)));
 
@@ -80,15 +81,17 @@ __global__ __launch_bounds__(256) void k_kr_nn(const double* __restrict__ A, int
 }
 
 // out (J x nc, row-major) = A^T B over n rows (A: n x J, lda; B: n x nc, ldb).
-// One workgroup per 16 x 16 output tile (blockIdx.x: rows of out, blockIdx.y: columns).
-__global__ __launch_bounds__(256) void k_kr_tn(const double* __restrict__ A, int lda, int J,
-                                               const double* __restrict__ B, int ldb, int nc, int n,
-                                               double* __restrict__ out) {
-  __shared__ double red[256];
+// One workgroup per 16 x 16 output tile (blockIdx.x: rows of out, blockIdx.y: columns);
+// its sixteen waves take consecutive row ranges, so the chain of dependent
+// matrix-core steps per wave is short (a handful of tiles fill few CUs).
+__global__ __launch_bounds__(KR_TN_WAVES * 64) void k_kr_tn(const double* __restrict__ A, int lda, int J,
+                                                           const double* __restrict__ B, int ldb, int nc, int n,
+                                                           double* __restrict__ out) {
+  __shared__ double red[KR_TN_WAVES * 256];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i16 = lane & 15, q = lane >> 4;
   const int i0 = blockIdx.x * 16, c0 = blockIdx.y * 16;
-  const int nw = ((n + 15) / 16) * 4;   // rows per wave, a multiple of 4
+  const int nw = ((n + 4 * KR_TN_WAVES - 1) / (4 * KR_TN_WAVES)) * 4;   // rows per wave, a multiple of 4
   const int s0 = wave * nw, s1 = min(s0 + nw, n);
   const bool aok = i0 + i16 < J, bok = c0 + i16 < nc;
   doublex4_k acc = {0.0, 0.0, 0.0, 0.0};
@@ -100,12 +103,17 @@ __global__ __launch_bounds__(256) void k_kr_tn(const double* __restrict__ A, int
     const double b = (rok && bok) ? B[(int64_t)rr * ldb + c0 + i16] : 0.0;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  acc = kr_wave_sum(acc, red);
+  // the waves' partials, summed by wave 0 in wave order
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + r * 64 + lane] = acc[r];
+  __syncthreads();
   if (wave == 0 && bok) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      double t = 0.0;
+      for (int w = 0; w < KR_TN_WAVES; ++w) t += red[w * 256 + r * 64 + lane];
       const int ii = i0 + q + 4 * r;
-      if (ii < J) out[(int64_t)ii * nc + c0 + i16] = acc[r];
+      if (ii < J) out[(int64_t)ii * nc + c0 + i16] = t;
     }
   }
 }
@@ -246,7 +254,8 @@ unsigned g16(int64_t n) { return (unsigned)((n + 15) / 16); }
 
 // out (J x nc) = A^T B over n rows
 void tn(Ctx* c, const double* A, int lda, int J, const double* B, int ldb, int nc, int n, double* out) {
-  hipLaunchKernelGGL(k_kr_tn, dim3(g16(J), g16(nc)), dim3(256), 0, c->stream, A, lda, J, B, ldb, nc, n, out);
+  hipLaunchKernelGGL(k_kr_tn, dim3(g16(J), g16(nc)), dim3(KR_TN_WAVES * 64), 0, c->stream, A, lda, J, B, ldb, nc, n,
+                     out);
   TK_CHECK_LAUNCH();
 }
 
