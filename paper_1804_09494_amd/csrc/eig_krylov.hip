@@ -184,17 +184,27 @@ __global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, in
     for (int i = l; i < b * b; i += 64) Rinv[i] = 0.0;
     return;
   }
-  // column c of R^-1 by back substitution, one lane per column
+  // column c of R^-1 by back substitution, one lane per column with the
+  // column in registers; the entries of row i of R are the same for every lane
+  // (broadcast reads), and x[k] = 0 for k > c leaves the sums as they are
   if (l < b) {
     const int c = l;
-    double* x = X + c * KR_B;
-    for (int i = 0; i < b; ++i) x[i] = 0.0;
-    x[c] = 1.0 / R[c * KR_B + c];
-    for (int i = c - 1; i >= 0; --i) {
-      double s = 0.0;
-      for (int k = i + 1; k <= c; ++k) s += R[i * KR_B + k] * x[k];
-      x[i] = -s / R[i * KR_B + i];
+    double x[KR_B];
+#pragma unroll
+    for (int i = 0; i < KR_B; ++i) x[i] = 0.0;
+#pragma unroll
+    for (int i = KR_B - 1; i >= 0; --i) {
+      if (i < b) {
+        double s = 0.0;   // minus the sum
+#pragma unroll
+        for (int k = i + 1; k < KR_B; ++k)
+          if (k < b) s -= R[i * KR_B + k] * x[k];
+        x[i] = i == c ? 1.0 / R[c * KR_B + c] : (i < c ? s / R[i * KR_B + i] : 0.0);
+      }
     }
+#pragma unroll
+    for (int i = 0; i < KR_B; ++i)
+      if (i < b) X[c * KR_B + i] = x[i];
   }
   __syncthreads();
   for (int t = l; t < b * b; t += 64) {
