@@ -32,35 +32,23 @@ typedef double doublex4_k __attribute__((ext_vector_type(4)));
 
 // The tall-skinny products run on the FP64 matrix cores (v_mfma_f64_16x16x4_f64:
 // lane l supplies A[i = l%16][k = l/16] and B[k = l/16][j = l%16]; register r
-// of the result holds D[l/16 + 4r][l%16]).  The k range is split over the four
+// of the result holds D[l/16 + 4r][l%16]).  The k range is split over the
 // waves of a workgroup and their tiles are summed in LDS in wave order, so
 // every result is deterministic.
-__device__ __forceinline__ doublex4_k kr_wave_sum(doublex4_k acc, double* red) {
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  for (int w = 0; w < 4; ++w) {
-    if (wave == w)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) red[r * 64 + lane] = (w == 0 ? 0.0 : red[r * 64 + lane]) + acc[r];
-    __syncthreads();
-  }
-  doublex4_k out;
-#pragma unroll
-  for (int r = 0; r < 4; ++r) out[r] = red[r * 64 + lane];
-  return out;
-}
 
 // D (n x nc, ldd) = A (n x J, lda) C (J x nc, ldc), or D = S - A C when SUB
-// (S may be D itself); nc <= 16.  One workgroup per 16-row block.
-template <bool SUB>
-__global__ __launch_bounds__(256) void k_kr_nn(const double* __restrict__ A, int lda, int J,
-                                               const double* __restrict__ C, int ldc, const double* S, int lds,
-                                               double* D, int ldd, int n, int nc) {
-  __shared__ double red[256];
+// (S may be D itself); nc <= 16.  One workgroup per 16-row block, whose NW
+// waves take consecutive parts of the k range.
+template <bool SUB, int NW>
+__global__ __launch_bounds__(NW * 64) void k_kr_nn(const double* __restrict__ A, int lda, int J,
+                                                  const double* __restrict__ C, int ldc, const double* S, int lds,
+                                                  double* D, int ldd, int n, int nc) {
+  __shared__ double red[NW * 256];
   const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int i16 = lane & 15, q = lane >> 4;
   const int r0 = blockIdx.x * 16;
   const int row = r0 + i16;
-  const int Jw = ((J + 15) / 16) * 4;   // k per wave, a multiple of 4
+  const int Jw = ((J + 4 * NW - 1) / (4 * NW)) * 4;   // k per wave, a multiple of 4
   const int k0 = wave * Jw, k1 = min(k0 + Jw, J);
   doublex4_k acc = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
@@ -70,12 +58,17 @@ __global__ __launch_bounds__(256) void k_kr_nn(const double* __restrict__ A, int
     const double b = (kk < k1 && i16 < nc) ? C[(int64_t)kk * ldc + i16] : 0.0;
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
   }
-  acc = kr_wave_sum(acc, red);
+  // the waves' partials, summed by wave 0 in wave order
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wave * 256 + r * 64 + lane] = acc[r];
+  __syncthreads();
   if (wave == 0 && i16 < nc) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      double t = 0.0;
+      for (int w = 0; w < NW; ++w) t += red[w * 256 + r * 64 + lane];
       const int rr = r0 + q + 4 * r;
-      if (rr < n) D[(int64_t)rr * ldd + i16] = SUB ? S[(int64_t)rr * lds + i16] - acc[r] : acc[r];
+      if (rr < n) D[(int64_t)rr * ldd + i16] = SUB ? S[(int64_t)rr * lds + i16] - t : t;
     }
   }
 }
@@ -273,7 +266,13 @@ void tn(Ctx* c, const double* A, int lda, int J, const double* B, int ldb, int n
 template <bool SUB>
 void nn(Ctx* c, const double* A, int lda, int J, const double* C, int ldc, const double* S, int lds, double* D,
         int ldd, int n, int nc) {
-  hipLaunchKernelGGL(k_kr_nn<SUB>, dim3(g16(n)), dim3(256), 0, c->stream, A, lda, J, C, ldc, S, lds, D, ldd, n, nc);
+  // a long k range (G Q) goes over sixteen waves, so each wave's chain of dependent steps is short
+  if (J >= 256)
+    hipLaunchKernelGGL((k_kr_nn<SUB, 16>), dim3(g16(n)), dim3(16 * 64), 0, c->stream, A, lda, J, C, ldc, S, lds, D, ldd,
+                       n, nc);
+  else
+    hipLaunchKernelGGL((k_kr_nn<SUB, 4>), dim3(g16(n)), dim3(4 * 64), 0, c->stream, A, lda, J, C, ldc, S, lds, D, ldd,
+                       n, nc);
   TK_CHECK_LAUNCH();
 }
 
