@@ -124,85 +124,87 @@ __global__ __launch_bounds__(KR_TN_WAVES * 64) void k_kr_tn(const double* __rest
 // its row of R is set to e_j and its column of Rinv to zero, so it adds
 // nothing to the other columns and comes out zero.  An all-zero block zeroes
 // Rinv.
+// x of lane l (l wave-uniform)
+__device__ __forceinline__ double kr_lane(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(unsigned)(v & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+
+// Lane k keeps column k of the block in registers (x[i] = A[i][k], then
+// R[i][k] in the upper triangle); an entry of another column is read across
+// lanes, so the factorisation and the inverse need no LDS and no barrier.
 __global__ __launch_bounds__(64) void k_kr_chol(const double* __restrict__ A, int b, double* __restrict__ Rinv,
                                                int shift_rows) {
-  __shared__ double R[KR_B * KR_B], X[KR_B * KR_B];
-  __shared__ int okf, dead;
   const int l = threadIdx.x;
-  for (int i = l; i < KR_B * KR_B; i += 64) {
-    const int r = i / KR_B, cc = i % KR_B;
-    R[i] = (r < b && cc < b) ? A[r * b + cc] : 0.0;
-  }
-  if (l == 0) {
-    okf = 1;
-    dead = 0;
-  }
-  __syncthreads();
+  double x[KR_B];
+#pragma unroll
+  for (int i = 0; i < KR_B; ++i) x[i] = (i < b && l < b) ? A[i * b + l] : 0.0;
   if (shift_rows > 0) {
     double tr = 0.0;
-    for (int i = 0; i < b; ++i) tr += R[i * KR_B + i];
+#pragma unroll
+    for (int i = 0; i < KR_B; ++i)
+      if (i < b) tr += kr_lane(x[i], i);
     const double sh = 11.0 * ((double)shift_rows * b + (double)b * (b + 1)) * 0x1p-53 * tr;
-    __syncthreads();
-    if (l < b) R[l * KR_B + l] += sh;
-    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < KR_B; ++i)
+      if (i == l && l < b) x[i] += sh;
   }
   double dmax = 0.0;
-  for (int i = 0; i < b; ++i) dmax = fmax(dmax, R[i * KR_B + i]);
-  if (!(dmax > 0.0) && l == 0) okf = 0;
-  __syncthreads();
-  // R in the upper triangle, row j: R[j][j..b-1]
-  for (int j = 0; j < b && okf; ++j) {
-    const double d = R[j * KR_B + j];
-    __syncthreads();
-    if (!(d > 1e-14 * dmax)) {   // dependent column: dropped
-      if (l == 0) {
-        R[j * KR_B + j] = 1.0;
-        dead |= 1 << j;
-      }
-      if (l > j && l < b) R[j * KR_B + l] = 0.0;
-      __syncthreads();
-      continue;
-    }
-    const double rjj = sqrt(d), ri = 1.0 / rjj;
-    if (l > j && l < b) R[j * KR_B + l] *= ri;
-    if (l == 0) R[j * KR_B + j] = rjj;
-    __syncthreads();
-    for (int t = l; t < KR_B * KR_B; t += 64) {
-      const int i = t / KR_B, k = t % KR_B;
-      if (i > j && k >= i && k < b) R[i * KR_B + k] -= R[j * KR_B + i] * R[j * KR_B + k];
-    }
-    __syncthreads();
-  }
-  if (!okf) {
+#pragma unroll
+  for (int i = 0; i < KR_B; ++i)
+    if (i < b) dmax = fmax(dmax, kr_lane(x[i], i));
+  if (!(dmax > 0.0)) {
     for (int i = l; i < b * b; i += 64) Rinv[i] = 0.0;
     return;
   }
-  // column c of R^-1 by back substitution, one lane per column with the
-  // column in registers; the entries of row i of R are the same for every lane
-  // (broadcast reads), and x[k] = 0 for k > c leaves the sums as they are
-  if (l < b) {
-    const int c = l;
-    double x[KR_B];
+  // R in the upper triangle, row j: R[j][j..b-1] (lane k holds R[j][k] in x[j])
+  int dead = 0;
 #pragma unroll
-    for (int i = 0; i < KR_B; ++i) x[i] = 0.0;
+  for (int j = 0; j < KR_B; ++j) {
+    if (j < b) {
+      const double d = kr_lane(x[j], j);
+      if (!(d > 1e-14 * dmax)) {   // dependent column: dropped
+        dead |= 1 << j;
+        if (l == j) x[j] = 1.0;
+        if (l > j && l < b) x[j] = 0.0;
+      } else {
+        const double rjj = sqrt(d), ri = 1.0 / rjj;
+        if (l > j && l < b) x[j] *= ri;
+        if (l == j) x[j] = rjj;
+        // trailing update A[i][k] -= R[j][i] R[j][k], j < i <= k
 #pragma unroll
-    for (int i = KR_B - 1; i >= 0; --i) {
-      if (i < b) {
-        double s = 0.0;   // minus the sum
-#pragma unroll
-        for (int k = i + 1; k < KR_B; ++k)
-          if (k < b) s -= R[i * KR_B + k] * x[k];
-        x[i] = i == c ? 1.0 / R[c * KR_B + c] : (i < c ? s / R[i * KR_B + i] : 0.0);
+        for (int i = j + 1; i < KR_B; ++i) {
+          if (i < b) {
+            const double rji = kr_lane(x[j], i);
+            if (l >= i && l < b) x[i] -= rji * x[j];
+          }
+        }
       }
     }
+  }
+  // column c = l of R^-1 by back substitution; x[k] = 0 for k > c leaves the
+  // sums as they are
+  double y[KR_B];
+#pragma unroll
+  for (int i = 0; i < KR_B; ++i) y[i] = 0.0;
+#pragma unroll
+  for (int i = KR_B - 1; i >= 0; --i) {
+    if (i < b) {
+      double s = 0.0;   // minus the sum
+#pragma unroll
+      for (int k = i + 1; k < KR_B; ++k)
+        if (k < b) s -= kr_lane(x[i], k) * y[k];
+      const double rii = kr_lane(x[i], i);
+      y[i] = i == l ? 1.0 / rii : (i < l ? s / rii : 0.0);
+    }
+  }
+  if (l < b) {
+    const bool dc = (dead >> l) & 1;
 #pragma unroll
     for (int i = 0; i < KR_B; ++i)
-      if (i < b) X[c * KR_B + i] = x[i];
-  }
-  __syncthreads();
-  for (int t = l; t < b * b; t += 64) {
-    const int i = t / b, c = t % b;
-    Rinv[t] = (dead >> c) & 1 ? 0.0 : X[c * KR_B + i];
+      if (i < b) Rinv[i * b + l] = dc ? 0.0 : y[i];
   }
 }
 
