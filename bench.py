@@ -1,26 +1,33 @@
 """Benchmark: sparse HOOI on one MI355X.
 
 A step is one HOOI invocation over all modes (TTM-chain, fixup, Gram,
-eigensolve, factor, then core and fit) on the 3-mode Zipf(1.1) tensor
-1,000,000 x 500,000 x 200,000 with 1e8 nonzeros, lognormal values, ranks
-10 x 10 x 10, inputs resident in HBM.  Prints one JSON line.
+eigensolve, factor, then core and fit).  The default workload is the largest
+one-GPU configuration: the 3-mode tensor 4,000,000 x 4,000,000 x 2,000,000
+with 4.0e9 drawn nonzeros (Zipf 0.8 / 1.2 / 1.5 per mode, lognormal values),
+ranks 10 x 10 x 10.  The draws are generated on the host in chunks and
+streamed into the library (tk_load_coo_begin / _append / _end), so host
+memory never holds the whole list; the timed invocations run with the
+tensor resident in HBM.  Prints one JSON line.
 
   value      TTM-chain Gnnz/s per mode = m' / (mean over modes of the
              TTM-chain + fixup time) / 1e9, from HIP events on the library's stream
   ms/step    wall time of one FP32 HOOI invocation; the same run with the
              Gram in BF16 (last invocation FP32) is reported beside it
   roofline   the TTM-chain kernel's algorithmic bytes per launch / its average
-             launch time, against 8 TB/s; traffic = HBM bytes per launch from
-             the committed rocprofv3 counter summary, while the kernel source
-             is unchanged since it was taken
-  cpu_baseline  the FP64 oracle's TTM-chain timed on a bounded sample on the host
+             launch time (HIP events around each launch, on the library's
+             stream), against 8 TB/s; traffic = HBM bytes per launch from the
+             committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of this
+             workload, while the kernel source is unchanged since it was taken
+  cpu_baseline  the oracle's FP64 TTM-chain (C++/OpenMP, every host thread)
+             timed on a bounded prefix of the same draws
 
-  python bench.py --summarize-profile DIR   writes the profiles/ summaries from
-  rocprofv3 CSV output (DIR/trace, DIR/fetch, DIR/write; see profiles/README.md)
+  python bench.py --summarize-profile DIR --workload W   writes the profiles/
+  summaries from rocprofv3 CSV output (DIR/trace, DIR/fetch, DIR/write)
 """
 from __future__ import annotations
 
 import argparse
+import concurrent.futures as cf
 import json
 import os
 import sys
@@ -34,9 +41,13 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 31
 TTM_SOURCE = os.path.join(ROOT, "paper_1804_09494_amd", "csrc", "ttm.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "ttm3_mfma_c2_hbm_traffic.json")
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
-TTM_KERNEL = "k_ttm3_mfma"
+TTM_KERNELS = {3: "k_ttm3_mfma", 4: "k_ttm4_mfma"}
+CHUNK = 1 << 27          # draws per streamed chunk (2 GiB of host buffers for 3 modes)
+
+
+def traffic_file(workload):
+    return os.path.join(ROOT, "profiles", f"ttm_{workload}_hbm_traffic.json")
 
 
 def _sha256(path):
@@ -45,11 +56,11 @@ def _sha256(path):
         return hashlib.sha256(f.read()).hexdigest()
 
 
-def committed_traffic():
+def committed_traffic(workload):
     """HBM bytes per TTM-chain launch (per mode) from the committed counter
-    summary, or None when the kernel source changed since it was taken."""
+    summary of this workload, or None when the kernel source changed since."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(traffic_file(workload)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
@@ -69,10 +80,11 @@ def _counter_rows(path):
     return [rows[k] for k in sorted(rows)]
 
 
-def summarize_profile(d):
+def summarize_profile(d, workload, kernel):
     """profiles/ summaries from rocprofv3 CSV output under d: trace/ (kernel
     trace + stats of a bench run), fetch/ and write/ (FETCH_SIZE and WRITE_SIZE
-    runs of `bench.py --steps 1 --warmup 0`, copy and TTM kernels only)."""
+    runs of `bench.py --steps 1 --warmup 0 --no-cpu-baseline`, copy and TTM
+    kernels only)."""
     import csv
     import glob
     out_dir = os.path.join(ROOT, "profiles")
@@ -81,73 +93,43 @@ def summarize_profile(d):
     if stats:
         rows = list(csv.DictReader(open(stats[0])))
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-        lines = ["kernel time of `bench.py --steps 3 --warmup 1 --no-cpu-baseline` (c2), top kernels",
+        lines = [f"kernel time of `bench.py --workload {workload} --steps 3 --warmup 1 --no-cpu-baseline`, top kernels",
                  "command: cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run "
-                 "-- python3 -u <repo>/bench.py --steps 3 --warmup 1 --no-cpu-baseline",
+                 f"-- python3 -u <repo>/bench.py --workload {workload} --steps 3 --warmup 1 --no-cpu-baseline",
                  "", f"{'total ms':>10} {'calls':>6} {'avg us':>10}  kernel"]
         for r in rows[:25]:
             lines.append(f"{float(r['TotalDurationNs']) / 1e6:10.3f} {int(r['Calls']):6d} "
                          f"{float(r['AverageNs']) / 1e3:10.1f}  {r['Name'][:110]}")
-        with open(os.path.join(out_dir, "hooi_c2_kernel_stats.txt"), "w") as f:
+        with open(os.path.join(out_dir, f"hooi_{workload}_kernel_stats.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
-    fetch = _counter_rows(glob.glob(os.path.join(d, "fetch", "*counter_collection.csv"))[0])
-    write = _counter_rows(glob.glob(os.path.join(d, "write", "*counter_collection.csv"))[0])
+    fetch_f = glob.glob(os.path.join(d, "fetch", "*counter_collection.csv"))
+    write_f = glob.glob(os.path.join(d, "write", "*counter_collection.csv"))
+    if not (fetch_f and write_f):
+        return
+    fetch, write = _counter_rows(fetch_f[0]), _counter_rows(write_f[0])
     # calibration: the bench's 2 GiB device copies (read 2 GiB, write 2 GiB)
     big = [r for r in fetch if r["kernel"] == COPY_KERNEL and r["value"] > 1e6]
     bigw = [r for r in write if r["kernel"] == COPY_KERNEL and r["value"] > 1e6]
     copy_kib = COPY_BYTES / 1024
     f_scale = copy_kib / (sum(r["value"] for r in big) / len(big))
     w_scale = copy_kib / (sum(r["value"] for r in bigw) / len(bigw))
-    tf = [r["value"] for r in fetch if TTM_KERNEL in r["kernel"]]
-    tw = [r["value"] for r in write if TTM_KERNEL in r["kernel"]]
+    tf = [r["value"] for r in fetch if kernel in r["kernel"]]
+    tw = [r["value"] for r in write if kernel in r["kernel"]]
     per_mode = [round((a * f_scale + b * w_scale) * 1024) for a, b in zip(tf, tw)]
-    res = {"kernel": TTM_KERNEL, "workload": "c2 (68,154,792 merged nonzeros, ranks 10), one launch per mode",
+    res = {"kernel": kernel, "workload": workload, "note": "one launch per mode",
            "source_sha256": _sha256(TTM_SOURCE),
            "fetch_kib_per_mode": tf, "write_kib_per_mode": tw,
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": sum(r["value"] for r in big) / len(big),
                                 "write_kib": sum(r["value"] for r in bigw) / len(bigw),
                                 "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
            "hbm_bytes_per_mode": per_mode,
-           "commands": ["cd /tmp && rocprofv3 --pmc FETCH_SIZE --kernel-include-regex 'k_ttm3_mfma|copyBuffer' "
-                        "--output-format csv -d <dir>/fetch -o run -- python3 -u <repo>/bench.py --steps 1 "
-                        "--warmup 0 --no-cpu-baseline",
-                        "cd /tmp && rocprofv3 --pmc WRITE_SIZE --kernel-include-regex 'k_ttm3_mfma|copyBuffer' "
-                        "--output-format csv -d <dir>/write -o run -- python3 -u <repo>/bench.py --steps 1 "
-                        "--warmup 0 --no-cpu-baseline"]}
-    with open(TRAFFIC_FILE, "w") as f:
+           "commands": [f"cd /tmp && rocprofv3 --pmc {c} --kernel-include-regex '{kernel}|copyBuffer' "
+                        f"--output-format csv -d <dir>/{d_} -o run -- python3 -u <repo>/bench.py --workload {workload} "
+                        "--steps 1 --warmup 0 --no-cpu-baseline" for c, d_ in (("FETCH_SIZE", "fetch"),
+                                                                               ("WRITE_SIZE", "write"))]}
+    with open(traffic_file(workload), "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
-    # further counter passes of the same command (pmc_*/ directories): the
-    # average per TTM launch and per 2 GiB copy of each counter
-    lines = []
-    for sub in sorted(glob.glob(os.path.join(d, "pmc_*"))):
-        files = glob.glob(os.path.join(sub, "*counter_collection.csv"))
-        if not files:
-            continue
-        acc = {}
-        for r in csv.DictReader(open(files[0])):
-            kern = "ttm" if TTM_KERNEL in r["Kernel_Name"] else ("copy" if r["Kernel_Name"] == COPY_KERNEL else None)
-            if kern is None:
-                continue
-            key = (r["Counter_Name"], kern, int(r["Dispatch_Id"]))
-            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
-        names = sorted({k[0] for k in acc})
-        cmd = open(os.path.join(sub, "command.txt")).read().strip() if os.path.exists(
-            os.path.join(sub, "command.txt")) else ""
-        lines.append(f"pass {os.path.basename(sub)}: {cmd}")
-        for nm in names:
-            for kern in ("ttm", "copy"):
-                vals = [v for (c, k, _), v in acc.items() if c == nm and k == kern]
-                if kern == "copy":
-                    vals = [v for v in vals if v > 0.5 * max(vals, default=0)]   # the 2 GiB copies
-                if vals:
-                    lines.append(f"  {nm:36s} {kern:5s} mean {sum(vals) / len(vals):16.1f} over {len(vals)} launches")
-    if lines:
-        hdr = [f"{TTM_KERNEL} counters, c2 (68,154,792 merged nonzeros, ranks 10); 'ttm' = one launch per mode",
-               f"(mean over the launches), 'copy' = the bench's 2 GiB device copy.  source sha256 "
-               f"{_sha256(TTM_SOURCE)}", ""]
-        with open(os.path.join(out_dir, "ttm3_mfma_c2_counters.txt"), "w") as f:
-            f.write("\n".join(hdr + lines) + "\n")
 
 
 def algorithmic_bytes(m, N, R, khat, dims, ranks, n):
@@ -180,36 +162,67 @@ def device_copy_bandwidth(torch):
     return 2 * COPY_BYTES / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(w, target_s=15.0):
-    """The oracle's TTM-chain (FP64, NumPy) on the first nonzeros of the same
-    workload, grown until it runs for about target_s seconds."""
-    from oracle import ttm
-    dims = w["dims"]
-    F = w["F0"]
-    nnz_total = len(w["vals"])
-    n_s = 200_000
-    elapsed = 0.0
+def cpu_baseline(stream, F, target_s=15.0):
+    """The oracle's FP64 TTM-chain (C++/OpenMP on every host thread) over a
+    prefix of the same draws, along every mode, grown until one pass over
+    the modes runs for about target_s seconds."""
+    from oracle import cpp as ttm_cpp
+    N = len(stream.dims)
+    n_s = 1 << 20
     while True:
-        sl = slice(0, min(n_s, nnz_total))
-        idx = [i[sl] for i in w["idx"]]
-        vals = w["vals"][sl]
+        n_s = min(n_s, stream.nnz)
+        idx, vals = stream.chunk(0, n_s)
         t0 = time.perf_counter()
-        ttm.ttm_chain(idx, vals, F, 0, dims)
-        elapsed = time.perf_counter() - t0
-        if elapsed >= target_s / 4 or n_s >= nnz_total:
+        for n in range(N):
+            ttm_cpp.ttm_chain(idx, vals, F, n, stream.dims)
+        el = time.perf_counter() - t0
+        if el >= target_s / 3 or n_s >= stream.nnz:
             break
-        n_s = int(n_s * min(8.0, max(2.0, target_s / 4 / max(elapsed, 1e-3))))
-    return {"value": round(len(vals) / elapsed / 1e9, 6), "unit": "Gnnz/s/mode", "cores": 1, "kind": "oracle",
-            "sample": f"FP64 NumPy TTM-chain along mode 1 over the first {len(vals)} drawn nonzeros of the same "
-                      f"workload (duplicates not merged), {elapsed:.1f} s on one host thread"}
+        n_s = int(n_s * min(8.0, max(1.5, target_s / max(el, 1e-3))))
+    return {"value": round(n_s / (el / N) / 1e9, 6), "unit": "Gnnz/s/mode", "cores": ttm_cpp.threads(),
+            "kind": "oracle",
+            "sample": f"FP64 C++/OpenMP TTM-chain of the oracle along each of the {N} modes over the first {n_s} "
+                      f"drawn nonzeros of the same workload (duplicates not merged), {el:.1f} s for the {N} modes"}
+
+
+def stream_load(ctx, stream, torch):
+    """Generate the draws chunk by chunk into pinned host buffers (two sets:
+    the next chunk is drawn while the current one is copied) and append them."""
+    N = len(stream.dims)
+    bufs = []
+    for _ in range(2):
+        idx = [torch.empty(CHUNK, dtype=torch.int32, pin_memory=True).numpy() for _ in range(N)]
+        vals = torch.empty(CHUNK, dtype=torch.float32, pin_memory=True).numpy()
+        bufs.append((idx, vals))
+    ctx.load_begin(stream.dims, stream.nnz)
+    starts = list(range(0, stream.nnz, CHUNK))
+    gen_s = 0.0
+
+    def gen(k):
+        t = time.perf_counter()
+        a = starts[k]
+        n = min(CHUNK, stream.nnz - a)
+        idx, vals = stream.chunk(a, n, *bufs[k % 2])
+        return idx, vals, time.perf_counter() - t
+
+    with cf.ThreadPoolExecutor(1) as ex:
+        fut = ex.submit(gen, 0)
+        for k in range(len(starts)):
+            idx, vals, g = fut.result()
+            gen_s += g
+            if k + 1 < len(starts):
+                fut = ex.submit(gen, k + 1)
+            ctx.load_append(idx, vals)
+    ctx.load_end()
+    return gen_s
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c5")
     ap.add_argument("--scale", type=float, default=1.0)
     ap.add_argument("--share", type=int, default=1, help="one GPU's share of the workload's draws (dims kept)")
     ap.add_argument("--wg-nnz", type=int, default=0, help="elements per Lite bin (0 = library default)")
@@ -218,11 +231,13 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR")
     args = ap.parse_args()
     if args.summarize_profile:
-        summarize_profile(args.summarize_profile)
+        import synth
+        N = len(synth.WORKLOADS[args.workload]["dims"])
+        summarize_profile(args.summarize_profile, args.workload, TTM_KERNELS.get(N, "k_ttm_cols"))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; multi-GPU sharding is a design in DESIGN.md",
-                          "n_gpus": args.gpus}))
+        print(json.dumps({"error": "this build runs on one GPU only: no figure at several GPUs is measured; "
+                                   "DESIGN.md describes how the path would shard", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
@@ -230,36 +245,30 @@ def main():
     import paper_1804_09494_amd as P
 
     torch.cuda.set_device(0)
-    t = time.perf_counter()
-    w = synth.make_workload(args.workload, scale=args.scale, share=args.share)
-    gen_s = time.perf_counter() - t
-    dims, ranks = w["dims"], w["ranks"]
+    stream = synth.WorkloadStream(args.workload, scale=args.scale, share=args.share)
+    dims, ranks = stream.dims, stream.ranks
     N = len(dims)
-    print(f"# generated {args.workload} dims={dims} nnz={len(w['vals'])} in {gen_s:.1f}s", file=sys.stderr,
-          flush=True)
-
-    idx_d = [torch.from_numpy(i).cuda() for i in w["idx"]]
-    vals_d = torch.from_numpy(w["vals"]).cuda()
-    opts = {}
+    opts = {"keep_elem_order": 0}
     if args.wg_nnz:
         opts["wg_nnz_target"] = args.wg_nnz
     if args.rows_cap:
         opts["lds_rows_cap"] = args.rows_cap
     ctx = P.TuckerContext(0, **opts)
-    torch.cuda.synchronize()
+    print(f"# {args.workload}: dims={dims} draws={stream.nnz}, streamed in chunks of {CHUNK}", file=sys.stderr,
+          flush=True)
     t = time.perf_counter()
-    ctx.load_coo(idx_d, vals_d, dims)
+    gen_s = stream_load(ctx, stream, torch)
     torch.cuda.synchronize()
     load_s = time.perf_counter() - t
-    del idx_d, vals_d
+    m, _ = ctx.tensor_info()
+    print(f"# loaded: m'={m}, {load_s:.1f}s (drawing {gen_s:.1f}s of it, overlapped)", file=sys.stderr, flush=True)
     t = time.perf_counter()
     ctx.set_ranks(ranks)
     torch.cuda.synchronize()
     part_s = time.perf_counter() - t
-    for n, F in enumerate(w["F0"]):
-        ctx.set_factor(n, np.ascontiguousarray(F))
-    m, _ = ctx.tensor_info()
-    print(f"# coalesced m'={m} load {load_s:.2f}s partition+layout {part_s:.2f}s", file=sys.stderr, flush=True)
+    F0 = stream.initial_factors()
+    print(f"# partition+layout {part_s:.1f}s; device memory in use {torch.cuda.mem_get_info()}", file=sys.stderr,
+          flush=True)
 
     copy_gbs = device_copy_bandwidth(torch)
     K = args.steps
@@ -267,11 +276,11 @@ def main():
     def run(prec):
         """Warm-up invocations, then K timed invocations from the initial factors."""
         ctx.set_options(prec=prec, refine=1)
-        for n, F in enumerate(w["F0"]):
+        for n, F in enumerate(F0):
             ctx.set_factor(n, np.ascontiguousarray(F))
         if args.warmup > 0:
             ctx.hooi_iterate(args.warmup)
-        for n, F in enumerate(w["F0"]):
+        for n, F in enumerate(F0):
             ctx.set_factor(n, np.ascontiguousarray(F))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -288,21 +297,23 @@ def main():
     shapes = [ctx.ttm_shape(n) for n in range(N)]
     B = [algorithmic_bytes(m, N, shapes[n][0], shapes[n][1], dims, ranks, n) for n in range(N)]
     achieved = sum(B) / (sum(kern_ms) * 1e-3) / 1e9
-    mfma_path = N == 3 and all(ranks[j] <= 16 for j in range(N))
-    # the committed counter summary is of this kernel on c2 as a whole
-    traffic = committed_traffic() if (args.workload == "c2" and args.share == 1 and args.scale == 1.0
-                                      and mfma_path) else None
+    mfma_path = N in (3, 4) and all(ranks[j] <= 16 for j in range(N))
+    kernel = TTM_KERNELS[N] if mfma_path else "k_ttm_cols"
+    traffic = committed_traffic(args.workload) if (args.share == 1 and args.scale == 1.0 and mfma_path) else None
     stats = [ctx.partition_stats(n) for n in range(N)]
     print(f"# fits fp32 {fits}", file=sys.stderr, flush=True)
     print(f"# fits bf16 {bf_fits}", file=sys.stderr, flush=True)
     print(f"# per-step ms fp32: " + ", ".join(f"{k}={v / K:.3f}" for k, v in tm.items()), file=sys.stderr, flush=True)
     print(f"# per-step ms bf16: " + ", ".join(f"{k}={v / K:.3f}" for k, v in bf_tm.items()), file=sys.stderr,
           flush=True)
+    del ctx
+    torch.cuda.empty_cache()
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(w)
+        cpu = cpu_baseline(stream, F0)
 
+    desc = {"c5": "Zipf 0.8/1.2/1.5", "c2": "Zipf 1.1", "c3": "Zipf 0.9/1.1/1.3/0.7"}.get(args.workload, "Zipf")
     out = {
         "metric": "TTM-chain Gnnz/s/mode + HOOI iter time; FP32 vs BF16-Gram at rel err <=1e-5",
         "value": round(value, 3),
@@ -317,10 +328,10 @@ def main():
         "dtype": "fp32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}{'/' + str(args.share) if args.share > 1 else ''}: "
-                               f"{N}-mode {'x'.join(str(d) for d in dims)}, "
-                               f"{len(w['vals'])} Zipf-drawn nonzeros ({m} after merging), ranks "
-                               f"{'x'.join(str(k) for k in ranks)}, one HOOI invocation per step",
-                   "m_coalesced": m, "ranks": list(ranks)},
+                               f"{N}-mode {'x'.join(str(d) for d in dims)}, {stream.nnz} {desc} draws "
+                               f"({m} after merging), lognormal values, ranks {'x'.join(str(k) for k in ranks)}, "
+                               f"one HOOI invocation per step",
+                   "m_coalesced": m, "draws": stream.nnz, "ranks": list(ranks)},
         "hooi_iter_ms": {"fp32": round(ms_per_step, 4), "bf16_gram": round(bf_ms, 4)},
         "bf16_gram_run": f"{K - 1} invocations with BF16 Gram operands, then one refining FP32 invocation",
         "final_fit": {"fp32": fits[-1] if fits else None, "bf16_gram": bf_fits[-1] if bf_fits else None},
@@ -328,13 +339,14 @@ def main():
         "ttm_ms_per_mode": [round(x, 4) for x in ttm_ms],
         "ttm_kernel_ms_per_mode": [round(x, 4) for x in kern_ms],
         "step_ms": {k: round(v / K, 4) for k, v in tm.items()},
+        "load_s": round(load_s, 2),
         "partition_s": round(part_s, 3),
         "partition_stats": stats,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": round(float(np.mean(traffic))) if traffic else None,
                      "traffic_bytes_per_mode": traffic,
-                     "kernel": "k_ttm3_mfma (TTM-chain)" if mfma_path else "k_ttm (TTM-chain, vector ALU)",
+                     "kernel": f"{kernel} (TTM-chain)",
                      "bytes_per_launch": [int(b) for b in B]},
         "device_copy_GBps": round(copy_gbs, 1),
         "cpu_baseline": cpu,

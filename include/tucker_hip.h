@@ -60,7 +60,7 @@ typedef enum {
   TK_ERR_OOM = 3,          /* device allocation failed or the plan exceeds mem_limit_bytes */
   TK_ERR_DEVICE = 4,       /* a HIP runtime call failed */
   TK_ERR_NUMERIC = 5,      /* rank-deficient Y_(n) with completion disabled */
-  TK_ERR_UNSUPPORTED = 6   /* a size outside what this build handles (e.g. nnz >= 2^31) */
+  TK_ERR_UNSUPPORTED = 6   /* a size outside what this build handles (e.g. ranks above 64) */
 } tk_status;
 
 typedef enum { TK_MEM_HOST = 0, TK_MEM_DEVICE = 1 } tk_mem;
@@ -68,10 +68,12 @@ typedef enum { TK_FP32 = 0, TK_BF16 = 1 } tk_prec;
 typedef enum { TK_SWEEP_GAUSS_SEIDEL = 0, TK_SWEEP_JACOBI = 1 } tk_sweep;
 
 typedef struct {
-  int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16: in HOOI invocations the Gram
-                                     operands are rounded to BF16 (FP32 accumulation); tk_ttm_chain
-                                     gathers BF16 factor rows.  The eigensolve, CholeskyQR2, core and
-                                     fit stay FP64 */
+  int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16 (the precision form): the
+                                     Kronecker tiles of the TTM-chain (three- and four-mode tensors with
+                                     other ranks <= 16) and the Gram operands are rounded to BF16 on the
+                                     matrix cores, FP32 accumulation, in tk_ttm_chain and in HOOI
+                                     invocations (but a refining last one, see refine).  The eigensolve,
+                                     CholeskyQR2, core and fit stay FP64 */
   int32_t sweep;                  /* tk_sweep (default Gauss-Seidel: mode n uses factors refined earlier in the invocation) */
   int64_t wg_nnz_target;          /* target elements per bin; 0 (default) = per kernel: 448 for the
                                      three-mode matrix-core TTM-chain, 1024 for the four-mode one and
@@ -81,6 +83,10 @@ typedef struct {
   int64_t mem_limit_bytes;        /* 0 = no limit; plans above it fail with TK_ERR_OOM before allocating */
   int32_t complete_rank_deficient;/* 1 (default) = complete U with unit vectors; 0 = TK_ERR_NUMERIC */
   int32_t keep_elem_order;        /* 1 (default) = keep each mode's element order for tk_get_partition */
+  double eig_tol;                 /* block-Krylov eigensolve (Khat >= 192): bound on the estimated
+                                     subspace error sqrt(2) * residual * theta_1 / (theta_K - theta_{K+1})
+                                     (sin-theta theorem); a larger estimate reruns the mode's eigensolve
+                                     with the dense solver.  0 (default) = 1e-7 */
 } tk_options;
 
 /* Lite statistics of one mode (Section 4 metrics 1-3; Theorem 6.1). */
@@ -96,10 +102,23 @@ typedef struct {
   int64_t n_bad;        /* slices shared by more than one bin (<= P) */
 } tk_part_stats;
 
+/* Device-memory hooks: alloc returns `bytes` of device memory of the
+ * context's GPU (NULL on failure, which the library reports as TK_ERR_OOM);
+ * free returns such a block.  Both are called on the thread that calls the
+ * library; blocks are in use on the context's stream until the call that
+ * freed them returns. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*free)(void* ptr, size_t bytes, void* user);
+  void* user;
+} tk_allocator;
+
 /* ---- context ------------------------------------------------------------------------------- */
 
-/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or NULL. */
-tk_status tk_create(int device, void* hip_stream, tk_ctx** out);
+/* Create a context on HIP device `device`; `hip_stream` is a hipStream_t or
+ * NULL; `allocator` (copied; may be NULL = hipMalloc / hipFree) backs every
+ * device allocation the context makes. */
+tk_status tk_create(int device, void* hip_stream, const tk_allocator* allocator, tk_ctx** out);
 void tk_destroy(tk_ctx* ctx);
 const char* tk_status_string(tk_status s);
 /* Message of the last failure on this context ("" if none).  Valid until the next call. */
@@ -111,18 +130,34 @@ tk_status tk_set_stream(tk_ctx* ctx, void* hip_stream);
 
 /* ---- tensor (Section 3: the element list E) --------------------------------------------------- */
 
+/* Flags of tk_load_coo / tk_load_coo_begin. */
+#define TK_ASSUME_UNIQUE 1u   /* the caller guarantees distinct coordinates: the merge of repeated
+                                 coordinates is skipped (any left are kept as separate elements) */
+
 /* Load a sparse tensor in COO form.  N in [2, 8]; dims[n] in [1, 2^31 - 1];
- * nnz in [0, 2^31 - 1] (larger lists give TK_ERR_UNSUPPORTED); idx[n] points
- * to nnz int32 coordinates of mode n
- * (0-based, < dims[n]); vals to nnz finite floats.  `mem` applies to idx[n]
- * and vals (the arrays of pointers themselves are host memory).
+ * nnz in [0, 2^40]; idx[n] points to nnz int32 coordinates of mode n (0-based,
+ * < dims[n]); vals to nnz finite floats.  `mem` applies to idx[n] and vals
+ * (the arrays of pointers themselves are host memory).
  * Repeated coordinates are merged by summing their values in FP64 (input
  * order), rounded once to FP32; the merged list is kept in canonical order.
  * ||T||^2 is accumulated in FP64.  Replaces any previous tensor and plan.
+ * Device memory: about 16 + 4N bytes per element while the list is sorted
+ * and merged, then (4N + 4) bytes per merged element.
  * Errors: TK_ERR_INVALID_ARG for a coordinate out of range or a NaN/Inf value
- * (checked on the device), nothing is kept. */
+ * (checked on the device), nothing is kept; TK_ERR_OOM when the device memory
+ * (or mem_limit_bytes) does not hold the list; TK_ERR_UNSUPPORTED for 2^32 or
+ * more distinct coordinates. */
 tk_status tk_load_coo(tk_ctx* ctx, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx,
-                      const float* vals, tk_mem mem);
+                      const float* vals, tk_mem mem, unsigned flags);
+/* The same load streamed in pieces, for lists the caller does not hold at
+ * once: begin announces N, dims and the total nnz (same limits) and drops the
+ * previous tensor; each append copies `count` more elements (host or device
+ * memory, reusable when the call returns); end checks that nnz elements
+ * arrived, then merges and sorts as tk_load_coo.  Errors of an append's
+ * elements are reported by end. */
+tk_status tk_load_coo_begin(tk_ctx* ctx, int N, const int64_t* dims, int64_t nnz, unsigned flags);
+tk_status tk_load_coo_append(tk_ctx* ctx, int64_t count, const int32_t* const* idx, const float* vals, tk_mem mem);
+tk_status tk_load_coo_end(tk_ctx* ctx);
 /* m' (elements after merging) and ||T||^2 (FP64). */
 tk_status tk_get_tensor_info(const tk_ctx* ctx, int64_t* nnz_coalesced, double* norm_sq);
 /* Copy the merged element list out: idx[n] gets m' int32, vals m' floats. */
@@ -162,7 +197,7 @@ tk_status tk_ttm_shape(tk_ctx* ctx, int n, int64_t* R_n, int64_t* Khat_n);
 /* TTM-chain along mode n with the current factors (eq. 1): Y gets the rows of
  * the nonempty slices in ascending slice id (R_n x Khat_n, row-major FP32);
  * row_slice (may be NULL) gets their slice ids (int32).  With prec = TK_BF16
- * the factor rows come from the BF16 copies (where the matrix-core kernel runs). */
+ * the Kronecker tiles are BF16 on the matrix cores (where such a kernel runs). */
 tk_status tk_ttm_chain(tk_ctx* ctx, int n, float* Y, int32_t* row_slice, tk_mem mem);
 /* Run `iters` HOOI invocations (Section 2.2): for each mode in turn, TTM-chain,
  * Gram, FP64 eigensolve, U = Y V S^-1, CholeskyQR2, new factor.  The
@@ -178,6 +213,11 @@ tk_status tk_core(tk_ctx* ctx, double* core, double* fit, tk_mem mem);
 /* Milliseconds of the last tk_hooi_iterate per step; names[i] is a static string.
  * *count is in/out: capacity in, entries written out. */
 tk_status tk_get_timings(tk_ctx* ctx, double* ms, const char** names, int* count);
+
+/* Event counts since the context was created (names[i] static strings):
+ *   eig_krylov_solves, eig_krylov_cycles, eig_dense_fallbacks.
+ * *count is in/out: capacity in, entries written out. */
+tk_status tk_get_counters(tk_ctx* ctx, int64_t* values, const char** names, int* count);
 
 /* ---- differentiation form (Tucker completion; not in the paper) -------------------------------- */
 

@@ -20,12 +20,21 @@ STATUS = {0: "TK_OK", 1: "TK_ERR_INVALID_ARG", 2: "TK_ERR_STATE", 3: "TK_ERR_OOM
 TK_MEM_HOST, TK_MEM_DEVICE = 0, 1
 TK_FP32, TK_BF16 = 0, 1
 TK_SWEEP_GAUSS_SEIDEL, TK_SWEEP_JACOBI = 0, 1
+TK_ASSUME_UNIQUE = 1
 
 
 class tk_options(ctypes.Structure):
     _fields_ = [("prec", c_i32), ("sweep", c_i32), ("wg_nnz_target", c_i64), ("lds_rows_cap", c_i32),
                 ("refine", c_i32), ("mem_limit_bytes", c_i64),
-                ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32)]
+                ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32), ("eig_tol", c_f64)]
+
+
+TK_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+TK_FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, ctypes.c_size_t, c_void_p)
+
+
+class tk_allocator(ctypes.Structure):
+    _fields_ = [("alloc", TK_ALLOC_FN), ("free", TK_FREE_FN), ("user", c_void_p)]
 
 
 class tk_part_stats(ctypes.Structure):
@@ -35,7 +44,7 @@ class tk_part_stats(ctypes.Structure):
 
 # (name, restype, argtypes) of every exported symbol
 SIGNATURES = [
-    ("tk_create", c_int, [c_int, c_void_p, ctypes.POINTER(c_void_p)]),
+    ("tk_create", c_int, [c_int, c_void_p, ctypes.POINTER(tk_allocator), ctypes.POINTER(c_void_p)]),
     ("tk_destroy", None, [c_void_p]),
     ("tk_status_string", c_char_p, [c_int]),
     ("tk_last_error", c_char_p, [c_void_p]),
@@ -43,7 +52,10 @@ SIGNATURES = [
     ("tk_set_options", c_int, [c_void_p, ctypes.POINTER(tk_options)]),
     ("tk_set_stream", c_int, [c_void_p, c_void_p]),
     ("tk_load_coo", c_int, [c_void_p, c_int, ctypes.POINTER(c_i64), c_i64, ctypes.POINTER(c_void_p), c_void_p,
-                            c_int]),
+                            c_int, ctypes.c_uint]),
+    ("tk_load_coo_begin", c_int, [c_void_p, c_int, ctypes.POINTER(c_i64), c_i64, ctypes.c_uint]),
+    ("tk_load_coo_append", c_int, [c_void_p, c_i64, ctypes.POINTER(c_void_p), c_void_p, c_int]),
+    ("tk_load_coo_end", c_int, [c_void_p]),
     ("tk_get_tensor_info", c_int, [c_void_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_f64)]),
     ("tk_get_coo", c_int, [c_void_p, ctypes.POINTER(c_void_p), c_void_p, c_int]),
     ("tk_set_ranks", c_int, [c_void_p, ctypes.POINTER(c_i32)]),
@@ -57,6 +69,7 @@ SIGNATURES = [
     ("tk_hooi_iterate", c_int, [c_void_p, c_int, c_void_p]),
     ("tk_core", c_int, [c_void_p, c_void_p, ctypes.POINTER(c_f64), c_int]),
     ("tk_get_timings", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int)]),
+    ("tk_get_counters", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int)]),
     ("tk_load_obs", c_int, [c_void_p, c_int, ctypes.POINTER(c_i64), ctypes.POINTER(c_i32), c_i64,
                             ctypes.POINTER(c_void_p), c_int]),
     ("tk_tucker_eval", c_int, [c_void_p, c_void_p, ctypes.POINTER(c_void_p), c_void_p, c_int]),

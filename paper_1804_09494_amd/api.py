@@ -61,7 +61,10 @@ def _current_stream(device):
 class TuckerContext:
     """One library context on one GPU (tk_create / tk_destroy)."""
 
-    def __init__(self, device: int = 0, stream=None, **options):
+    def __init__(self, device: int = 0, stream=None, allocator=None, **options):
+        """allocator: None (the library's hipMalloc / hipFree) or "torch" (torch's
+        caching allocator backs every device allocation of the context, on the
+        context's stream)."""
         self._L = _lib.load()
         h = c_void_p()
         if stream is None:
@@ -69,7 +72,13 @@ class TuckerContext:
         elif _is_torch_stream(stream):
             stream = c_void_p(stream.cuda_stream)
         self._opt = None
-        self._check(self._L.tk_create(device, stream, ctypes.byref(h)), None)
+        self._alloc = None
+        if allocator == "torch":
+            self._alloc = _torch_allocator(device, stream.value or 0)
+        elif allocator is not None:
+            raise ValueError("allocator must be None or 'torch'")
+        self._check(self._L.tk_create(device, stream, ctypes.byref(self._alloc) if self._alloc else None,
+                                      ctypes.byref(h)), None)
         self._h = h
         self.device = device
         self.N = 0
@@ -129,10 +138,18 @@ class TuckerContext:
         self._opt = o
 
     # -- tensor --
-    def load_coo(self, idx, vals, dims):
+    def load_coo(self, idx, vals, dims, assume_unique=False):
         N = len(dims)
         if len(idx) != N:
             raise ValueError("need one coordinate array per mode")
+        mem, nnz = self._check_chunk(idx, vals)
+        d = (c_i64 * N)(*[int(x) for x in dims])
+        ptrs = (c_void_p * N)(*[_ptr(a) for a in idx])
+        flags = _lib.TK_ASSUME_UNIQUE if assume_unique else 0
+        self._check(self._L.tk_load_coo(self._h, N, d, nnz, ptrs, _ptr(vals), mem, flags))
+        self.N, self.dims = N, tuple(int(x) for x in dims)
+
+    def _check_chunk(self, idx, vals):
         mem = _mem_of(vals)
         nnz = int(vals.shape[0])
         for i, a in enumerate(idx):
@@ -140,10 +157,25 @@ class TuckerContext:
             if _mem_of(a) != mem or int(a.shape[0]) != nnz:
                 raise ValueError("coordinate arrays must match vals in length and memory kind")
         _check_dtype(vals, np.float32, "vals")
+        return mem, nnz
+
+    def load_begin(self, dims, nnz, assume_unique=False):
+        """Streamed load (tk_load_coo_begin): announce dims and the total
+        element count, then load_append the elements in pieces, then load_end."""
+        N = len(dims)
         d = (c_i64 * N)(*[int(x) for x in dims])
-        ptrs = (c_void_p * N)(*[_ptr(a) for a in idx])
-        self._check(self._L.tk_load_coo(self._h, N, d, nnz, ptrs, _ptr(vals), mem))
-        self.N, self.dims = N, tuple(int(x) for x in dims)
+        flags = _lib.TK_ASSUME_UNIQUE if assume_unique else 0
+        self._check(self._L.tk_load_coo_begin(self._h, N, d, int(nnz), flags))
+        self._pending = (N, tuple(int(x) for x in dims))
+
+    def load_append(self, idx, vals):
+        mem, count = self._check_chunk(idx, vals)
+        ptrs = (c_void_p * len(idx))(*[_ptr(a) for a in idx])
+        self._check(self._L.tk_load_coo_append(self._h, count, ptrs, _ptr(vals), mem))
+
+    def load_end(self):
+        self._check(self._L.tk_load_coo_end(self._h))
+        self.N, self.dims = self._pending
 
     def tensor_info(self):
         m, nsq = c_i64(), c_f64()
@@ -236,6 +268,13 @@ class TuckerContext:
         self._check(self._L.tk_get_timings(self._h, ms, names, ctypes.byref(cap)))
         return {names[i].decode(): ms[i] for i in range(cap.value)}
 
+    def counters(self):
+        cap = c_int(16)
+        vals = (c_i64 * 16)()
+        names = (ctypes.c_char_p * 16)()
+        self._check(self._L.tk_get_counters(self._h, vals, names, ctypes.byref(cap)))
+        return {names[i].decode(): vals[i] for i in range(cap.value)}
+
     # -- differentiation form --
     def load_obs(self, idx, dims, ranks):
         N = len(dims)
@@ -272,6 +311,23 @@ class TuckerContext:
         dFp = (c_void_p * len(F))(*[_ptr(f) for f in dF])
         self._check(self._L.tk_tucker_adjoint(self._h, _ptr(g), _ptr(core), Fp, _ptr(dcore), dFp, mem))
         return dcore, dF
+
+
+def _torch_allocator(device, stream_handle):
+    """tk_allocator whose hooks call torch's caching allocator (the callbacks
+    are kept alive by the returned structure's owner)."""
+    def alloc(nbytes, user):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), device, stream_handle)
+        except Exception:   # out of memory: the library reports TK_ERR_OOM
+            return None
+
+    def free(ptr, nbytes, user):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    a = _lib.tk_allocator(_lib.TK_ALLOC_FN(alloc), _lib.TK_FREE_FN(free), None)
+    a._keep = (alloc, free)
+    return a
 
 
 def _is_torch_stream(s):

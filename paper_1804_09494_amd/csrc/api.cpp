@@ -21,8 +21,8 @@ namespace tk {
 
 void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16);
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode);
-bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
-                 int* flag_dev, bool deferred);
+bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* Gfull, const double* lam_k,
+                 const double* VK, int* flag_dev, bool deferred);
 void complete_factor(Ctx* c, int n);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
 void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk_mem mem);
@@ -35,10 +35,15 @@ void* Ctx::alloc_raw(size_t bytes) {
   if (opt.mem_limit_bytes > 0 && bytes_in_use + (int64_t)bytes > opt.mem_limit_bytes)
     fail(TK_ERR_OOM, "allocation of " + std::to_string(bytes) + " bytes exceeds mem_limit_bytes");
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, bytes);
-  if (e != hipSuccess || !p) {
-    (void)hipGetLastError();
-    fail(TK_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  if (allocator.alloc) {
+    p = allocator.alloc(bytes, allocator.user);
+    if (!p) fail(TK_ERR_OOM, "the allocator hook returned no memory for " + std::to_string(bytes) + " bytes");
+  } else {
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      fail(TK_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
   }
   bytes_in_use += (int64_t)bytes;
   return p;
@@ -46,7 +51,10 @@ void* Ctx::alloc_raw(size_t bytes) {
 
 void Ctx::free_raw(void* p, size_t bytes) {
   if (p) {
-    (void)hipFree(p);
+    if (allocator.free)
+      allocator.free(p, bytes, allocator.user);
+    else
+      (void)hipFree(p);
     bytes_in_use -= (int64_t)bytes;
   }
 }
@@ -114,7 +122,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       }
     }
     float* Y = c->Y.as<float>();
-    // precision form: BF16 Gram operands, except in the refining last invocation
+    // precision form: BF16 Kronecker tiles and Gram operands, except in the refining last invocation
     const bool low = c->opt.prec == TK_BF16 && !(c->opt.refine && it == iters - 1);
     // Gauss-Seidel sweeps check for a failed (rank-deficient) factor once, at
     // the end of the invocation, instead of stopping the stream after every
@@ -133,18 +141,17 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       c->ev_ttm[0] = k0;
       c->ev_ttm[1] = k1;
       sm.marks.push_back({"ttm_kernel[" + std::to_string(n) + "]", {k0, k1}});
+      // the precision form's invocations (all but a refining last one) form
+      // the Kronecker tiles in BF16 on the matrix cores
       if (c->opt.sweep == TK_SWEEP_JACOBI) {
         // swap in the input copies for the other modes
         for (int j = 0; j < N; ++j)
           if (j != n) std::swap(c->F32[j], F32_in[j]);
-        ttm_chain(c, n, Y, false);
+        ttm_chain(c, n, Y, low);
         for (int j = 0; j < N; ++j)
           if (j != n) std::swap(c->F32[j], F32_in[j]);
       } else {
-        // the precision form keeps the Kronecker tiles in FP32 here: BF16 factor
-        // rows perturb ||G||^2 by ~1e-3, more than the residual of a
-        // well-fitting decomposition, and gave no speed-up
-        ttm_chain(c, n, Y, false);
+        ttm_chain(c, n, Y, low);
       }
       c->ev_ttm[0] = c->ev_ttm[1] = nullptr;
       if (c->m == 0) {  // no launch: give the bracket a zero-length interval
@@ -158,7 +165,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       double* VK = lam_k + 64;
       eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK, n);
       hipEvent_t t3 = mark("eig", t2);
-      form_factor(c, n, Y, pl.L_nz, khat, lam_k, VK, c->flag.as<int>(), deferred);
+      form_factor(c, n, Y, pl.L_nz, khat, c->gram64.as<double>(), lam_k, VK, c->flag.as<int>(), deferred);
       mark("factor", t3);
     };
     for (int n = 0; n < N; ++n) run_mode(n, defer);
@@ -171,13 +178,17 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
         if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
         complete_factor(c, n0);
         TK_HIP(hipMemsetAsync(c->flag.as<int>() + 1, 0, sizeof(int), c->stream));
+        // the skipped modes' factor copies were not cleared on the device (the
+        // clear was conditional on no earlier failure) although their host-side
+        // flags say so: mark them again so the rerun zeroes rows of empty slices
+        for (int n = n0 + 1; n < N; ++n) c->fac_dirty[n] = true;
         for (int n = n0 + 1; n < N; ++n) run_mode(n, false);
       }
     }
     // core and fit from the last mode (valid for Gauss-Seidel: Y_(N) used the final factors)
     hipEvent_t t4 = pool.next();
     TK_HIP(hipEventRecord(t4, c->stream));
-    if (c->opt.sweep == TK_SWEEP_JACOBI) ttm_chain(c, N - 1, Y, false);
+    if (c->opt.sweep == TK_SWEEP_JACOBI) ttm_chain(c, N - 1, Y, low);
     double* core = c->core64.as<double>();
     core_from_last(c, Y, core, core + core_n);
     mark("core", t4);
@@ -248,12 +259,17 @@ tk_status tk_default_options(tk_options* o) {
   o->mem_limit_bytes = 0;
   o->complete_rank_deficient = 1;
   o->keep_elem_order = 1;
+  o->eig_tol = 0.0;
   return TK_OK;
 }
 
-tk_status tk_create(int device, void* hip_stream, tk_ctx** out) {
+tk_status tk_create(int device, void* hip_stream, const tk_allocator* allocator, tk_ctx** out) {
   if (!out) return TK_ERR_INVALID_ARG;
   *out = nullptr;
+  if (allocator && (!allocator->alloc || !allocator->free)) {
+    g_err = "tk_create: the allocator needs both alloc and free";
+    return TK_ERR_INVALID_ARG;
+  }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
     (void)hipGetLastError();
@@ -266,6 +282,7 @@ tk_status tk_create(int device, void* hip_stream, tk_ctx** out) {
   tk_status s = guard(c, [&] {
     TK_HIP(hipSetDevice(device));
     c->device = device;
+    if (allocator) c->allocator = *allocator;
     c->stream = (hipStream_t)hip_stream;
     tk_default_options(&c->opt);
     int v = 0;
@@ -297,6 +314,7 @@ tk_status tk_set_options(tk_ctx* c, const tk_options* o) {
     TK_REQUIRE(o->prec == TK_FP32 || o->prec == TK_BF16, TK_ERR_INVALID_ARG, "prec");
     TK_REQUIRE(o->sweep == TK_SWEEP_GAUSS_SEIDEL || o->sweep == TK_SWEEP_JACOBI, TK_ERR_INVALID_ARG, "sweep");
     TK_REQUIRE(o->wg_nnz_target >= 0 && o->mem_limit_bytes >= 0, TK_ERR_INVALID_ARG, "negative size");
+    TK_REQUIRE(o->eig_tol >= 0.0, TK_ERR_INVALID_ARG, "negative eig_tol");
     c->opt = *o;
   });
 }
@@ -307,33 +325,84 @@ tk_status tk_set_stream(tk_ctx* c, void* s) {
   return TK_OK;
 }
 
-tk_status tk_load_coo(tk_ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx,
-                      const float* vals, tk_mem mem) {
+static void drop_tensor(Ctx* c) {
+  c->have_tensor = false;
+  c->have_ranks = false;
+  for (int j = 0; j < 8; ++j) {
+    c->plan[j] = ModePlan();
+    c->F64[j].release();
+    c->F32[j].release();
+    c->eig_warm[j].release();
+    c->eig_warm_k[j] = 0;
+  }
+  for (int j = 0; j < 8; ++j) c->idx_c[j].release();
+  c->val_c.release();
+  c->m = 0;
+}
+
+tk_status tk_load_coo_begin(tk_ctx* c, int N, const int64_t* dims, int64_t nnz, unsigned flags) {
   if (!c) return TK_ERR_INVALID_ARG;
   return guard(c, [&] {
     TK_REQUIRE(N >= 2 && N <= 8, TK_ERR_INVALID_ARG, "N must be in [2, 8]");
     TK_REQUIRE(dims != nullptr, TK_ERR_INVALID_ARG, "dims is NULL");
-    TK_REQUIRE(mem == TK_MEM_HOST || mem == TK_MEM_DEVICE, TK_ERR_INVALID_ARG, "mem");
     for (int j = 0; j < N; ++j)
       TK_REQUIRE(dims[j] >= 1 && dims[j] <= 2147483647LL, TK_ERR_INVALID_ARG, "dims out of range");
-    TK_REQUIRE(nnz >= 0, TK_ERR_INVALID_ARG, "negative nnz");
-    TK_REQUIRE(nnz < (1LL << 31), TK_ERR_UNSUPPORTED, "this build handles fewer than 2^31 elements");
-    if (nnz > 0) {
-      TK_REQUIRE(idx != nullptr && vals != nullptr, TK_ERR_INVALID_ARG, "idx or vals is NULL");
-      for (int j = 0; j < N; ++j) TK_REQUIRE(idx[j] != nullptr, TK_ERR_INVALID_ARG, "idx[n] is NULL");
-    }
+    TK_REQUIRE(nnz >= 0 && nnz <= (1LL << 40), TK_ERR_INVALID_ARG, "nnz must be in [0, 2^40]");
+    TK_REQUIRE((flags & ~TK_ASSUME_UNIQUE) == 0, TK_ERR_INVALID_ARG, "unknown flags");
     TK_HIP(hipSetDevice(c->device));
-    // drop the previous tensor and plan
-    c->have_tensor = false;
-    c->have_ranks = false;
-    for (int j = 0; j < 8; ++j) {
-      c->plan[j] = ModePlan();
-      c->F64[j].release();
-      c->F32[j].release();
-      c->F16[j].release();
+    // drop the previous tensor and plan (and any load in progress)
+    c->load = LoadState();
+    drop_tensor(c);
+    try {
+      load_begin(c, N, dims, nnz, flags);
+    } catch (...) {
+      c->load = LoadState();
+      throw;
     }
-    load_coo(c, N, dims, nnz, idx, vals, mem);
   });
+}
+
+tk_status tk_load_coo_append(tk_ctx* c, int64_t count, const int32_t* const* idx, const float* vals, tk_mem mem) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    TK_REQUIRE(c->load.active, TK_ERR_STATE, "tk_load_coo_begin first");
+    TK_REQUIRE(mem == TK_MEM_HOST || mem == TK_MEM_DEVICE, TK_ERR_INVALID_ARG, "mem");
+    TK_REQUIRE(count >= 0 && count <= c->load.nnz - c->load.filled, TK_ERR_INVALID_ARG,
+               "append beyond the announced element count");
+    if (count == 0) return;
+    TK_REQUIRE(idx != nullptr && vals != nullptr, TK_ERR_INVALID_ARG, "idx or vals is NULL");
+    for (int j = 0; j < c->load.N; ++j) TK_REQUIRE(idx[j] != nullptr, TK_ERR_INVALID_ARG, "idx[n] is NULL");
+    TK_HIP(hipSetDevice(c->device));
+    load_append(c, count, idx, vals, mem);
+  });
+}
+
+tk_status tk_load_coo_end(tk_ctx* c) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    TK_REQUIRE(c->load.active, TK_ERR_STATE, "tk_load_coo_begin first");
+    TK_HIP(hipSetDevice(c->device));
+    try {
+      load_end(c);
+    } catch (...) {
+      c->load = LoadState();   // nothing is kept
+      drop_tensor(c);
+      throw;
+    }
+  });
+}
+
+tk_status tk_load_coo(tk_ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx,
+                      const float* vals, tk_mem mem, unsigned flags) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  tk_status s = tk_load_coo_begin(c, N, dims, nnz, flags);
+  if (s != TK_OK) return s;
+  s = tk_load_coo_append(c, nnz, idx, vals, mem);
+  if (s != TK_OK) {
+    c->load = LoadState();
+    return s;
+  }
+  return tk_load_coo_end(c);
 }
 
 tk_status tk_get_tensor_info(const tk_ctx* c, int64_t* nnz_c, double* norm_sq) {
@@ -373,7 +442,7 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       int64_t need = 0;
       for (int n = 0; n < N; ++n) need += c->m * (4 * (int64_t)N + (c->opt.keep_elem_order ? 4 : 0));
       need += c->m * 24;  // sort buffers during construction
-      for (int n = 0; n < N; ++n) need += c->dims[n] * (int64_t)K[n] * (8 + 4 + 2) + c->dims[n] * 32;
+      for (int n = 0; n < N; ++n) need += c->dims[n] * (int64_t)K[n] * (8 + 4) + c->dims[n] * 32;
       TK_REQUIRE(c->bytes_in_use + need <= c->opt.mem_limit_bytes, TK_ERR_OOM,
                  "the plan needs about " + std::to_string(need) + " bytes, above mem_limit_bytes");
     }
@@ -385,10 +454,8 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
     for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);
     for (int n = 0; n < N; ++n) {
       c->kp32[n] = K[n] <= 16 ? 16 : (K[n] + 3) & ~3;  // 64-byte rows: one 16-lane MFMA operand load
-      c->kp16[n] = (K[n] + 7) & ~7;
       c->F64[n].alloc(c, sizeof(double) * (size_t)c->dims[n] * K[n]);
       c->F32[n].alloc(c, sizeof(float) * (size_t)c->dims[n] * c->kp32[n]);
-      c->F16[n].alloc(c, sizeof(uint16_t) * (size_t)c->dims[n] * c->kp16[n]);
       std::vector<double> I((size_t)c->dims[n] * K[n], 0.0);
       for (int k = 0; k < K[n]; ++k) I[(size_t)k * K[n] + k] = 1.0;
       h2d(c, c->F64[n].as<double>(), I.data(), I.size());
@@ -522,6 +589,20 @@ tk_status tk_get_timings(tk_ctx* c, double* ms, const char** names, int* count) 
   for (int i = 0; i < w; ++i) {
     if (ms) ms[i] = c->timings.ms[i];
     if (names) names[i] = c->timings.names[i].c_str();
+  }
+  *count = w;
+  return TK_OK;
+}
+
+tk_status tk_get_counters(tk_ctx* c, int64_t* values, const char** names, int* count) {
+  if (!c || !count) return TK_ERR_INVALID_ARG;
+  static const char* const kNames[] = {"eig_krylov_solves", "eig_krylov_cycles", "eig_dense_fallbacks"};
+  const int64_t v[] = {c->counters.eig_krylov_solves, c->counters.eig_krylov_cycles,
+                       c->counters.eig_dense_fallbacks};
+  const int w = std::min(*count, 3);
+  for (int i = 0; i < w; ++i) {
+    if (values) values[i] = v[i];
+    if (names) names[i] = kNames[i];
   }
   *count = w;
   return TK_OK;

@@ -107,7 +107,6 @@ struct ModePlan {
   int64_t fix_rows = 0;         // n_slots + all level rows
   Buf lay_idx[7];         // int32[m_pad] other modes' coordinates in padded layout order (modes ascending)
   Buf lay_val;            // float[m_pad]
-  Buf lay_val_bf16;       // bf16[m] (precision form)
   Buf elem_order;         // uint32[m] canonical element index per layout position (optional)
 };
 
@@ -121,6 +120,26 @@ struct Timings {
     names.push_back(n);
     ms.push_back(v);
   }
+};
+
+// Event counts of the adaptive parts of the path (tk_get_counters).
+struct Counters {
+  int64_t eig_krylov_solves = 0;     // block-Krylov eigensolves
+  int64_t eig_krylov_cycles = 0;     // their restart cycles
+  int64_t eig_dense_fallbacks = 0;   // Krylov results replaced by the dense solver (estimate above eig_tol)
+};
+
+// A streamed load in progress (tk_load_coo_begin .. tk_load_coo_end): the raw
+// element list, filled append by append.
+struct LoadState {
+  bool active = false;
+  int N = 0;
+  int64_t dims[8] = {0};
+  int64_t nnz = 0, filled = 0;
+  unsigned flags = 0;
+  Buf raw[8];             // int32[nnz] per mode, input order
+  Buf rawv;               // float[nnz]
+  Buf flag;               // int32: 1 = coordinate out of range, 2 = NaN/Inf value
 };
 
 struct ObsSet {
@@ -143,6 +162,7 @@ struct Ctx {
   tk_options opt{};
   std::string last_error;
   int64_t bytes_in_use = 0;
+  tk_allocator allocator{};   // all-null: hipMalloc / hipFree
   int cu_count = 256;
   size_t lds_per_block = 65536;
 
@@ -154,6 +174,7 @@ struct Ctx {
   Buf idx_c[8];           // int32[m] canonical order
   Buf val_c;              // float[m]
   bool have_tensor = false;
+  LoadState load;
 
   // ranks / plans / factors
   int32_t K[8] = {0};
@@ -161,9 +182,7 @@ struct Ctx {
   ModePlan plan[8];
   Buf F64[8];             // double[L_n x K_n]
   Buf F32[8];             // float [L_n x Kp_n], Kp_n = padded row stride
-  Buf F16[8];             // bf16  [L_n x Kb_n]
   int kp32[8] = {0};      // FP32 row stride
-  int kp16[8] = {0};      // BF16 row stride
 
   // work buffers (grown on demand)
   Buf Y;                  // float [max R_n x Khat_n]
@@ -184,6 +203,7 @@ struct Ctx {
   Buf flag;               // int32 flags
 
   Timings timings;
+  Counters counters;
   hipEvent_t ev_ttm[2] = {nullptr, nullptr};  // when set, bracket the TTM-chain kernel launch
   ObsSet obs;
   bool have_obs = false;
@@ -191,6 +211,7 @@ struct Ctx {
   void* alloc_raw(size_t bytes);
   void free_raw(void* p, size_t bytes);
   void sync() { TK_HIP(hipStreamSynchronize(stream)); }
+  double eig_tol() const { return opt.eig_tol > 0.0 ? opt.eig_tol : 1e-7; }
 };
 
 inline void Buf::alloc(Ctx* c, size_t bytes) {
@@ -262,6 +283,12 @@ void sort_pairs_u32(Ctx* c, const uint32_t* kin, uint32_t* kout, const uint32_t*
                     int64_t n, int end_bit);
 void sort_pairs_u64_u32(Ctx* c, const uint64_t* kin, uint64_t* kout, const uint32_t* vin, uint32_t* vout,
                         int64_t n, int end_bit);
+void sort_pairs_u32_key(Ctx* c, const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, int64_t n,
+                        int end_bit);
+void sort_pairs_u32_key(Ctx* c, const uint32_t* kin, uint32_t* kout, const uint64_t* vin, uint64_t* vout, int64_t n,
+                        int end_bit);
+void exclusive_scan_pos(Ctx* c, const uint32_t* in, uint32_t* out, int64_t n);
+void exclusive_scan_pos(Ctx* c, const uint64_t* in, uint64_t* out, int64_t n);
 void exclusive_scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void inclusive_scan_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void exclusive_scan_i32(Ctx* c, const int32_t* in, int32_t* out, int64_t n);
@@ -269,8 +296,9 @@ void reduce_max_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
 void reduce_min_i64(Ctx* c, const int64_t* in, int64_t* out, int64_t n);
 
 // ---- stages ----
-void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx, const float* vals,
-              tk_mem mem);
+void load_begin(Ctx* c, int N, const int64_t* dims, int64_t nnz, unsigned flags);
+void load_append(Ctx* c, int64_t count, const int32_t* const* idx, const float* vals, tk_mem mem);
+void load_end(Ctx* c);
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
                 int64_t khat, int tile_w, int64_t wg_default, bool keep_order);
 void relabel_layout(Ctx* c, ModePlan& pl, int N, int n, const ModePlan* plans, int64_t m);
@@ -283,8 +311,8 @@ bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y, const uint16_t* const* H16 = nullptr);
-void ttm_chain(Ctx* c, int n, float* Y, bool bf16);
+             const float* lay_val, int64_t m, float* Y, bool bf16 = false, float* partial = nullptr);
+void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial = nullptr);
 void hooi_iterate(Ctx* c, int iters, double* fits);
 void core_and_fit(Ctx* c, double* core_dev, double* fit);
 

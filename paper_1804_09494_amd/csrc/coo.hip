@@ -1,8 +1,10 @@
 // Loading and coalescing the element list E (Section 3 keeps the tensor as a
 // set of elements, each a coordinate vector and a value).
 //
-// Steps, all on the device:
-//   1. validate coordinates (0 <= l_n < L_n) and values (finite) -> one flag;
+// The elements arrive in one or more appends (tk_load_coo_begin / _append /
+// _end; tk_load_coo is one append).  Steps, all on the device:
+//   1. validate coordinates (0 <= l_n < L_n) and values (finite) of each
+//      append -> one flag, read at the end;
 //   2. LSD radix sort of element positions by the coordinates, least
 //      significant mode first, so the result is lexicographic with l_1 most
 //      significant; the sort is stable, so repeated coordinates keep input order;
@@ -31,13 +33,16 @@ __global__ void k_validate_vals(const float* __restrict__ vals, int64_t m, int32
   if (bad) atomicOr(flag, 2);
 }
 
-__global__ void k_iota_u32(uint32_t* __restrict__ out, int64_t m) {
+// The element-position type PT is uint32_t below 2^32 elements, else uint64_t.
+template <class PT>
+__global__ void k_iota(PT* __restrict__ out, int64_t m) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = (uint32_t)i;
+    out[i] = (PT)i;
 }
 
-__global__ void k_gather_key(const int32_t* __restrict__ idx, const uint32_t* __restrict__ perm,
-                             uint32_t* __restrict__ key, int64_t m) {
+template <class PT>
+__global__ void k_gather_key(const int32_t* __restrict__ idx, const PT* __restrict__ perm, uint32_t* __restrict__ key,
+                             int64_t m) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x)
     key[i] = (uint32_t)idx[perm[i]];
 }
@@ -47,41 +52,66 @@ struct IdxPtrs {
   const int32_t* p[8];
 };
 
-__global__ void k_mark_runs(IdxPtrs idx, int N, const uint32_t* __restrict__ perm, int64_t m,
-                            int32_t* __restrict__ mark) {
+template <class PT>
+__global__ void k_mark_runs(IdxPtrs idx, int N, const PT* __restrict__ perm, int64_t m, PT* __restrict__ mark) {
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
-    int32_t f = 1;
+    PT f = 1;
     if (s > 0) {
-      uint32_t a = perm[s], b = perm[s - 1];
-      f = 0;
-      for (int j = 0; j < N; ++j) f |= (idx.p[j][a] != idx.p[j][b]);
+      const PT a = perm[s], b = perm[s - 1];
+      int d = 0;
+      for (int j = 0; j < N; ++j) d |= (idx.p[j][a] != idx.p[j][b]);
+      f = (PT)d;
     }
     mark[s] = f;
   }
 }
 
 // Run r starts at sorted position s where mark[s] == 1 and runid[s] = r.
-__global__ void k_run_starts(const int32_t* __restrict__ mark, const int32_t* __restrict__ runid, int64_t m,
-                             uint32_t* __restrict__ start) {
+template <class PT>
+__global__ void k_run_starts(const PT* __restrict__ mark, const PT* __restrict__ runid, int64_t m,
+                             PT* __restrict__ start) {
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x)
-    if (mark[s]) start[runid[s]] = (uint32_t)s;
+    if (mark[s]) start[runid[s]] = (PT)s;
 }
 
 struct OutPtrs {
   int32_t* p[8];
 };
 
-__global__ void k_merge_runs(IdxPtrs idx, int N, const float* __restrict__ vals, const uint32_t* __restrict__ perm,
-                             const uint32_t* __restrict__ start, int64_t runs, int64_t m, OutPtrs out_idx,
+// One thread per run: its values summed in FP64 in input order (the stable
+// sort keeps that order inside a run), rounded once.  Loads of 16 elements are
+// issued before their adds, which stay in order.
+template <class PT>
+__global__ void k_merge_runs(IdxPtrs idx, int N, const float* __restrict__ vals, const PT* __restrict__ perm,
+                             const PT* __restrict__ start, int64_t runs, int64_t m, OutPtrs out_idx,
                              float* __restrict__ out_val) {
   for (int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; r < runs; r += (int64_t)gridDim.x * blockDim.x) {
-    int64_t a = start[r];
-    int64_t b = (r + 1 < runs) ? (int64_t)start[r + 1] : m;
-    uint32_t e0 = perm[a];
+    const int64_t a = (int64_t)start[r];
+    const int64_t b = (r + 1 < runs) ? (int64_t)start[r + 1] : m;
+    const PT e0 = perm[a];
     double s = 0.0;
-    for (int64_t k = a; k < b; ++k) s += (double)vals[perm[k]];
+    int64_t k = a;
+    for (; k + 16 <= b; k += 16) {
+      float v[16];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) v[i] = vals[perm[k + i]];
+#pragma unroll
+      for (int i = 0; i < 16; ++i) s += (double)v[i];
+    }
+    for (; k < b; ++k) s += (double)vals[perm[k]];
     out_val[r] = (float)s;
     for (int j = 0; j < N; ++j) out_idx.p[j][r] = idx.p[j][e0];
+  }
+}
+
+// Elements known to be distinct: the sorted list itself.
+template <class PT>
+__global__ void k_gather_sorted(IdxPtrs idx, int N, const float* __restrict__ vals, const PT* __restrict__ perm,
+                                int64_t m, OutPtrs out_idx, float* __restrict__ out_val) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
+    const PT e = perm[s];
+    out_val[s] = vals[e];
+    for (int j = 0; j < N; ++j) out_idx.p[j][s] = idx.p[j][e];
   }
 }
 
@@ -121,85 +151,137 @@ static int bits_for(int64_t L) {
   return b < 1 ? 1 : b;
 }
 
-void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* const* idx, const float* vals,
-              tk_mem mem) {
-  const int B = 256;
-  // raw copies
-  Buf raw[8];
-  Buf rawv(c, sizeof(float) * (size_t)nnz);
-  for (int j = 0; j < N; ++j) {
-    raw[j].alloc(c, sizeof(int32_t) * (size_t)nnz);
-    copy_in(c, raw[j].as<int32_t>(), idx[j], (size_t)nnz, mem);
-  }
-  copy_in(c, rawv.as<float>(), vals, (size_t)nnz, mem);
+// ---- streamed load: begin, appends, end ---------------------------------------------------------
 
-  Buf flag(c, sizeof(int32_t));
-  TK_HIP(hipMemsetAsync(flag.get(), 0, sizeof(int32_t), c->stream));
-  for (int j = 0; j < N; ++j) {
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(nnz, B, 4096)), dim3(B), 0, c->stream, raw[j].as<int32_t>(), nnz,
-                       dims[j], flag.as<int32_t>());
+void load_begin(Ctx* c, int N, const int64_t* dims, int64_t nnz, unsigned flags) {
+  LoadState& ls = c->load;
+  ls = LoadState();
+  for (int j = 0; j < N; ++j) ls.raw[j].alloc(c, sizeof(int32_t) * (size_t)std::max<int64_t>(nnz, 1));
+  ls.rawv.alloc(c, sizeof(float) * (size_t)std::max<int64_t>(nnz, 1));
+  ls.flag.alloc(c, sizeof(int32_t));
+  TK_HIP(hipMemsetAsync(ls.flag.get(), 0, sizeof(int32_t), c->stream));
+  ls.N = N;
+  for (int j = 0; j < 8; ++j) ls.dims[j] = j < N ? dims[j] : 0;
+  ls.nnz = nnz;
+  ls.filled = 0;
+  ls.flags = flags;
+  ls.active = true;
+}
+
+void load_append(Ctx* c, int64_t count, const int32_t* const* idx, const float* vals, tk_mem mem) {
+  LoadState& ls = c->load;
+  const int B = 256;
+  const int64_t off = ls.filled;
+  for (int j = 0; j < ls.N; ++j) {
+    int32_t* dst = ls.raw[j].as<int32_t>() + off;
+    copy_in(c, dst, idx[j], (size_t)count, mem);
+    hipLaunchKernelGGL(k_validate, dim3(grid_for(count, B, 4096)), dim3(B), 0, c->stream, dst, count, ls.dims[j],
+                       ls.flag.as<int32_t>());
     TK_CHECK_LAUNCH();
   }
-  hipLaunchKernelGGL(k_validate_vals, dim3(grid_for(nnz, B, 4096)), dim3(B), 0, c->stream, rawv.as<float>(), nnz,
-                     flag.as<int32_t>());
+  float* dv = ls.rawv.as<float>() + off;
+  copy_in(c, dv, vals, (size_t)count, mem);
+  hipLaunchKernelGGL(k_validate_vals, dim3(grid_for(count, B, 4096)), dim3(B), 0, c->stream, dv, count,
+                     ls.flag.as<int32_t>());
   TK_CHECK_LAUNCH();
-  int32_t hflag = 0;
-  d2h(c, &hflag, flag.as<int32_t>(), 1);
+  // the caller may reuse its buffers once the call returns
   c->sync();
-  if (hflag & 1) fail(TK_ERR_INVALID_ARG, "tk_load_coo: a coordinate is out of range");
-  if (hflag & 2) fail(TK_ERR_INVALID_ARG, "tk_load_coo: a value is NaN or Inf");
+  ls.filled += count;
+}
 
-  // LSD sort by coordinates, least significant mode (N-1) first.
-  Buf perm(c, sizeof(uint32_t) * (size_t)nnz), perm2(c, sizeof(uint32_t) * (size_t)nnz);
-  Buf key(c, sizeof(uint32_t) * (size_t)nnz), key2(c, sizeof(uint32_t) * (size_t)nnz);
-  hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, perm.as<uint32_t>(), nnz);
+template <class PT>
+static void coalesce(Ctx* c, int N, const int64_t* dims, int64_t nnz, Buf* raw, Buf& rawv, bool assume_unique) {
+  const int B = 256;
+  // LSD sort by coordinates, least significant mode (N-1) first; stable, so
+  // repeated coordinates keep input order
+  const size_t n1 = (size_t)std::max<int64_t>(nnz, 1);
+  Buf perm(c, sizeof(PT) * n1), perm2(c, sizeof(PT) * n1);
+  Buf key(c, sizeof(uint32_t) * n1), key2(c, sizeof(uint32_t) * n1);
+  hipLaunchKernelGGL(k_iota<PT>, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, perm.as<PT>(), nnz);
   TK_CHECK_LAUNCH();
   for (int j = N - 1; j >= 0; --j) {
-    hipLaunchKernelGGL(k_gather_key, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, raw[j].as<int32_t>(),
-                       perm.as<uint32_t>(), key.as<uint32_t>(), nnz);
+    hipLaunchKernelGGL(k_gather_key<PT>, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, raw[j].as<int32_t>(),
+                       perm.as<PT>(), key.as<uint32_t>(), nnz);
     TK_CHECK_LAUNCH();
-    sort_pairs_u32(c, key.as<uint32_t>(), key2.as<uint32_t>(), perm.as<uint32_t>(), perm2.as<uint32_t>(), nnz,
-                   bits_for(dims[j]));
+    sort_pairs_u32_key(c, key.as<uint32_t>(), key2.as<uint32_t>(), perm.as<PT>(), perm2.as<PT>(), nnz,
+                       bits_for(dims[j]));
     std::swap(perm, perm2);
   }
+  perm2.release();
+  key.release();
   key2.release();
 
   IdxPtrs ip{};
   for (int j = 0; j < N; ++j) ip.p[j] = raw[j].as<int32_t>();
-  Buf mark(c, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1)), runid(c, sizeof(int32_t) * (size_t)(nnz > 0 ? nnz : 1));
-  int64_t runs = 0;
-  if (nnz > 0) {
-    hipLaunchKernelGGL(k_mark_runs, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, ip, N, perm.as<uint32_t>(), nnz,
-                       mark.as<int32_t>());
+  int64_t runs = nnz;
+  Buf mark, runid;
+  if (!assume_unique && nnz > 0) {
+    mark.alloc(c, sizeof(PT) * n1);
+    runid.alloc(c, sizeof(PT) * n1);
+    hipLaunchKernelGGL(k_mark_runs<PT>, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, ip, N, perm.as<PT>(), nnz,
+                       mark.as<PT>());
     TK_CHECK_LAUNCH();
-    exclusive_scan_i32(c, mark.as<int32_t>(), runid.as<int32_t>(), nnz);
-    int32_t last_id = 0, last_mark = 0;
-    d2h(c, &last_id, runid.as<int32_t>() + nnz - 1, 1);
-    d2h(c, &last_mark, mark.as<int32_t>() + nnz - 1, 1);
+    exclusive_scan_pos(c, mark.as<PT>(), runid.as<PT>(), nnz);
+    PT last_id = 0, last_mark = 0;
+    d2h(c, &last_id, runid.as<PT>() + nnz - 1, 1);
+    d2h(c, &last_mark, mark.as<PT>() + nnz - 1, 1);
     c->sync();
-    runs = (int64_t)last_id + last_mark;
+    runs = (int64_t)last_id + (int64_t)last_mark;
   }
-  Buf start(c, sizeof(uint32_t) * (size_t)(runs > 0 ? runs : 1));
+  TK_REQUIRE(runs < ((int64_t)1 << 32), TK_ERR_UNSUPPORTED,
+             "this build handles fewer than 2^32 distinct coordinates");
   for (int j = 0; j < 8; ++j) c->idx_c[j].release();
   c->val_c.release();
   OutPtrs op{};
+  const size_t r1 = (size_t)std::max<int64_t>(runs, 1);
   for (int j = 0; j < N; ++j) {
-    c->idx_c[j].alloc(c, sizeof(int32_t) * (size_t)(runs > 0 ? runs : 1));
+    c->idx_c[j].alloc(c, sizeof(int32_t) * r1);
     op.p[j] = c->idx_c[j].as<int32_t>();
   }
-  c->val_c.alloc(c, sizeof(float) * (size_t)(runs > 0 ? runs : 1));
-  if (runs > 0) {
-    hipLaunchKernelGGL(k_run_starts, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, mark.as<int32_t>(),
-                       runid.as<int32_t>(), nnz, start.as<uint32_t>());
+  c->val_c.alloc(c, sizeof(float) * r1);
+  if (runs > 0 && assume_unique) {
+    hipLaunchKernelGGL(k_gather_sorted<PT>, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, ip, N, rawv.as<float>(),
+                       perm.as<PT>(), nnz, op, c->val_c.as<float>());
     TK_CHECK_LAUNCH();
-    hipLaunchKernelGGL(k_merge_runs, dim3(grid_for(runs, B)), dim3(B), 0, c->stream, ip, N, rawv.as<float>(),
-                       perm.as<uint32_t>(), start.as<uint32_t>(), runs, nnz, op, c->val_c.as<float>());
+  } else if (runs > 0) {
+    Buf start(c, sizeof(PT) * r1);
+    hipLaunchKernelGGL(k_run_starts<PT>, dim3(grid_for(nnz, B)), dim3(B), 0, c->stream, mark.as<PT>(),
+                       runid.as<PT>(), nnz, start.as<PT>());
     TK_CHECK_LAUNCH();
+    mark.release();
+    runid.release();
+    hipLaunchKernelGGL(k_merge_runs<PT>, dim3(grid_for(runs, B)), dim3(B), 0, c->stream, ip, N, rawv.as<float>(),
+                       perm.as<PT>(), start.as<PT>(), runs, nnz, op, c->val_c.as<float>());
+    TK_CHECK_LAUNCH();
+    c->sync();
   }
+  c->m = runs;
+}
+
+void load_end(Ctx* c) {
+  LoadState& ls = c->load;
+  TK_REQUIRE(ls.filled == ls.nnz, TK_ERR_INVALID_ARG,
+             "tk_load_coo_end: " + std::to_string(ls.filled) + " of " + std::to_string(ls.nnz) +
+                 " announced elements were appended");
+  int32_t hflag = 0;
+  d2h(c, &hflag, ls.flag.as<int32_t>(), 1);
+  c->sync();
+  if (hflag & 1) fail(TK_ERR_INVALID_ARG, "tk_load_coo: a coordinate is out of range");
+  if (hflag & 2) fail(TK_ERR_INVALID_ARG, "tk_load_coo: a value is NaN or Inf");
+  const int N = ls.N;
+  const bool unique = (ls.flags & TK_ASSUME_UNIQUE) != 0;
+  if (ls.nnz < ((int64_t)1 << 32))
+    coalesce<uint32_t>(c, N, ls.dims, ls.nnz, ls.raw, ls.rawv, unique);
+  else
+    coalesce<uint64_t>(c, N, ls.dims, ls.nnz, ls.raw, ls.rawv, unique);
+  for (int j = 0; j < 8; ++j) ls.raw[j].release();
+  ls.rawv.release();
+  ls.active = false;
+
   // ||T||^2
   const int nb = 1024;
   Buf part(c, sizeof(double) * (nb + 1));
-  hipLaunchKernelGGL(k_sumsq_blocks, dim3(nb), dim3(256), 0, c->stream, c->val_c.as<float>(), runs,
+  hipLaunchKernelGGL(k_sumsq_blocks, dim3(nb), dim3(256), 0, c->stream, c->val_c.as<float>(), c->m,
                      part.as<double>());
   TK_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, c->stream, part.as<double>(), nb, part.as<double>() + nb);
@@ -209,8 +291,7 @@ void load_coo(Ctx* c, int N, const int64_t* dims, int64_t nnz, const int32_t* co
   c->sync();
 
   c->N = N;
-  for (int j = 0; j < 8; ++j) c->dims[j] = j < N ? dims[j] : 0;
-  c->m = runs;
+  for (int j = 0; j < 8; ++j) c->dims[j] = j < N ? ls.dims[j] : 0;
   c->norm_sq = nsq;
   c->have_tensor = true;
 }

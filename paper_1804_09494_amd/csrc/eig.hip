@@ -1030,16 +1030,14 @@ constexpr int KRYLOV_MIN_N = 192;   // above this, and for K <= 16, the block-Kr
 // Leading K eigenpairs of G (n0 x n0, FP64): lam_k[0..K) descending and VK (n0 x K).
 // Eigenpairs beyond n0 (K > n0) are reported as zero eigenvalues.  mode >= 0
 // lets the Krylov solver start from that mode's previous eigenvectors.
-void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode) {
+// The dense solvers (one workgroup): LDS-resident for K-hat up to about 128,
+// otherwise with the matrix in LDS or global memory.
+void eig_topk_dense(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK) {
   const int Ke = K < n0 ? K : n0;
   TK_REQUIRE(Ke <= 32, TK_ERR_UNSUPPORTED, "eigensolve: more than 32 eigenpairs");
   const size_t lim = c->lds_per_block;
   const SmallLayout SL = small_layout(n0, Ke);
   const bool small = n0 <= SM_N && Ke <= 16 && (size_t)SL.total * 8 <= lim;
-  if (!small && n0 >= KRYLOV_MIN_N && Ke <= 16) {
-    eig_topk_krylov(c, G, n0, Ke, K, lam_k, VK, mode);
-    return;
-  }
   const EigLayout L = eig_layout(n0, Ke);
   ensure(c, c->work, sizeof(double) * (size_t)(L.total + 16));
   if (K > Ke) TK_HIP(hipMemsetAsync(lam_k, 0, sizeof(double) * K, c->stream));
@@ -1057,6 +1055,18 @@ void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK,
     hipLaunchKernelGGL(k_syev_topk<0>, dim3(1), dim3(EIG_THREADS), 0, c->stream, G, n0, Ke, K, L, ws, lam_k, VK);
   }
   TK_CHECK_LAUNCH();
+}
+
+void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode) {
+  const int Ke = K < n0 ? K : n0;
+  TK_REQUIRE(Ke <= 32, TK_ERR_UNSUPPORTED, "eigensolve: more than 32 eigenpairs");
+  const SmallLayout SL = small_layout(n0, Ke);
+  const bool small = n0 <= SM_N && Ke <= 16 && (size_t)SL.total * 8 <= c->lds_per_block;
+  if (!small && n0 >= KRYLOV_MIN_N && Ke <= 16) {
+    eig_topk_krylov(c, G, n0, Ke, K, lam_k, VK, mode);
+    return;
+  }
+  eig_topk_dense(c, G, n0, K, lam_k, VK);
 }
 
 }  // namespace tk

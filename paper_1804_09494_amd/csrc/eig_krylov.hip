@@ -12,7 +12,11 @@
 //   Rayleigh-Ritz: H = Q^T (G Q)  (KR_S*KR_B square), its leading K eigenpairs by
 //         the dense solver, V = Q S;
 //   the largest residual ||G v - theta v|| / theta_1 decides a restart from V
-//   (up to KR_CYCLES cycles, ending early once a restart stops improving it).
+//   (up to KR_CYCLES cycles, ending early once a restart stops improving it);
+//   the cycle with the smallest residual is kept.  Its subspace error is
+//   bounded through the sin-theta theorem (Davis-Kahan) by
+//   sqrt(2) * residual * theta_1 / (theta_K - theta_{K+1}); above the
+//   context's eig_tol the dense solver is run on G instead.
 // The tall-skinny products are plain FP64 kernels with fixed-order partial sums.
 #include <cmath>
 
@@ -21,6 +25,7 @@
 namespace tk {
 
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode);
+void eig_topk_dense(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK);
 
 constexpr int KR_B = 16;    // block width
 constexpr int KR_S = 6;     // blocks per cycle (subspace KR_S * KR_B = 96: the dense solver's LDS path)
@@ -251,7 +256,7 @@ __global__ __launch_bounds__(256) void k_kr_resid(const double* __restrict__ GV,
 
 namespace {
 struct KrBufs {
-  double *Q, *GQ, *W, *W2, *small, *H, *lamH, *S, *GV, *res;
+  double *Q, *GQ, *W, *W2, *small, *H, *lamH, *S, *GV, *res, *bestV, *bestLam;
 };
 
 unsigned g1(int64_t n) { return (unsigned)((n + 255) / 256); }
@@ -299,10 +304,12 @@ void cholqr(Ctx* c, const KrBufs& b, int n, int q0) {
 // mode >= 0 keeps the eigenvectors for that mode's next call.
 void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* lam_k, double* VK, int mode) {
   TK_REQUIRE(K <= KR_B, TK_ERR_UNSUPPORTED, "Krylov eigensolve: more than 16 eigenpairs");
+  // the Rayleigh-Ritz step also yields theta_{K+1}, the gap estimate
+  const int Kr = K + 1;
   KrBufs b{};
   const size_t nQ = (size_t)n * KR_M;
-  const size_t need = 2 * nQ + 2 * (size_t)n * KR_B + 4 * KR_B * KR_B + KR_M * KR_M + 64 + (size_t)KR_M * KR_B +
-                      (size_t)n * KR_B + 8;
+  const size_t need = 2 * nQ + 2 * (size_t)n * KR_B + 4 * KR_B * KR_B + KR_M * KR_M + 64 +
+                      (size_t)KR_M * (KR_B + 1) + (size_t)n * KR_B + 8 + (size_t)n * KR_B + KR_B;
   ensure(c, c->kr_work, sizeof(double) * need);
   double* p = c->kr_work.as<double>();
   b.Q = p; p += nQ;
@@ -312,12 +319,15 @@ void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* la
   b.small = p; p += 4 * KR_B * KR_B;
   b.H = p; p += KR_M * KR_M;
   b.lamH = p; p += 64;
-  b.S = p; p += (size_t)KR_M * KR_B;
+  b.S = p; p += (size_t)KR_M * (KR_B + 1);
   b.GV = p; p += (size_t)n * KR_B;
-  b.res = p;
+  b.res = p; p += 8;
+  b.bestV = p; p += (size_t)n * KR_B;
+  b.bestLam = p;
   Buf* warm = mode >= 0 ? &c->eig_warm[mode] : nullptr;
   int kw = (warm && c->eig_warm_k[mode] == K && warm->bytes() >= sizeof(double) * (size_t)n * K) ? K : 0;
-  double prev_res = 0.0;
+  double prev_res = 0.0, best_res = 0.0, best_err = 0.0;
+  int best_cycle = -1, last_cycle = -1;
   for (int cycle = 0; cycle < KR_CYCLES; ++cycle) {
     // start block: the warm vectors (first cycle) or the last Ritz vectors (restart), then seeded directions
     const double* wsrc = nullptr;
@@ -350,21 +360,50 @@ void eig_topk_krylov(Ctx* c, const double* G, int n, int K, int Kout, double* la
       }
       cholqr(c, b, n, J);
     }
-    // Rayleigh-Ritz on span(Q)
+    // Rayleigh-Ritz on span(Q): K + 1 Ritz pairs, the first K kept
     tn(c, b.Q, KR_M, KR_M, b.GQ, KR_M, KR_M, n, b.H);
-    eig_topk(c, b.H, KR_M, K, b.lamH, b.S, -1);
-    nn<false>(c, b.Q, KR_M, KR_M, b.S, K, nullptr, 0, VK, Kout, n, K);
+    eig_topk(c, b.H, KR_M, Kr, b.lamH, b.S, -1);
+    nn<false>(c, b.Q, KR_M, KR_M, b.S, Kr, nullptr, 0, VK, Kout, n, K);
     TK_HIP(hipMemcpyAsync(lam_k, b.lamH, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
     // residual check
     nn<false>(c, G, n, n, VK, Kout, nullptr, 0, b.GV, K, n, K);
     hipLaunchKernelGGL(k_kr_resid, dim3(1), dim3(256), 0, c->stream, b.GV, VK, Kout, lam_k, n, K, b.res);
     TK_CHECK_LAUNCH();
-    double res = 0.0;
-    TK_HIP(hipMemcpyAsync(&res, b.res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double hres[3] = {0.0, 0.0, 0.0};   // residual / theta_1, theta_1, theta_{K+1}
+    TK_HIP(hipMemcpyAsync(&hres[0], b.res, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    TK_HIP(hipMemcpyAsync(&hres[1], b.lamH, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    double thK[2] = {0.0, 0.0};
+    TK_HIP(hipMemcpyAsync(thK, b.lamH + K - 1, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     c->sync();
+    const double res = hres[0];
+    const double gap = thK[0] - thK[1];
+    // estimated projector distance of the Ritz subspace from the eigenspace
+    const double err = hres[1] > 0.0 ? (gap > 0.0 ? std::sqrt(2.0) * res * hres[1] / gap : HUGE_VAL) : 0.0;
+    last_cycle = cycle;
+    ++c->counters.eig_krylov_cycles;
+    if (best_cycle < 0 || res < best_res) {
+      best_res = res;
+      best_err = err;
+      best_cycle = cycle;
+      TK_HIP(hipMemcpy2DAsync(b.bestV, sizeof(double) * K, VK, sizeof(double) * Kout, sizeof(double) * K, n,
+                              hipMemcpyDeviceToDevice, c->stream));
+      TK_HIP(hipMemcpyAsync(b.bestLam, lam_k, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+    }
     // converged, or a restart that no longer improves (rounding floor)
-    if (res <= 1e-10 || (cycle > 0 && res > 0.5 * prev_res)) break;
+    if ((res <= 1e-10 && err <= c->eig_tol()) || (cycle > 0 && res > 0.5 * prev_res)) break;
     prev_res = res;
+  }
+  ++c->counters.eig_krylov_solves;
+  if (best_cycle != last_cycle) {
+    TK_HIP(hipMemcpy2DAsync(VK, sizeof(double) * Kout, b.bestV, sizeof(double) * K, sizeof(double) * K, n,
+                            hipMemcpyDeviceToDevice, c->stream));
+    TK_HIP(hipMemcpyAsync(lam_k, b.bestLam, sizeof(double) * K, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (!(best_err <= c->eig_tol())) {
+    // the Krylov subspace is not accurate enough (slow convergence or a tight
+    // gap at K): the dense solver on G
+    ++c->counters.eig_dense_fallbacks;
+    eig_topk_dense(c, G, n, Kout, lam_k, VK);
   }
   if (warm) {
     ensure(c, *warm, sizeof(double) * (size_t)n * K);

@@ -5,7 +5,7 @@
 //   CholeskyQR2 in FP64: A = U^T U, A = R^T R (Cholesky), U <- U R^-1, twice,
 //   which restores orthonormality to working precision;
 //   F_n = U on the nonempty slices' rows, zero elsewhere (FP64 master),
-//   plus the padded FP32 and BF16 working copies the TTM-chain gathers.
+//   plus the padded FP32 working copy the TTM-chain gathers.
 // Columns whose singular value is zero (rank deficiency) are completed on the
 // host with unit vectors e_i (lowest i not yet spanned, Gram-Schmidt in FP64).
 #include <cmath>
@@ -61,12 +61,6 @@ __global__ __launch_bounds__(256) void k_uw(const float* __restrict__ Y, int64_t
     const int i = threadIdx.x + 256 * q;
     if (i < K * K) part[(int64_t)blockIdx.x * K * K + i] = acc[q];
   }
-}
-
-__device__ __forceinline__ uint16_t to_bf16_rne(float f) {
-  uint32_t b = __float_as_uint(f);
-  b += 0x7FFFu + ((b >> 16) & 1u);   // round to nearest even
-  return (uint16_t)(b >> 16);
 }
 
 typedef float floatx4_f __attribute__((ext_vector_type(4)));
@@ -149,14 +143,13 @@ __global__ __launch_bounds__(256) void k_uw_mfma(const float* __restrict__ Y, in
 // A[i = l%16][k = l/16] = U[row i][4s + k] and B[k][j = l%16] = Rinv[4s + k][j]
 // for s = 0..3; v_mfma_f64_16x16x4_f64 returns D[l/16 + 4r][l%16] in register r.  Not FINAL: write U back and the partial U^T U of the result.
 // FINAL: write the rows straight into the factor's FP64 master (slice order)
-// and its FP32 / BF16 working copies (storage labels).
+// and its FP32 working copy (storage labels).
 template <bool FINAL>
 __global__ __launch_bounds__(256) void k_rinv_mfma(double* __restrict__ U, int64_t R, int K,
                                                    const double* __restrict__ Rinv, double* __restrict__ part,
                                                    const int32_t* __restrict__ row_slice,
                                                    const int32_t* __restrict__ label, double* __restrict__ F64,
-                                                   float* __restrict__ F32, int kp32, uint16_t* __restrict__ F16,
-                                                   int kp16, const int* __restrict__ abort) {
+                                                   float* __restrict__ F32, int kp32, const int* __restrict__ abort) {
   // FINAL: an earlier mode of this invocation failed; keep this factor as it was
   if (FINAL && abort && *abort) return;
   __shared__ double red[256];
@@ -189,7 +182,6 @@ __global__ __launch_bounds__(256) void k_rinv_mfma(double* __restrict__ U, int64
           const int64_t sl = label[l];
           F64[l * K + i16] = c[r];
           F32[sl * kp32 + i16] = (float)c[r];
-          F16[sl * kp16 + i16] = to_bf16_rne((float)c[r]);
         } else {
           U[rr * K + i16] = c[r];
         }
@@ -368,22 +360,39 @@ __global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__
 
 // W = V_K diag(lam)^(-1/2); a column with a non-positive or negligible
 // eigenvalue (relative to the largest) is zeroed and flagged (bit 1).
-__global__ void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam, int khat, int K,
-                         double* __restrict__ W, int* __restrict__ flag) {
-  const double l0 = lam[0];
+// W = V_K diag(lam)^(-1/2).  A column whose eigenvalue is at or below the
+// Gram's rounding floor is not a direction of Y: the FP32 Gram carries an
+// error of about c u ||Y||_F^2 (u = 2^-24), so eigenvalues up to
+// RANK_FLOOR * trace(G) cannot be told from zero.  Such a column sets flag
+// bit 2 (rank deficiency) and gets W = 0.
+constexpr double RANK_FLOOR = 16.0 / 16777216.0;   // 16 u
+
+__global__ __launch_bounds__(256) void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam,
+                                                const double* __restrict__ G, int khat, int K, double* __restrict__ W,
+                                                int* __restrict__ flag) {
+  __shared__ double red[256];
+  double t = 0.0;
+  for (int i = threadIdx.x; i < khat; i += 256) t += G[(int64_t)i * khat + i];
+  red[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double floor_ = RANK_FLOOR * red[0];
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < khat * K; i += gridDim.x * blockDim.x) {
     const int k = i % K;
-    const bool ok = k < khat && l0 > 0.0 && lam[k] > 1e-13 * l0 * (double)khat;  // only khat eigenpairs exist
+    const bool ok = k < khat && lam[k] > floor_ && lam[k] > 0.0;  // only khat eigenpairs exist
     W[i] = ok ? VK[i] / sqrt(lam[k]) : 0.0;
     if (!ok && i < K) atomicOr(flag, 2);
   }
 }
 
-// F64[row_slice[r]] = U[r] (index order); FP32 / BF16 working copies of the
-// same rows at their storage labels.
+// F64[row_slice[r]] = U[r] (index order); the FP32 working copy of the same
+// rows at their storage labels.
 __global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
                                  const int32_t* __restrict__ label, double* __restrict__ F64, float* __restrict__ F32,
-                                 int kp32, uint16_t* __restrict__ F16, int kp16, const int* __restrict__ abort) {
+                                 int kp32, const int* __restrict__ abort) {
   if (abort && *abort) return;   // an earlier mode of this invocation failed
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R * K; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = i / K;
@@ -393,20 +402,17 @@ __global__ void k_scatter_factor(const double* __restrict__ U, int64_t R, int K,
     const double v = U[i];
     F64[l * K + k] = v;
     F32[s * kp32 + k] = (float)v;
-    F16[s * kp16 + k] = to_bf16_rne((float)v);
   }
 }
 
-// FP32 / BF16 working copies of a whole FP64 factor at the storage labels (padding stays zero).
+// The FP32 working copy of a whole FP64 factor at the storage labels (padding stays zero).
 __global__ void k_factor_copies(const double* __restrict__ F64, int64_t L, int K, const int32_t* __restrict__ label,
-                                float* __restrict__ F32, int kp32, uint16_t* __restrict__ F16, int kp16) {
+                                float* __restrict__ F32, int kp32) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * K; i += (int64_t)gridDim.x * blockDim.x) {
     const int64_t l = i / K;
     const int k = (int)(i - l * K);
     const int64_t s = label[l];
-    const float f = (float)F64[i];
-    F32[s * kp32 + k] = f;
-    F16[s * kp16 + k] = to_bf16_rne(f);
+    F32[s * kp32 + k] = (float)F64[i];
   }
 }
 
@@ -414,10 +420,8 @@ void refresh_factor_copies(Ctx* c, int n) {
   const int64_t L = c->dims[n];
   const int K = c->K[n];
   TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
-  TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
   hipLaunchKernelGGL(k_factor_copies, dim3(grid_for(L * K, 256)), dim3(256), 0, c->stream, c->F64[n].as<double>(), L,
-                     K, c->plan[n].label.as<int32_t>(), c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(),
-                     c->kp16[n]);
+                     K, c->plan[n].label.as<int32_t>(), c->F32[n].as<float>(), c->kp32[n]);
   TK_CHECK_LAUNCH();
 }
 
@@ -498,8 +502,8 @@ __global__ void k_flag_record(int* flag, int n) {
 // set, this call leaves factor n as it was (the caller runs the mode again
 // after completing the failed factor); a failure of this mode sets it when
 // R >= K, and is completed at once when R < K.
-bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* lam_k, const double* VK,
-                 int* flag_dev, bool deferred) {
+bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* Gfull, const double* lam_k,
+                 const double* VK, int* flag_dev, bool deferred) {
   const int* abort = deferred ? flag_dev + 1 : nullptr;
   const bool check_flag = !deferred || R < c->K[n];
   const int K = c->K[n];
@@ -517,16 +521,18 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   double* U = c->U64.as<double>();
   const ModePlan& pl = c->plan[n];
   TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
-  hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, khat,
-                     K, W, flag_dev);
+  hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, Gfull,
+                     khat, K, W, flag_dev);
   TK_CHECK_LAUNCH();
   // rows of empty slices (never written below) must be zero: clear the copies
   // only when something else may have written them (tk_set_factor, completion)
   auto clear_factor = [&]() {
     if (!c->fac_dirty[n]) return;
     if (abort) {
-      // deferred check: a later pass may have to keep this factor as it was
-      for (Buf* b : {&c->F64[n], &c->F32[n], &c->F16[n]}) {
+      // deferred check: a later pass may have to keep this factor as it was;
+      // the clear then does not happen, and the driver marks the factor dirty
+      // again before that pass
+      for (Buf* b : {&c->F64[n], &c->F32[n]}) {
         const int64_t n16 = (int64_t)(b->bytes() / 2);
         hipLaunchKernelGGL(k_clear_unless, dim3(grid_for(n16, 256, 4096)), dim3(256), 0, c->stream,
                            b->as<uint16_t>(), n16, abort);
@@ -535,7 +541,6 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     } else {
       TK_HIP(hipMemsetAsync(c->F64[n].get(), 0, c->F64[n].bytes(), c->stream));
       TK_HIP(hipMemsetAsync(c->F32[n].get(), 0, c->F32[n].bytes(), c->stream));
-      TK_HIP(hipMemsetAsync(c->F16[n].get(), 0, c->F16[n].bytes(), c->stream));
     }
     c->fac_dirty[n] = false;
   };
@@ -560,13 +565,13 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     TK_CHECK_LAUNCH();
     reduce_chol();
     hipLaunchKernelGGL(k_rinv_mfma<false>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part, nullptr, nullptr,
-                       nullptr, nullptr, 0, nullptr, 0, nullptr);
+                       nullptr, nullptr, 0, nullptr);
     TK_CHECK_LAUNCH();
     reduce_chol();
     clear_factor();
     hipLaunchKernelGGL(k_rinv_mfma<true>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part,
                        pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
-                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n], abort);
+                       c->F32[n].as<float>(), c->kp32[n], abort);
     TK_CHECK_LAUNCH();
   } else if (R > 0) {
     size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
@@ -582,7 +587,7 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     clear_factor();
     hipLaunchKernelGGL(k_scatter_factor, dim3(grid_for(R * K, 256)), dim3(256), 0, c->stream, U, R, K,
                        pl.row_slice.as<int32_t>(), pl.label.as<int32_t>(), c->F64[n].as<double>(),
-                       c->F32[n].as<float>(), c->kp32[n], c->F16[n].as<uint16_t>(), c->kp16[n], abort);
+                       c->F32[n].as<float>(), c->kp32[n], abort);
     TK_CHECK_LAUNCH();
   } else {
     clear_factor();

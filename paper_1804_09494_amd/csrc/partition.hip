@@ -319,7 +319,7 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   pl = ModePlan();
   pl.L = L;
   pl.khat = khat;
-  TK_REQUIRE(m < ((int64_t)1 << 31), TK_ERR_UNSUPPORTED, "this build handles fewer than 2^31 elements");
+  TK_REQUIRE(m < ((int64_t)1 << 32), TK_ERR_UNSUPPORTED, "this build handles fewer than 2^32 elements");
 
   // 1. slice-sorted order of the elements (stable => canonical order inside a slice)
   Buf key(c, 4 * (size_t)(m ? m : 1)), skey(c, 4 * (size_t)(m ? m : 1));

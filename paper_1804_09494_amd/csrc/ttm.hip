@@ -2,19 +2,17 @@
 // Appendix A): row l of Y_(n) is the sum over the elements e of slice l of
 // val(e) * (F_a[l_a] (x) F_b[l_b] (x) ...), the first remaining mode fastest.
 //
-// One workgroup per Lite bin (and per column tile when Khat is wide).  A bin
-// holds at most `limit` elements and at most ceil(L/P) + 2 distinct slices
-// (Theorem 6.1), so its rows of Y live in LDS for the whole bin:
-//   * each thread takes a contiguous run of the bin's elements (the layout is
-//     slice-sorted, so a run crosses few slice boundaries) and keeps the
-//     running Kronecker sum of its current slice in registers;
-//   * at a slice boundary the thread adds its registers into that slice's LDS
-//     row (ds_add_f32) and starts over;
-//   * after the bin, rows of slices the bin owns alone are written straight to
-//     Y; rows of slices split over several bins go to a partial slot, and the
-//     fixup kernel sums those slots in bin order.
-// Factor rows are gathered with 16-byte loads from FP32 copies whose row
-// stride is padded to a multiple of four floats.
+// One workgroup (or one wave) per Lite bin.  A bin holds at most `limit`
+// elements and at most ceil(L/P) + 2 distinct slices (Theorem 6.1), so its
+// rows of Y live in LDS for the whole bin; after the bin, rows of slices the
+// bin owns alone are written straight to Y and rows of slices split over
+// several bins go to a partial slot, which the fixup kernels sum in bin order.
+// Three kernels:
+//   * k_ttm3_mfma: three modes, other ranks <= 16, on the matrix cores;
+//   * k_ttm4_mfma: four modes, other ranks <= 16, on the matrix cores;
+//   * k_ttm_cols:  every other shape, on the vector ALUs.
+// None of them uses atomics: every sum runs in a fixed order.
+
 #include "common.hpp"
 
 namespace tk {
@@ -31,7 +29,6 @@ struct TtmArgs {
   const int32_t* lay[7];    // other modes' coordinates in layout order (ascending mode)
   const float* val;
   const float* F[7];        // FP32 factor copies of the other modes
-  const uint16_t* H[7];     // BF16 copies (row stride 16) for the precision form, or null
   int fstride[7];
   int Kj[7];
   int div[7];               // prod of Kj[1..j-1] (digit divisors of the slow index)
@@ -70,130 +67,160 @@ __device__ __forceinline__ int64_t xcd_bin(int64_t b, int64_t G) {
   return x * q + (x < r ? x : r) + i;
 }
 
-// MODE 1: two-mode tensors (one remaining mode).  MODE 2: three modes, the
-// slow factor is one row.  MODE 3: four or more modes, the slow factor is the
-// Kronecker of several rows, formed per element for the tile's columns.
-// EXACT: KA equals the runtime rank; otherwise KA is an upper bound.
-template <int KA, int TW, int MODE, bool EXACT>
-__global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
-  extern __shared__ float lds[];
-  constexpr int TILEW = KA * TW;
+// ---- TTM-chain on the vector ALUs (every shape the matrix-core kernels do not take) -------------
+//
+// One workgroup of four waves per (Lite bin, tile of TTMV_TILE columns of Y).
+// The waves take contiguous quarters of the bin's elements and stream them in
+// order; a lane owns TTMV_CPL columns of the tile and accumulates, for the
+// current slice, val(e) * prod_j F_j[l_j(e)][digit_j(col)] for each of them
+// (the Kronecker column of Appendix A, first remaining mode fastest).  The
+// coordinates and values of 64 elements at a time are loaded by the lanes
+// together and broadcast with readlane; the gathers of TTMV_U elements are
+// issued before their products are added.
+// When a slice ends, its row goes to the bin's LDS rows: stored when the slice
+// lies inside the wave's quarter, added at once when it began in an earlier
+// quarter (no other wave writes that row before the barrier), kept in
+// registers when it continues into a later quarter.  After the barrier the
+// waves add those kept rows in wave order.  Every sum therefore runs in a
+// fixed order: no atomics, bit-identical reruns.
+constexpr int TTMV_CPL = 2;                  // columns per lane
+constexpr int TTMV_TILE = 64 * TTMV_CPL;     // columns per tile
+constexpr int TTMV_U = 8;                    // elements whose gathers are in flight together
+
+__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
+
+// NO: number of other modes (1, 2, 3), or 0 for any number up to 7 (runtime).
+template <int NO>
+__global__ __launch_bounds__(256) void k_ttm_cols(TtmArgs A) {
+  extern __shared__ __align__(16) float lds[];
+  const int no = NO > 0 ? NO : A.n_other;
   const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
-  const int tile = blockIdx.y;
-  const int cw0 = tile * TW;
-  const int ka = EXACT ? KA : A.KA;
-  const int64_t e0 = A.bin_ptr[bin], e1 = A.bin_ptr[bin + 1];
-  const int s0 = A.seg_ptr[bin], s1 = A.seg_ptr[bin + 1];
-  const int nseg = s1 - s0;
-  float* rows = lds;                                        // nseg x TILEW
-  int* send = reinterpret_cast<int*>(lds + (size_t)nseg * TILEW);  // local end offset per segment
-  for (int i = threadIdx.x; i < nseg * TILEW; i += blockDim.x) rows[i] = 0.f;
-  for (int i = threadIdx.x; i < nseg; i += blockDim.x) send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
+  const int col0 = blockIdx.y * TTMV_TILE;
+  const int khat = A.khat;
+  const int64_t e0 = A.bin_ptr[bin];
+  const int E = (int)(A.bin_ptr[bin + 1] - e0);
+  const int s0 = A.seg_ptr[bin];
+  const int nseg = A.seg_ptr[bin + 1] - s0;
+  float* rows = lds;                                                   // nseg x TTMV_TILE
+  int* send = reinterpret_cast<int*>(rows + (size_t)nseg * TTMV_TILE);  // end of each segment in the bin
+  for (int i = threadIdx.x; i < nseg * TTMV_TILE; i += 256) rows[i] = 0.f;
+  for (int i = threadIdx.x; i < nseg; i += 256) send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
   __syncthreads();
 
-  const int E = (int)(e1 - e0);
-  const int q = (E + (int)blockDim.x - 1) / (int)blockDim.x;
-  const int lo = (int)threadIdx.x * q;
-  const int hi = min(lo + q, E);
-  if (lo < hi) {
-    int a = 0, b = nseg - 1;  // first segment whose end exceeds lo
-    while (a < b) {
-      int mid = (a + b) >> 1;
-      if (send[mid] > lo) b = mid; else a = mid + 1;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = uni(tid >> 6);
+  const int Q = (E + 3) >> 2;
+  const int cs = min(wave * Q, E), ce = min(cs + Q, E);
+  // the lane's columns: Kronecker digits of col = i + K_a (d_1 + K_1 (d_2 + ...))
+  int off[TTMV_CPL][7];
+  bool colok[TTMV_CPL];
+#pragma unroll
+  for (int u = 0; u < TTMV_CPL; ++u) {
+    const int col = col0 + lane + 64 * u;
+    colok[u] = col < khat;
+    int rest = colok[u] ? col : 0;
+    off[u][0] = rest % A.Kj[0];
+    rest /= A.Kj[0];
+    for (int j = 1; j < no; ++j) {
+      off[u][j] = rest % A.Kj[j];
+      rest /= A.Kj[j];
     }
-    int sg = a;
-    int end = send[sg];
-    float acc[TW][KA];
+  }
+  float acc[TTMV_CPL];
 #pragma unroll
-    for (int t = 0; t < TW; ++t)
+  for (int u = 0; u < TTMV_CPL; ++u) acc[u] = 0.f;
+  bool has_right = false;
+  int right_sg = 0;
+  if (cs < ce) {
+    int lo = 0, hi = nseg - 1;   // first segment ending after cs
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (uni(send[mid]) > cs) hi = mid; else lo = mid + 1;
+    }
+    int sg = lo;
+    int seg_lo = sg > 0 ? uni(send[sg - 1]) : 0;
+    int seg_hi = uni(send[sg]);
+    auto flush = [&]() __attribute__((always_inline)) {
+      const bool left = seg_lo < cs, right = seg_hi > ce;
+      float* row = rows + (size_t)sg * TTMV_TILE + lane;
+      if (right) {   // the quarter's last slice continues in a later quarter: kept in registers
+        has_right = true;
+        right_sg = sg;
+        return;
+      }
 #pragma unroll
-      for (int c = 0; c < KA; ++c) acc[t][c] = 0.f;
-
-    auto flush = [&](int s) {
-      float* row = rows + (size_t)s * TILEW;
-#pragma unroll
-      for (int t = 0; t < TW; ++t) {
-        if (cw0 + t < A.KW) {
-#pragma unroll
-          for (int c = 0; c < KA; ++c) {
-            if (EXACT || c < ka) atomicAdd(row + t * ka + c, acc[t][c]);
-            acc[t][c] = 0.f;
-          }
-        }
+      for (int u = 0; u < TTMV_CPL; ++u) {
+        if (left) row[64 * u] += acc[u];
+        else row[64 * u] = acc[u];
+        acc[u] = 0.f;
       }
     };
-
-    const float* __restrict__ Fa = A.F[0];
-    const int sa = A.fstride[0];
-    const int32_t* __restrict__ la = A.lay[0];
-    const float* __restrict__ vv = A.val;
-    for (int e = lo; e < hi; ++e) {
-      if (e == end) {
-        flush(sg);
-        ++sg;
-        end = send[sg];
-      }
-      const int64_t g = e0 + e;
-      const float v = vv[g];
-      float ar[KA];
-      if constexpr (EXACT) {
-        load_row4<KA>(Fa + (int64_t)la[g] * sa, ar);   // row stride >= KA rounded up to 4
-      } else {
-        const float* ap = Fa + (int64_t)la[g] * sa;
+    const float* __restrict__ vv = A.val + e0;
+    for (int g = cs; g < ce; g += 64) {
+      // coordinates and values of elements g .. g+63, one per lane
+      const int ge = min(g + lane, ce - 1);
+      const float vl = vv[ge];
+      int li[7];
 #pragma unroll
-        for (int c = 0; c < KA; ++c) ar[c] = (c < ka) ? ap[c] : 0.f;
-      }
+      for (int j = 0; j < (NO > 0 ? NO : 7); ++j)
+        if (j < no) li[j] = A.lay[j][e0 + ge];
+      const int cnt = min(64, ce - g);
+      for (int k0 = 0; k0 < cnt; k0 += TTMV_U) {
+        float p[TTMV_U][TTMV_CPL];
 #pragma unroll
-      for (int c = 0; c < KA; ++c) ar[c] *= v;
-      float w[TW];
-      if constexpr (MODE == 1) {
+        for (int q = 0; q < TTMV_U; ++q) {
+          const int k = min(k0 + q, cnt - 1);
+          const float v = __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, vl), k));
+          const int64_t ra = (int64_t)__builtin_amdgcn_readlane(li[0], k) * A.fstride[0];
 #pragma unroll
-        for (int t = 0; t < TW; ++t) w[t] = (t == 0) ? 1.f : 0.f;
-      } else if constexpr (MODE == 2) {
-        const float* wr = A.F[1] + (int64_t)A.lay[1][g] * A.fstride[1] + cw0;
-        if ((cw0 & 3) == 0 && cw0 + ((TW + 3) & ~3) <= A.fstride[1]) {
-          load_row4<TW>(wr, w);
-        } else {
+          for (int u = 0; u < TTMV_CPL; ++u) p[q][u] = v * A.F[0][ra + off[u][0]];
 #pragma unroll
-          for (int t = 0; t < TW; ++t) w[t] = (cw0 + t < A.KW) ? wr[t] : 0.f;
-        }
-      } else {
-        int64_t base[7];
-        for (int j = 1; j < A.n_other; ++j) base[j] = (int64_t)A.lay[j][g] * A.fstride[j];
+          for (int j = 1; j < (NO > 0 ? NO : 7); ++j) {
+            if (j < no) {
+              const int64_t rj = (int64_t)__builtin_amdgcn_readlane(li[j], k) * A.fstride[j];
 #pragma unroll
-        for (int t = 0; t < TW; ++t) {
-          const int cw = cw0 + t;
-          float p = 0.f;
-          if (cw < A.KW) {
-            p = 1.f;
-            for (int j = 1; j < A.n_other; ++j) p *= A.F[j][base[j] + (cw / A.div[j]) % A.Kj[j]];
+              for (int u = 0; u < TTMV_CPL; ++u) p[q][u] *= A.F[j][rj + off[u][j]];
+            }
           }
-          w[t] = p;
+        }
+#pragma unroll
+        for (int q = 0; q < TTMV_U; ++q) {
+          const int e = g + k0 + q;
+          if (k0 + q >= cnt) break;
+          if (e >= seg_hi) {   // a new slice starts at element e
+            flush();
+            ++sg;
+            seg_lo = seg_hi;
+            seg_hi = uni(send[sg]);
+          }
+#pragma unroll
+          for (int u = 0; u < TTMV_CPL; ++u) acc[u] += p[q][u];
         }
       }
-#pragma unroll
-      for (int t = 0; t < TW; ++t)
-#pragma unroll
-        for (int c = 0; c < KA; ++c) acc[t][c] = fmaf(ar[c], w[t], acc[t][c]);
     }
-    flush(sg);
+    flush();   // the quarter's last slice
   }
   __syncthreads();
-
-  // write the bin's rows: owned slices to Y, split slices to their partial slot
-  const int tilew = ka * TW;
-  const int col0 = ka * cw0;
-  for (int i = threadIdx.x; i < nseg * tilew; i += blockDim.x) {
-    const int s = i / tilew;
-    const int j = i - s * tilew;
-    const int col = col0 + j;
-    if (col >= A.khat) continue;
-    const float x = rows[(size_t)s * TILEW + j];
-    const int slot = A.seg_slot[s0 + s];
+  // rows of slices continued by a later quarter, added in wave order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w && has_right) {
+      float* row = rows + (size_t)right_sg * TTMV_TILE + lane;
+#pragma unroll
+      for (int u = 0; u < TTMV_CPL; ++u) row[64 * u] += acc[u];
+    }
+    __syncthreads();
+  }
+  // the bin's rows out: owned slices to Y, split slices to their partial slot
+  const int tw = min(TTMV_TILE, khat - col0);
+  for (int i = threadIdx.x; i < nseg * tw; i += 256) {
+    const int sgi = i / tw;
+    const int j = i - sgi * tw;
+    const float x = rows[(size_t)sgi * TTMV_TILE + j];
+    const int slot = A.seg_slot[s0 + sgi];
     if (slot < 0)
-      A.Y[(int64_t)A.seg_row[s0 + s] * A.khat + col] = x;
+      A.Y[(int64_t)A.seg_row[s0 + sgi] * khat + col0 + j] = x;
     else
-      A.partial[(int64_t)slot * A.khat + col] = x;
+      A.partial[(int64_t)slot * khat + col0 + j] = x;
   }
 }
 
@@ -224,8 +251,6 @@ __global__ __launch_bounds__(256) void k_ttm(TtmArgs A) {
 constexpr int TTM3_RING = 3;   // blocks of 16 elements with gathers in flight per wave
 constexpr int TTM4_RING = 3;   // the same for the four-mode kernel (three 16-byte loads per lane per block)
 
-__device__ __forceinline__ int uni(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
 // s_waitcnt immediate that waits for vector memory only (vmcnt 0; expcnt and
 // lgkmcnt at their maxima, gfx9 encoding)
 constexpr int kVmcnt0 = 0x0F70;
@@ -240,9 +265,17 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ float4 bf16x2_lo_hi(uint32_t x, uint32_t y) {
-  return make_float4(__uint_as_float(x << 16), __uint_as_float(x & 0xffff0000u), __uint_as_float(y << 16),
-                     __uint_as_float(y & 0xffff0000u));
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (finite inputs)
+__device__ __forceinline__ uint32_t bf16_bits(float f) {
+  const uint32_t b = __float_as_uint(f);
+  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
+}
+// four FP32 values as the four BF16 halves of an MFMA operand, in order
+__device__ __forceinline__ bf16x4_t bf16x4_of(float a, float b, float c, float d) {
+  const uint32_t lo = bf16_bits(a) | (bf16_bits(b) << 16), hi = bf16_bits(c) | (bf16_bits(d) << 16);
+  return __builtin_bit_cast(bf16x4_t, (uint64_t)lo | ((uint64_t)hi << 32));
 }
 
 // Three-mode TTM-chain on the matrix cores, one wave per Lite bin.
@@ -250,20 +283,24 @@ __device__ __forceinline__ float4 bf16x2_lo_hi(uint32_t x, uint32_t y) {
 // The bin's layout (coordinates of the two other modes and values) is staged
 // in LDS.  The wave streams it in blocks of 16 elements with a ring of
 // TTM3_RING blocks of gathers in flight: four lanes fetch one 64-byte factor
-// row with a 16-byte load, the block's F_a (times the value) and F_b rows go
-// through a 2 KB LDS tile into the MFMA operand layout, and each 4-element step
-// is one v_mfma_f32_16x16x4f32 accumulating (val F_a)^T F_b of the current
-// slice (a K_a x K_b block of its row of Y, column i + K_a j).  When a slice
+// row with a 16-byte load, and the block's F_a rows (times the value) and F_b
+// rows go through a 2 KB LDS tile into the MFMA operand layout.  When a slice
 // ends its row goes to the bin's LDS rows; at the end the rows are written to
 // Y (or to the partial slots of slices split across bins) with 16-byte stores.
 // All slices of a bin belong to its one wave: no barriers and no merging of
 // partial rows between waves.  The slice table (end, partial slot, row) is
 // held across the lanes, lane i for slice base + i, and read with readlane.
 //
-// BF: the factor rows are gathered from the BF16 copies (32-byte rows, two
-// lanes per row, lanes 0-31 for F_a and 32-63 for F_b) and widened to FP32
-// before the LDS tile; the contraction and the accumulation stay FP32.
-template <bool BF>
+// BFM = false: each 4-element step is one v_mfma_f32_16x16x4_f32
+// accumulating (val F_a)^T F_b of the current slice (segments are padded to
+// multiples of 4, so a step never straddles two slices).
+// BFM = true (the precision form): the operands are rounded once to BF16
+// (round to nearest even) and a block of 16 elements is one
+// v_mfma_f32_16x16x16_bf16 with FP32 accumulation: lane group q = l/16
+// supplies the block's four elements 4q .. 4q+3 (one padded quad, so one
+// slice).  A block whose quads belong to several slices issues one MFMA per
+// slice, the other lane groups' A operands zeroed.
+template <bool BFM>
 __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.KA, kb = A.KW;
@@ -321,68 +358,73 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
     }
     C = floatx4_t{0.f, 0.f, 0.f, 0.f};
   };
-  // Gather of block g.  FP32: lane l takes element g + l/4, 16-byte quarter
-  // l%4 of its F_a and F_b rows.  BF16: lane l takes element g + (l/2)%16,
-  // half l%2 of the F_a (l < 32) or F_b row.  All lanes load: the factor
-  // copies are zero beyond column K, so no predicate (a predicated load would
-  // make the in-flight count path dependent).
-  struct Blk { u32x4 x, y; float v; };
-  const uintptr_t hbase = reinterpret_cast<uintptr_t>(A.H[0]);
-  const uintptr_t hdiff = reinterpret_cast<uintptr_t>(A.H[1]) - hbase;
-  auto fetch = [&](int g, Blk& r) __attribute__((always_inline)) {
-    if constexpr (BF) {
-      const int e = g + ((lane >> 1) & 15);
-      const bool fa = lane < 32;
-      const int ix = fa ? sia[e] : sib[e];
-      r.v = fa ? sv[e] : 1.f;
-      // select a distance, not one of two pointers: a select of two
-      // argument loads becomes a per-lane load of the chosen pointer
-      const uintptr_t h = hbase + (fa ? 0 : hdiff) + 2 * (uintptr_t)(uint32_t)(ix * 16 + 8 * (lane & 1));
-      r.x = *reinterpret_cast<const __attribute__((address_space(1))) u32x4*>(h);
-    } else {
-      const int e = g + (lane >> 2);
-      const int ia = sia[e], ib = sib[e];
-      r.v = sv[e];
-      r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + 4 * (lane & 3)));
-      r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + 4 * (lane & 3)));
+  auto next_slice = [&]() __attribute__((always_inline)) {
+    ++sg;
+    if (sg - base == 64) {
+      base = sg;
+      load_segs(base);
     }
+    seg_hi = __builtin_amdgcn_readlane(v_end, sg - base);
+  };
+  // Gather of block g: lane l takes element g + l/4, 16-byte quarter l%4 of
+  // its F_a and F_b rows.  All lanes load: the factor copies are zero beyond
+  // column K, so no predicate (a predicated load would make the in-flight
+  // count path dependent).
+  struct Blk { u32x4 x, y; float v; };
+  auto fetch = [&](int g, Blk& r) __attribute__((always_inline)) {
+    const int e = g + (lane >> 2);
+    const int ia = sia[e], ib = sib[e];
+    r.v = sv[e];
+    r.x = *reinterpret_cast<const u32x4*>(A.F[0] + ((size_t)(uint32_t)ia * 16 + 4 * (lane & 3)));
+    r.y = *reinterpret_cast<const u32x4*>(A.F[1] + ((size_t)(uint32_t)ib * 16 + 4 * (lane & 3)));
   };
   auto consume = [&](int g, const Blk& r) __attribute__((always_inline)) {
     // the rows of the block into the tile: F_a (times val) at 0, F_b at 256
-    if constexpr (BF) {
-      const float4 w0 = bf16x2_lo_hi(r.x.x, r.x.y), w1 = bf16x2_lo_hi(r.x.z, r.x.w);
-      float4* t = reinterpret_cast<float4*>(tile + 8 * lane);
-      t[0] = make_float4(w0.x * r.v, w0.y * r.v, w0.z * r.v, w0.w * r.v);
-      t[1] = make_float4(w1.x * r.v, w1.y * r.v, w1.z * r.v, w1.w * r.v);
-    } else {
-      reinterpret_cast<float4*>(tile)[lane] =
-          make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
-                      __uint_as_float(r.x.w) * r.v);
-      reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
-          __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
-    }
+    reinterpret_cast<float4*>(tile)[lane] =
+        make_float4(__uint_as_float(r.x.x) * r.v, __uint_as_float(r.x.y) * r.v, __uint_as_float(r.x.z) * r.v,
+                    __uint_as_float(r.x.w) * r.v);
+    reinterpret_cast<float4*>(tile + 256)[lane] = make_float4(
+        __uint_as_float(r.y.x), __uint_as_float(r.y.y), __uint_as_float(r.y.z), __uint_as_float(r.y.w));
     wave_lds_sync();
-    // operand layout: step u, lane l reads element 4u + l/16, column l%16
-    float xa[4], xb[4];
+    if constexpr (!BFM) {
+      // operand layout: step u, lane l reads element 4u + l/16, column l%16
+      float xa[4], xb[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      xa[u] = tile[(4 * u + k) * 16 + cix];
-      xb[u] = tile[256 + (4 * u + k) * 16 + cix];
-    }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int gu = g + 4 * u;
-      if (gu >= E) break;
-      if (gu >= seg_hi) {  // a new slice starts at this step
-        flush();
-        ++sg;
-        if (sg - base == 64) {
-          base = sg;
-          load_segs(base);
-        }
-        seg_hi = __builtin_amdgcn_readlane(v_end, sg - base);
+      for (int u = 0; u < 4; ++u) {
+        xa[u] = tile[(4 * u + k) * 16 + cix];
+        xb[u] = tile[256 + (4 * u + k) * 16 + cix];
       }
-      C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int gu = g + 4 * u;
+        if (gu >= E) break;
+        if (gu >= seg_hi) {  // a new slice starts at this step
+          flush();
+          next_slice();
+        }
+        C = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], xb[u], C, 0, 0, 0);
+      }
+    } else {
+      // operand layout: lane l holds elements 4(l/16) .. +3 of the block, column l%16
+      const float* ta = tile + (4 * k) * 16 + cix;
+      const bf16x4_t xa = bf16x4_of(ta[0], ta[16], ta[32], ta[48]);
+      const bf16x4_t xb = bf16x4_of(ta[256], ta[256 + 16], ta[256 + 32], ta[256 + 48]);
+      const bf16x4_t zero = {0, 0, 0, 0};
+      // runs of quads in one slice: quads [q0, q) belong to slice sg
+      int q0 = 0;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int gq = g + 4 * q;
+        if (gq >= E) break;
+        if (gq >= seg_hi) {   // quad q starts a new slice: close the run before it
+          if (q > q0) C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(k >= q0 && k < q ? xa : zero, xb, C, 0, 0, 0);
+          flush();
+          next_slice();
+          q0 = q;
+        }
+      }
+      const int qend = min(4, (E - g) >> 2);
+      if (qend > q0) C = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(k >= q0 && k < qend ? xa : zero, xb, C, 0, 0, 0);
     }
     wave_lds_sync();   // the next block's write follows these reads
   };
@@ -400,7 +442,7 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
 #pragma unroll
     for (int d = 0; d < TTM3_RING; ++d) {
       const int gg = g + 16 * d;
-      consume(gg, ring[d]);
+      if (gg < E) consume(gg, ring[d]);
       // keep the refill behind the consumption of its slot: hoisted above it,
       // the refill takes fresh registers and the wait at the loop head
       // drains every load in flight
@@ -472,7 +514,12 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
 // A wave's slices that continue into a neighbouring wave keep their partial
 // rows in registers and are added to the bin's LDS rows in wave order after
 // the main loop (no atomics, deterministic).
-template <int NT>
+//
+// BFM (the precision form): the operands are rounded once to BF16 and each
+// block of 16 elements takes NT v_mfma_f32_16x16x16_bf16 per slice present in
+// it (lane group q supplies elements 4q .. 4q+3; other slices' lane groups get
+// a zero A operand), FP32 accumulation, as in the three-mode kernel.
+template <int NT, bool BFM>
 __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.Kj[0], kb = A.Kj[1], kbc = A.Kj[1] * A.Kj[2];
@@ -605,9 +652,9 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       const int ia = sia[e], ib = sib[e], ic = sic[e];
       r.v = sv[e];
       const uint32_t o = 4 * (lane & 3);
-      r.x = *reinterpret_cast<const u32x4*>(A.F[0] + (uint32_t)(ia * 16 + o));
-      r.y = *reinterpret_cast<const u32x4*>(A.F[1] + (uint32_t)(ib * 16 + o));
-      r.z = *reinterpret_cast<const u32x4*>(A.F[2] + (uint32_t)(ic * 16 + o));
+      r.x = *reinterpret_cast<const u32x4*>(A.F[0] + ((size_t)(uint32_t)ia * 16 + o));
+      r.y = *reinterpret_cast<const u32x4*>(A.F[1] + ((size_t)(uint32_t)ib * 16 + o));
+      r.z = *reinterpret_cast<const u32x4*>(A.F[2] + ((size_t)(uint32_t)ic * 16 + o));
     };
     auto consume = [&](int g, const Blk& r) __attribute__((always_inline)) {
       reinterpret_cast<float4*>(tile)[lane] =
@@ -616,23 +663,61 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       reinterpret_cast<u32x4*>(tile + 256)[lane] = r.y;
       reinterpret_cast<u32x4*>(tile + 512)[lane] = r.z;
       wave_lds_sync();
-      float xa[4];
+      if constexpr (!BFM) {
+        float xa[4];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) xa[u] = tile[(4 * u + k) * 16 + cix];
+        for (int u = 0; u < 4; ++u) xa[u] = tile[(4 * u + k) * 16 + cix];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int gu = g + 4 * u;
-        if (gu >= ce) break;
-        if (gu >= seg_hi) {
-          flush();
-          ++sg;
-          seg_lo = seg_hi;
-          seg_hi = uni(send[sg]);
+        for (int u = 0; u < 4; ++u) {
+          const int gu = g + 4 * u;
+          if (gu >= ce) break;
+          if (gu >= seg_hi) {
+            flush();
+            ++sg;
+            seg_lo = seg_hi;
+            seg_hi = uni(send[sg]);
+          }
+          const float* te = tile + (4 * u + k) * 16;
+#pragma unroll
+          for (int t = 0; t < NT; ++t)
+            C[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], te[pk[t] & 0xffffu] * te[pk[t] >> 16], C[t], 0, 0, 0);
         }
-        const float* te = tile + (4 * u + k) * 16;
+      } else {
+        // lane l holds elements 4(l/16) .. +3 of the block
+        const float* tq = tile + (4 * k) * 16;
+        const bf16x4_t xa = bf16x4_of(tq[cix], tq[16 + cix], tq[32 + cix], tq[48 + cix]);
+        bf16x4_t xb[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t)
-          C[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[u], te[pk[t] & 0xffffu] * te[pk[t] >> 16], C[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) {
+          const uint32_t ob = pk[t] & 0xffffu, oc = pk[t] >> 16;
+          xb[t] = bf16x4_of(tq[ob] * tq[oc], tq[16 + ob] * tq[16 + oc], tq[32 + ob] * tq[32 + oc],
+                            tq[48 + ob] * tq[48 + oc]);
+        }
+        const bf16x4_t zero = {0, 0, 0, 0};
+        int q0 = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int gq = g + 4 * q;
+          if (gq >= ce) break;
+          if (gq >= seg_hi) {   // quad q starts a new slice: close the run before it
+            if (q > q0) {
+              const bf16x4_t a = k >= q0 && k < q ? xa : zero;
+#pragma unroll
+              for (int t = 0; t < NT; ++t) C[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb[t], C[t], 0, 0, 0);
+            }
+            flush();
+            ++sg;
+            seg_lo = seg_hi;
+            seg_hi = uni(send[sg]);
+            q0 = q;
+          }
+        }
+        const int qend = min(4, (ce - g) >> 2);
+        if (qend > q0) {
+          const bf16x4_t a = k >= q0 && k < qend ? xa : zero;
+#pragma unroll
+          for (int t = 0; t < NT; ++t) C[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb[t], C[t], 0, 0, 0);
+        }
       }
       wave_lds_sync();   // the next block's write follows these reads
     };
@@ -719,32 +804,6 @@ __global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __re
 
 // ---- dispatch -----------------------------------------------------------------------------------
 
-struct TtmShape {
-  int KA, TW, ntiles, mode;
-  bool exact;
-};
-
-static TtmShape ttm_shape(int N, const int32_t* K, int n) {
-  TtmShape s{};
-  int first = (n == 0) ? 1 : 0;
-  int KA = K[first];
-  int KW = 1;
-  for (int j = 0; j < N; ++j)
-    if (j != n && j != first) KW *= K[j];
-  s.mode = (N == 2) ? 1 : (N == 3 ? 2 : 3);
-  s.KA = KA;
-  // exact instantiations for the common ranks, bounded ones otherwise
-  if (s.mode == 2 && KA == 10 && KW == 10) { s.TW = 10; s.exact = true; }
-  else if (s.mode == 2 && KA == 5 && KW == 5) { s.TW = 5; s.exact = true; }
-  else if (s.mode == 2 && KA == 16 && KW == 16) { s.TW = 8; s.exact = true; }
-  else if (s.mode == 3 && KA == 10) { s.TW = 10; s.exact = true; }
-  else if (s.mode == 1) { s.TW = 1; s.exact = false; }
-  else if (KA <= 16) { s.TW = 8; s.exact = false; }
-  else { s.TW = 4; s.exact = false; }
-  s.ntiles = (s.mode == 1) ? 1 : (int)ceil_div(KW, s.TW);
-  return s;
-}
-
 // Three-mode tensors with both remaining ranks <= 16 and 16-float factor rows
 // take the matrix-core kernel.
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp) {
@@ -763,19 +822,16 @@ bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp) {
   return true;
 }
 
+// Columns of Y a bin keeps in LDS per launch: whole rows for the matrix-core
+// kernels, one tile of TTMV_TILE columns for the vector-ALU kernel.
 int ttm_tile_width(int N, const int32_t* K, int n) {
-  TtmShape s = ttm_shape(N, K, n);
   int kp16[8];
   for (int j = 0; j < N; ++j) kp16[j] = K[j] <= 16 ? 16 : 0;
-  // the matrix-core kernels keep whole rows of Y in LDS
-  if (ttm_uses_mfma(N, K, n, kp16) || ttm_uses_mfma4(N, K, n, kp16)) {
-    int kh = 1;
-    for (int j = 0; j < N; ++j)
-      if (j != n) kh *= K[j];
-    return kh;
-  }
-  int kmax = s.exact ? s.KA : (s.mode == 1 ? 32 : (s.KA <= 16 ? 16 : 32));
-  return kmax * s.TW;
+  int kh = 1;
+  for (int j = 0; j < N; ++j)
+    if (j != n) kh *= K[j];
+  if (ttm_uses_mfma(N, K, n, kp16) || ttm_uses_mfma4(N, K, n, kp16)) return kh;
+  return TTMV_TILE;
 }
 
 // Default elements per Lite bin for the kernel mode n takes: the one-wave
@@ -804,21 +860,15 @@ int ttm_rows_cap(Ctx* c, int64_t tile_w) {
   return (int)cap;
 }
 
-template <int KA, int TW, int MODE, bool EXACT>
-static void launch_ttm(Ctx* c, const TtmArgs& a, const ModePlan& pl, int ntiles, int tilew_alloc) {
-  size_t lds = (size_t)pl.R_max * (4 * (size_t)tilew_alloc + 4);
-  if (lds == 0) lds = 4;
-  dim3 grid((unsigned)pl.P, (unsigned)ntiles);
-  hipLaunchKernelGGL((k_ttm<KA, TW, MODE, EXACT>), grid, dim3(256), lds, c->stream, a);
-  TK_CHECK_LAUNCH();
-}
-
 // TTM-chain of the elements of plan `pl` along mode n with FP32 factor copies
 // F32[j] (row stride kp[j]) of every mode j != n; values are the plan's layout values.
+__global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
+
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y, const uint16_t* const* H16) {
-  TtmShape s = ttm_shape(N, K, n);
-  TK_REQUIRE(s.KA <= 32, TK_ERR_UNSUPPORTED, "rank of the first remaining mode above 32");
+             const float* lay_val, int64_t m, float* Y, bool bf16, float* partial) {
   TtmArgs a{};
   a.bin_ptr = pl.bin_pptr.as<int64_t>();
   a.seg_ptr = pl.seg_ptr.as<int32_t>();
@@ -830,32 +880,38 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     if (j == n) continue;
     a.lay[no] = pl.lay_idx[no].as<int32_t>();
     a.F[no] = F32[j];
-    a.H[no] = H16 ? H16[j] : nullptr;
     a.fstride[no] = kp[j];
     a.Kj[no] = K[j];
     if (no >= 1) { a.div[no] = prod; prod *= K[j]; }
     ++no;
   }
   a.n_other = no;
-  a.KA = s.KA;
-  a.KW = (s.mode == 1) ? 1 : prod;
+  a.KA = a.Kj[0];
+  a.KW = prod;
   a.khat = (int)pl.khat;
   a.val = lay_val;
   a.Y = Y;
-  ensure(c, c->partial, sizeof(float) * (size_t)std::max<int64_t>(pl.fix_rows, 1) * (size_t)pl.khat);
-  a.partial = c->partial.as<float>();
+  if (!partial) {
+    ensure(c, c->partial, sizeof(float) * (size_t)std::max<int64_t>(pl.fix_rows, 1) * (size_t)pl.khat);
+    partial = c->partial.as<float>();
+  }
+  a.partial = partial;
   a.P = pl.P;
   if (m == 0) {
-    if (pl.L_nz > 0) TK_HIP(hipMemsetAsync(Y, 0, sizeof(float) * (size_t)pl.L_nz * pl.khat, c->stream));
+    // a fill kernel, not a memset node, so the call can be captured into a graph
+    const int64_t ny = pl.L_nz * pl.khat;
+    if (ny > 0) {
+      hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(ny, 256, 4096)), dim3(256), 0, c->stream, Y, ny);
+      TK_CHECK_LAUNCH();
+    }
     return;
   }
-  const int tw = ttm_tile_width(N, K, n);
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
   if (ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const size_t lds = 12 * (size_t)Epad + sizeof(float) * 512 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
-    if (H16)
+    if (bf16)
       hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
     else
       hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
@@ -868,8 +924,13 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
     const dim3 g((unsigned)pl.P), b(256);
     switch ((a.Kj[1] * a.Kj[2] + 15) / 16) {
-#define TK_TTM4_CASE(NT) \
-      case NT: hipLaunchKernelGGL(k_ttm4_mfma<NT>, g, b, lds, c->stream, a, Epad, nseg_pad); break;
+#define TK_TTM4_CASE(NT)                                                                         \
+      case NT:                                                                                   \
+        if (bf16)                                                                                \
+          hipLaunchKernelGGL((k_ttm4_mfma<NT, true>), g, b, lds, c->stream, a, Epad, nseg_pad);  \
+        else                                                                                     \
+          hipLaunchKernelGGL((k_ttm4_mfma<NT, false>), g, b, lds, c->stream, a, Epad, nseg_pad); \
+        break;
       TK_TTM4_CASE(1) TK_TTM4_CASE(2) TK_TTM4_CASE(3) TK_TTM4_CASE(4) TK_TTM4_CASE(5) TK_TTM4_CASE(6)
       TK_TTM4_CASE(7) TK_TTM4_CASE(8) TK_TTM4_CASE(9) TK_TTM4_CASE(10) TK_TTM4_CASE(11) TK_TTM4_CASE(12)
       TK_TTM4_CASE(13) TK_TTM4_CASE(14) TK_TTM4_CASE(15) TK_TTM4_CASE(16)
@@ -877,24 +938,22 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
       default: fail(TK_ERR_UNSUPPORTED, "four-mode TTM: rank above 16");
     }
     TK_CHECK_LAUNCH();
-  } else if (s.exact) {
-    if (s.mode == 2 && s.KA == 10) launch_ttm<10, 10, 2, true>(c, a, pl, s.ntiles, tw);
-    else if (s.mode == 2 && s.KA == 5) launch_ttm<5, 5, 2, true>(c, a, pl, s.ntiles, tw);
-    else if (s.mode == 2 && s.KA == 16) launch_ttm<16, 8, 2, true>(c, a, pl, s.ntiles, tw);
-    else launch_ttm<10, 10, 3, true>(c, a, pl, s.ntiles, tw);
-  } else if (s.mode == 1) {
-    launch_ttm<32, 1, 1, false>(c, a, pl, s.ntiles, tw);
-  } else if (s.KA <= 16) {
-    if (s.mode == 2) launch_ttm<16, 8, 2, false>(c, a, pl, s.ntiles, tw);
-    else launch_ttm<16, 8, 3, false>(c, a, pl, s.ntiles, tw);
   } else {
-    if (s.mode == 2) launch_ttm<32, 4, 2, false>(c, a, pl, s.ntiles, tw);
-    else launch_ttm<32, 4, 3, false>(c, a, pl, s.ntiles, tw);
+    const size_t lds = (size_t)pl.R_max * (sizeof(float) * TTMV_TILE + sizeof(int)) + 4;
+    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
+    const dim3 g((unsigned)pl.P, (unsigned)ceil_div(pl.khat, TTMV_TILE)), b(256);
+    switch (no) {
+      case 1: hipLaunchKernelGGL(k_ttm_cols<1>, g, b, lds, c->stream, a); break;
+      case 2: hipLaunchKernelGGL(k_ttm_cols<2>, g, b, lds, c->stream, a); break;
+      case 3: hipLaunchKernelGGL(k_ttm_cols<3>, g, b, lds, c->stream, a); break;
+      default: hipLaunchKernelGGL(k_ttm_cols<0>, g, b, lds, c->stream, a); break;
+    }
+    TK_CHECK_LAUNCH();
   }
   if (c->ev_ttm[1]) TK_HIP(hipEventRecord(c->ev_ttm[1], c->stream));
   if (pl.n_bad > 0) {
     const int thr = pl.khat > 128 ? 256 : 128;
-    float* buf = c->partial.as<float>();
+    float* buf = partial;
     int64_t first = pl.n_slots, off = 0;
     for (int64_t nl : pl.fix_n) {
       const int32_t* lohi = pl.fix_lohi.as<int32_t>() + off;
@@ -912,16 +971,12 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
 
 // bf16: gather the BF16 factor copies (precision form); taken only where the
 // matrix-core kernel runs and every other factor's BF16 row stride is 16.
-void ttm_chain(Ctx* c, int n, float* Y, bool bf16) {
+// bf16: the precision form's BF16 Kronecker tiles on the matrix cores (where a
+// matrix-core kernel runs; other shapes stay FP32).
+void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial) {
   const float* F[8];
-  const uint16_t* H[8];
-  bool bf_ok = bf16 && ttm_uses_mfma(c->N, c->K, n, c->kp32);
-  for (int j = 0; j < c->N; ++j) {
-    F[j] = c->F32[j].as<float>();
-    H[j] = c->F16[j].as<uint16_t>();
-    if (j != n && c->kp16[j] != 16) bf_ok = false;
-  }
-  ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y, bf_ok ? H : nullptr);
+  for (int j = 0; j < c->N; ++j) F[j] = c->F32[j].as<float>();
+  ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y, bf16, partial);
 }
 
 }  // namespace tk

@@ -50,8 +50,14 @@ def _L():
             lib.synth_uniform_idx.argtypes = [u64, u64, i64, i64, p]
             lib.synth_zipf_idx.argtypes = [u64, u64, ctypes.c_double, i64, p, i64, p]
             lib.synth_planted_values.argtypes = [ctypes.c_int, p, p, p, i64, p, p]
+            lib.synth_zipf_table.argtypes = [ctypes.c_double, i64, p]
+            lib.synth_zipf_guide.argtypes = [p, i64, ctypes.c_int, p]
+            lib.synth_zipf_idx_range.argtypes = [u64, u64, p, p, ctypes.c_int, i64, p, i64, i64, p]
+            lib.synth_lognormal_f32_range.argtypes = [u64, u64, i64, i64, p]
             for f in (lib.synth_u01, lib.synth_normal, lib.synth_lognormal_f32, lib.synth_uniform_f32,
-                      lib.synth_perm, lib.synth_uniform_idx, lib.synth_zipf_idx, lib.synth_planted_values):
+                      lib.synth_perm, lib.synth_uniform_idx, lib.synth_zipf_idx, lib.synth_planted_values,
+                      lib.synth_zipf_table, lib.synth_zipf_guide, lib.synth_zipf_idx_range,
+                      lib.synth_lognormal_f32_range):
                 f.restype = None
             _lib = lib
     return _lib
@@ -107,7 +113,8 @@ def uniform_idx(seed: int, stream: int, L: int, n: int) -> np.ndarray:
     return out
 
 
-def zipf_idx(seed: int, stream: int, s: float, L: int, n: int, perm: np.ndarray | None = None) -> np.ndarray:
+def zipf_idx_plain(seed: int, stream: int, s: float, L: int, n: int, perm: np.ndarray | None = None) -> np.ndarray:
+    """Zipf draws by the plain inverse-CDF binary search over the whole table."""
     if perm is None:
         perm = permutation(seed, S_PERM + stream, L)
     perm = np.ascontiguousarray(perm, dtype=np.int32)
@@ -115,6 +122,46 @@ def zipf_idx(seed: int, stream: int, s: float, L: int, n: int, perm: np.ndarray 
     out = np.empty(n, np.int32)
     _L().synth_zipf_idx(seed, stream, float(s), L, _ptr(perm), n, _ptr(out))
     return out
+
+
+GUIDE_LOG2 = 20   # buckets of the guided Zipf search
+
+
+class ZipfSampler:
+    """Zipf(s) draws over a permuted [0, L) in any range of the counter: the
+    inverse-CDF search narrowed by a guide table (same draws as
+    zipf_idx_plain, bit for bit)."""
+
+    def __init__(self, seed: int, stream: int, s: float, L: int, perm: np.ndarray | None = None):
+        self.seed, self.stream, self.L = int(seed), int(stream), int(L)
+        if perm is None:
+            perm = permutation(seed, S_PERM + stream, L)
+        self.perm = np.ascontiguousarray(perm, dtype=np.int32)
+        assert self.perm.shape == (L,)
+        self.table = np.empty(L, np.float64)
+        _L().synth_zipf_table(float(s), L, _ptr(self.table))
+        self.guide = np.empty((1 << GUIDE_LOG2) + 1, np.int64)
+        _L().synth_zipf_guide(_ptr(self.table), L, GUIDE_LOG2, _ptr(self.guide))
+
+    def draw(self, start: int, n: int, out: np.ndarray | None = None) -> np.ndarray:
+        if out is None:
+            out = np.empty(n, np.int32)
+        assert out.dtype == np.int32 and out.flags["C_CONTIGUOUS"] and out.shape[0] >= n
+        _L().synth_zipf_idx_range(self.seed, self.stream, _ptr(self.table), _ptr(self.guide), GUIDE_LOG2, self.L,
+                                  _ptr(self.perm), int(start), int(n), _ptr(out))
+        return out[:n]
+
+
+def zipf_idx(seed: int, stream: int, s: float, L: int, n: int, perm: np.ndarray | None = None) -> np.ndarray:
+    return ZipfSampler(seed, stream, s, L, perm).draw(0, n)
+
+
+def lognormal_f32_range(seed: int, stream: int, start: int, n: int, out: np.ndarray | None = None) -> np.ndarray:
+    if out is None:
+        out = np.empty(n, np.float32)
+    assert out.dtype == np.float32 and out.flags["C_CONTIGUOUS"] and out.shape[0] >= n
+    _L().synth_lognormal_f32_range(seed, stream, int(start), int(n), _ptr(out))
+    return out[:n]
 
 
 def gaussian_factors(seed: int, dims, ranks):
@@ -215,6 +262,43 @@ def make_workload(name: str, scale: float = 1.0, share: int = 1):
     ranks = tuple(min(k, L) for k, L in zip(w["ranks"], dims))
     F0 = orthonormal_init(9494 + c, dims, ranks)
     return dict(dims=dims, idx=idx, vals=vals, ranks=ranks, F0=F0, iters=w.get("iters", 1))
+
+
+class WorkloadStream:
+    """A named Zipf workload drawn in consecutive chunks of the counter range
+    (the same draws as make_workload, chunk by chunk), for inputs too large to
+    hold at once.  chunk(start, n) fills caller buffers (idx: N int32 arrays,
+    vals: float32) with draws start .. start+n-1."""
+
+    def __init__(self, name: str, scale: float = 1.0, share: int = 1):
+        w = dict(WORKLOADS[name])
+        if w["dist"] != "zipf" or w["values"] != "lognormal":
+            raise ValueError("streamed workloads are the Zipf / lognormal ones")
+        c = w["number"]
+        self.name = name
+        self.seed = 1804 + c
+        self.dims = tuple(max(2, int(round(L * scale))) for L in w["dims"])
+        self.nnz = max(1, int(round(w["nnz"] * scale)) // max(1, int(share)))
+        self.ranks = tuple(min(k, L) for k, L in zip(w["ranks"], self.dims))
+        self.zipf = w["zipf"]
+        self.iters = w.get("iters", 1)
+        self.samplers = [ZipfSampler(self.seed, S_IDX + n, float(self.zipf[n]), int(L))
+                         for n, L in enumerate(self.dims)]
+        self.factor_seed = 9494 + c
+
+    def chunk(self, start: int, n: int, idx=None, vals=None):
+        N = len(self.dims)
+        if idx is None:
+            idx = [np.empty(n, np.int32) for _ in range(N)]
+        if vals is None:
+            vals = np.empty(n, np.float32)
+        for j in range(N):
+            self.samplers[j].draw(start, n, idx[j])
+        lognormal_f32_range(self.seed, S_VAL, start, n, vals)
+        return [a[:n] for a in idx], vals[:n]
+
+    def initial_factors(self):
+        return orthonormal_init(self.factor_seed, self.dims, self.ranks)
 
 
 def make_completion(dims, n_obs, ranks, zipf=(1.0, 1.0, 1.0), noise=0.01, seed=4949, with_values=True):

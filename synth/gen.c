@@ -114,6 +114,57 @@ void synth_zipf_idx(uint64_t seed, uint64_t stream, double s, int64_t L,
   free(c);
 }
 
+/* The same Zipf draws, faster, in ranges of the counter.
+ *
+ * synth_zipf_table writes the prefix table c (built exactly as above).
+ * synth_zipf_guide writes, for the 2^g buckets of the 53-bit uniform u,
+ * guide[b] = first j with c[j] > fl(b 2^-g * total) (L - 1 if none), for
+ * b = 0 .. 2^g.  A draw u in bucket b has fl(u * total) between the products
+ * of its bucket's two ends (rounded multiplication is monotonic), so its
+ * answer lies in [guide[b], guide[b+1]]: the binary search over that range
+ * returns exactly the plain search's answer.
+ * synth_zipf_idx_range draws counters start .. start+n-1. */
+void synth_zipf_table(double s, int64_t L, double* c) {
+  double acc = 0.0;
+  for (int64_t j = 0; j < L; ++j) { acc += pow((double)(j + 1), -s); c[j] = acc; }
+}
+
+static int64_t first_above(const double* c, int64_t lo, int64_t hi, double x) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (c[mid] > x) hi = mid; else lo = mid + 1;
+  }
+  return lo;
+}
+
+void synth_zipf_guide(const double* c, int64_t L, int g, int64_t* guide) {
+  const double total = c[L - 1];
+  const int64_t B = (int64_t)1 << g;
+  const double scale = 1.0 / (double)B;
+#pragma omp parallel for schedule(static)
+  for (int64_t b = 0; b <= B; ++b) guide[b] = first_above(c, 0, L - 1, ((double)b * scale) * total);
+}
+
+void synth_zipf_idx_range(uint64_t seed, uint64_t stream, const double* c, const int64_t* guide, int g, int64_t L,
+                          const int32_t* perm, int64_t start, int64_t n, int32_t* out) {
+  const double total = c[L - 1];
+  const uint64_t k = stream_key(seed, stream);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    const uint64_t r = draw(k, (uint64_t)(start + i));
+    const double x = u01(r) * total;
+    const int64_t b = (int64_t)((r >> 11) >> (53 - g));
+    out[i] = perm[first_above(c, guide[b], guide[b + 1], x)];
+  }
+}
+
+/* Values lognormal(0, 1) rounded to float, counters start .. start+n-1. */
+void synth_lognormal_f32_range(uint64_t seed, uint64_t stream, int64_t start, int64_t n, float* out) {
+  uint64_t k = stream_key(seed, stream);
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) out[i] = (float)exp(normal_at(k, (uint64_t)(start + i)));
+}
+
 /* Planted Tucker model value at each observation:
  *   v_e = sum over core entries c of G[c] * prod_n F_n[idx_n[e], c_n]
  * with G stored first index fastest and F_n row-major (L_n x K_n).

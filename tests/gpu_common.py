@@ -30,3 +30,30 @@ def oracle_Y(idx_c, vals_c, F, n, dims):
     Y = ttm.ttm_chain(idx_c, vals_c, F, n, dims)
     rows = ttm.nonempty_slices(idx_c[n], dims[n])
     return Y[rows], rows
+
+
+U32 = 2.0 ** -24   # FP32 unit roundoff
+
+
+def factor_tolerance(sv, K, tol=1e-5):
+    """Allowed projector distance of a GPU factor from the oracle's.
+
+    Where the oracle's spectrum separates the leading K-subspace
+    (sigma_K / sigma_{K+1} - 1 >= 1e-3) the bar is tol.  Below that, the
+    sin-theta theorem bounds the subspace error of an eigensolve of a Gram
+    matrix with FP32 perturbation ||E|| <= c u sigma_1^2 by
+    sqrt(2) c u sigma_1^2 / (sigma_K^2 - sigma_{K+1}^2); c = 4 covers the FP32
+    rounding of Y and of the Gram's accumulation."""
+    if len(sv) <= K or sv[K] == 0.0 or sv[K - 1] / sv[K] - 1.0 >= 1e-3:
+        return tol, 1.0
+    cond = sv[0] ** 2 / max(sv[K - 1] ** 2 - sv[K] ** 2, 1e-300)
+    return max(tol, np.sqrt(2.0) * 4.0 * U32 * cond), cond
+
+
+def fit_noise(fit):
+    """Rounding noise of the fit 1 - sqrt(||T||^2 - ||G||^2)/||T|| when
+    ||G||^2 carries a relative FP32 error of c u (c = 4, from Y and the core's
+    accumulation): delta fit <= c u / (2 (1 - fit)) for ||G|| <= ||T||, and a
+    difference of two such values at most twice that.  Fits that should not
+    decrease (Gauss-Seidel HOOI) are allowed to drop by this much."""
+    return max(1e-6, 4.0 * U32 / max(1.0 - fit, 1e-12))

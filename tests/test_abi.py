@@ -44,11 +44,14 @@ def test_status_strings_and_default_options():
 
 def test_null_context_is_rejected():
     lib, L = _lib()
-    assert lib.tk_load_coo(None, 3, None, 0, None, None, 0) == 1
+    assert lib.tk_load_coo(None, 3, None, 0, None, None, 0, 0) == 1
+    assert lib.tk_load_coo_begin(None, 3, None, 0, 0) == 1
+    assert lib.tk_load_coo_append(None, 0, None, None, 0) == 1
+    assert lib.tk_load_coo_end(None) == 1
     assert lib.tk_set_ranks(None, None) == 1
     assert lib.tk_hooi_iterate(None, 1, None) == 1
     assert lib.tk_ttm_chain(None, 0, None, None, 0) == 1
-    assert lib.tk_create(0, None, None) == 1
+    assert lib.tk_create(0, None, None, None) == 1
 
 
 def test_create_without_device_reports_device_error():
@@ -57,7 +60,7 @@ def test_create_without_device_reports_device_error():
         pytest.skip("a GPU is present")
     lib, L = _lib()
     h = ctypes.c_void_p()
-    assert lib.tk_create(0, None, ctypes.byref(h)) == 4
+    assert lib.tk_create(0, None, None, ctypes.byref(h)) == 4
     assert h.value is None
 
 

@@ -15,7 +15,7 @@ import pytest
 
 import synth
 from oracle import lite, ttm
-from tests.gpu_common import rel_fro
+from tests.gpu_common import fit_noise, rel_fro
 
 pytestmark = pytest.mark.gpu
 
@@ -117,16 +117,16 @@ def test_fullsize_hooi_properties(c2):
             ctx.set_factor(n, np.ascontiguousarray(F))
         return ctx.hooi_iterate(iters)
 
-    fits = run("fp32", 3)
+    fits = run("fp32", 6)
     for a, b in zip(fits, fits[1:]):
-        assert b >= a - 1e-6
+        assert b >= a - fit_noise(a)
     for n in range(3):
         F = ctx.get_factor(n)
         np.testing.assert_allclose(F.T @ F, np.eye(w["ranks"][n]), atol=1e-12)
     _, fit = ctx.core()
     assert abs(fit - fits[-1]) <= 1e-12
-    again = run("fp32", 3)
+    again = run("fp32", 6)
     assert again == fits                             # no atomics anywhere: bit-identical
-    bf = run("bf16", 3)
+    bf = run("bf16", 6)
     print("fits fp32", fits, "bf16-gram", bf, flush=True)
     assert abs(bf[-1] - fits[-1]) <= 1e-5

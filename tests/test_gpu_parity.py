@@ -8,7 +8,7 @@ import pytest
 
 import synth
 from oracle import coo, hooi, lite, ttm
-from tests.gpu_common import oracle_Y, rel_fro, uniform_tensor, zipf_tensor
+from tests.gpu_common import U32, factor_tolerance, fit_noise, oracle_Y, rel_fro, uniform_tensor, zipf_tensor
 
 pytestmark = pytest.mark.gpu
 
@@ -176,17 +176,26 @@ def test_ttm_empty_tensor(tk):
         assert Y.shape == (0, 4) and rows.shape == (0,)
 
 
-def test_ttm_deterministic(tk):
-    idx, vals = zipf_tensor((3000, 2000, 500), 100_000, s=1.4, seed=41)
+DET_CASES = ["zipf_k10_smallbins", "4mode_k10", "2mode", "5mode", "k32_vector", "4mode_k20", "deep_fixup"]
+
+
+@pytest.mark.parametrize("name", DET_CASES)
+def test_ttm_deterministic(tk, name):
+    """Reruns are bit-identical for every kernel family (three-mode and
+    four-mode matrix-core kernels, the vector-ALU kernel for two, five and
+    high-rank modes, and the fixup tree): no sum depends on timing."""
+    make, ranks, wg = TTM_CASES[name]
+    idx, vals = make()
     dims = tuple(int(i.max()) + 1 for i in idx)
-    ctx = _load(tk, idx, vals, dims, (10, 10, 10), wg_nnz_target=512)
-    F = synth.orthonormal_init(5, dims, (10, 10, 10))
-    for n in range(3):
+    print("case", name, dims, len(vals), ranks, flush=True)
+    ctx = _load(tk, idx, vals, dims, ranks, wg_nnz_target=wg)
+    F = synth.orthonormal_init(5, dims, ranks)
+    for n in range(len(dims)):
         ctx.set_factor(n, F[n])
-    for n in range(3):
+    for n in range(len(dims)):
         a, _ = ctx.ttm_chain(n)
         b, _ = ctx.ttm_chain(n)
-        assert rel_fro(a, b) <= 1e-6
+        np.testing.assert_array_equal(a, b)
 
 
 # ---- HOOI ---------------------------------------------------------------------------------------
@@ -196,6 +205,27 @@ def _last_sigmas(ic, vc, dims, ranks, o, n):
     qualify how well the leading K_n-subspace is determined."""
     Z = ttm.ttm_chain(ic, vc, o["factors"], n, dims)
     return np.linalg.svd(Z, compute_uv=False)
+
+
+def core_tolerance(svs, ranks, tol=1e-5):
+    """Allowed relative error of the sign-aligned core, or None where a
+    cluster inside the leading K singular values leaves the individual
+    columns (and so the core's entries) undetermined.  Each column k is
+    determined to about sqrt(2) c u sigma_1^2 / min_gap_k (sin-theta theorem
+    for one vector), with min_gap_k the distance of sigma_k^2 from its
+    neighbours."""
+    worst = tol
+    for sv, K in zip(svs, ranks):
+        s2 = np.asarray(sv[:K + 1], np.float64) ** 2
+        for k in range(min(K, len(s2))):
+            gaps = [s2[k - 1] - s2[k]] if k > 0 else []
+            if k + 1 < len(s2):
+                gaps.append(s2[k] - s2[k + 1])
+            g = min(gaps) if gaps else s2[0]
+            if g <= 1e-3 * s2[k]:
+                return None
+            worst = max(worst, np.sqrt(2.0) * 4.0 * U32 * s2[0] / g)
+    return worst
 
 
 def _hooi_compare(P, w, iters, tol_fit=1e-5, tol_proj=1e-5, sweep="gauss_seidel"):
@@ -209,23 +239,26 @@ def _hooi_compare(P, w, iters, tol_fit=1e-5, tol_proj=1e-5, sweep="gauss_seidel"
     print("fits gpu", fits, "oracle", o["fits"], flush=True)
     for a, b in zip(fits, o["fits"]):
         assert abs(a - b) <= tol_fit
+    svs = []
     for n in range(len(dims)):
         Fg = ctx.get_factor(n)
         np.testing.assert_allclose(Fg.T @ Fg, np.eye(ranks[n]), atol=1e-12)
-        # Gram-route subspace error ~ u * s_1^2 / (s_K^2 - s_{K+1}^2): the tolerance widens only
-        # where the oracle's own spectrum says the subspace is ill-conditioned
         K = ranks[n]
         d = hooi.projector_distance(Fg, o["factors"][n])
         sv = _last_sigmas(ic, vc, dims, ranks, o, n)
-        cond = sv[0] ** 2 / max(sv[K - 1] ** 2 - sv[K] ** 2, 1e-300) if len(sv) > K else 1.0
-        allowed = max(tol_proj, 6e-8 * 50 * cond)
+        svs.append(sv)
+        allowed, cond = factor_tolerance(sv, K, tol_proj)
         print(f"  mode {n}: projector distance {d:.3e} (allowed {allowed:.3e}, cond {cond:.3e})", flush=True)
-        if cond < 1e6:
-            assert d <= allowed
+        assert d <= allowed
     core, fit = ctx.core()
     assert abs(fit - o["fits"][-1]) <= tol_fit
     Go = o["core"]
-    # compare the core up to the factors' column signs
+    # rotation-invariant: the singular values of every unfolding of the core
+    for n in range(len(dims)):
+        sg_g = np.linalg.svd(np.moveaxis(core, n, 0).reshape(ranks[n], -1), compute_uv=False)
+        sg_o = np.linalg.svd(np.moveaxis(Go, n, 0).reshape(ranks[n], -1), compute_uv=False)
+        assert rel_fro(sg_g, sg_o) <= 1e-5, n
+    # entrywise, up to the factors' column signs, where the columns are determined
     Fs = [ctx.get_factor(n) for n in range(len(dims))]
     sg = [np.sign(np.sum(Fs[n] * o["factors"][n], axis=0)) for n in range(len(dims))]
     Ga = core.copy()
@@ -233,7 +266,11 @@ def _hooi_compare(P, w, iters, tol_fit=1e-5, tol_proj=1e-5, sweep="gauss_seidel"
         shape = [1] * len(dims)
         shape[n] = ranks[n]
         Ga = Ga * sg[n].reshape(shape)
-    assert rel_fro(Ga, Go) <= 1e-4
+    tol_core = core_tolerance(svs, ranks)
+    err_core = rel_fro(Ga, Go)
+    print(f"  core: rel err {err_core:.3e} (allowed {tol_core})", flush=True)
+    if tol_core is not None:
+        assert err_core <= tol_core
     return ctx, fits, o
 
 
@@ -317,7 +354,7 @@ def test_hooi_fit_non_decreasing_and_timings(tk):
         ctx.set_factor(n, np.ascontiguousarray(F))
     fits = ctx.hooi_iterate(4)
     for a, b in zip(fits, fits[1:]):
-        assert b >= a - 1e-6
+        assert b >= a - fit_noise(a)
     t = ctx.timings()
     assert set(t) >= {"gram", "eig", "factor", "core"}
     assert all(f"ttm[{n}]" in t and f"ttm_kernel[{n}]" in t for n in range(3))

@@ -153,3 +153,49 @@ def test_choose_bins_bounds_rows():
         P = lite.choose_bins(m, Lnz, wg, cap)
         assert -(-Lnz // P) + 2 <= cap
         assert -(-m // P) <= wg or P >= -(-m // wg)
+
+
+# ---- the C++ Lite (oracle/lite_seq.cpp) ---------------------------------------------------------
+
+def _cpp_equals_python(sizes, P):
+    from oracle import cpp
+    res = lite.lite(sizes, P)
+    st, sb, ss, sc, bad = cpp.lite(np.asarray(sizes, np.int64), P)
+    segs = [(p, s, c, 1 if len(res.pieces[s]) > 1 else 0) for p in range(P) for s, c in res.bin_slices[p]]
+    segs = np.array(segs, np.int64).reshape(-1, 4)
+    np.testing.assert_array_equal(sb, segs[:, 0])
+    np.testing.assert_array_equal(ss, segs[:, 1])
+    np.testing.assert_array_equal(sc, segs[:, 2])
+    np.testing.assert_array_equal(bad, segs[:, 3])
+    for k in ("P", "limit", "m", "L_nonempty", "n_stage1", "E_max", "R_sum", "R_max", "n_bad"):
+        assert st[k] == res.stats[k], k
+
+
+def test_cpp_lite_worked_example(golden_dir):
+    """The figure's ten slices over five bins, as in the Python oracle."""
+    import json
+    g = json.load(open(os.path.join(golden_dir, "lite_fig_bins.json")))
+    _cpp_equals_python(g["printed"]["sorted_sizes"], g["printed"]["P"])
+    from oracle import cpp
+    st, *_ = cpp.lite(np.asarray(g["printed"]["sorted_sizes"], np.int64), g["printed"]["P"])
+    dv = g["derived_by_hand_from_the_pseudocode"]
+    assert st["R_sum"] == dv["R_sum"] and st["R_max"] == dv["R_max"] and st["n_bad"] == dv["n_bad"]
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.lists(st.integers(min_value=0, max_value=60), min_size=1, max_size=80),
+       st.integers(min_value=1, max_value=40))
+def test_cpp_lite_equals_python_random(sizes, P):
+    _cpp_equals_python(sizes, P)
+
+
+@pytest.mark.parametrize("sizes,P", [([0, 0, 0], 3), ([100], 7), ([1] * 50, 64), ([5, 0, 5, 0, 5], 1),
+                                     ([1, 2, 3, 1000, 4, 5], 13)])
+def test_cpp_lite_equals_python_degenerate(sizes, P):
+    _cpp_equals_python(sizes, P)
+
+
+def test_cpp_lite_zipf_sizes():
+    rng = np.random.default_rng(4)
+    sizes = (rng.zipf(1.3, 20_000) % 5000).tolist()
+    _cpp_equals_python(sizes, 997)

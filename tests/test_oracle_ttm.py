@@ -102,3 +102,49 @@ def test_coalesce_brute_force():
         np.testing.assert_array_equal(vc, vc2)
         assert nsq == pytest.approx(sum(float(np.float32(d[k])) ** 2 for k in keys), rel=1e-15, abs=0)
         assert nsq == nsq2
+
+
+# ---- the C++/OpenMP oracle (oracle/ttm_cpp.py) --------------------------------------------------
+
+@pytest.mark.parametrize("dims,ranks", [((4, 3, 5), (2, 3, 2)), ((5, 4, 3, 2), (2, 2, 3, 1)),
+                                        ((6, 7), (3, 2)), ((3, 4, 2, 3, 2), (2, 1, 2, 3, 2))])
+def test_cpp_oracle_equals_unfolding_times_kron(dims, ranks):
+    """The multi-threaded FP64 TTM-chain against the dense identity
+    Z_(n) = T_(n) (F_N kron ... kron F_1 without F_n), numpy.kron on the right."""
+    from oracle import cpp as ttm_cpp
+    rng = np.random.default_rng(3)
+    idx, vals, _ = _random_sparse(rng, dims, 50)
+    F = [rng.standard_normal((L, K)) for L, K in zip(dims, ranks)]
+    T = ttm.dense(idx, vals, dims)
+    for n in range(len(dims)):
+        kr = np.ones((1, 1))
+        for j in range(len(dims)):
+            if j != n:
+                kr = np.kron(F[j], kr)
+        expect = ttm.unfold(T, n) @ kr
+        np.testing.assert_allclose(ttm_cpp.ttm_chain(idx, vals, F, n, dims), expect, rtol=1e-12, atol=1e-12)
+
+
+@pytest.mark.parametrize("name", ["c1", "zipf"])
+def test_cpp_oracle_matches_numpy_oracle(name):
+    """On the c1 workload and a Zipf tensor with repeated coordinates: the full
+    Z_(n), and rows of chosen slices streamed in uneven batches (including an
+    empty one), equal the NumPy oracle's."""
+    import synth
+    from oracle import cpp as ttm_cpp
+    if name == "c1":
+        w = synth.make_workload("c1")
+        dims, idx, vals, F = w["dims"], w["idx"], w["vals"], w["F0"]
+    else:
+        dims = (900, 600, 300)
+        idx, vals = synth.make_tensor(dims, 80_000, "zipf", (1.2, 1.0, 1.4), "lognormal", seed=9)
+        F = synth.orthonormal_init(19, dims, (7, 5, 6))
+    for n in range(3):
+        Zo = ttm.ttm_chain(idx, vals, F, n, dims)
+        np.testing.assert_allclose(ttm_cpp.ttm_chain(idx, vals, F, n, dims), Zo, rtol=1e-12, atol=1e-12)
+        pick = np.unique(np.concatenate([np.argsort(np.bincount(idx[n], minlength=dims[n]))[-5:], [0, dims[n] - 1]]))
+        acc = ttm_cpp.RowAccumulator(F, n, dims[n], pick)
+        m = len(vals)
+        for a, b in [(0, m // 3), (m // 3, m // 3), (m // 3, m - 7), (m - 7, m)]:
+            acc.add([i[a:b] for i in idx], vals[a:b])
+        np.testing.assert_allclose(acc.rows, Zo[pick], rtol=1e-12, atol=1e-12)

@@ -45,3 +45,25 @@ def test_lognormal_moments():
     v = synth.lognormal_f32(1, 1, 200_000).astype(np.float64)
     lv = np.log(v)
     assert abs(lv.mean()) < 0.01 and abs(lv.std() - 1) < 0.01
+
+
+def test_guided_zipf_equals_plain_search():
+    """The guide table only narrows the search: every draw is the plain
+    inverse-CDF binary search's answer, whatever the exponent and range."""
+    for s, L in [(1.1, 1000), (0.8, 4_000_000), (1.5, 2_000_000), (1.2, 37), (0.7, 1)]:
+        a = synth.zipf_idx_plain(1809, 3, s, L, 300_000)
+        zs = synth.ZipfSampler(1809, 3, s, L)
+        np.testing.assert_array_equal(zs.draw(0, 300_000), a)
+        np.testing.assert_array_equal(np.concatenate([zs.draw(0, 123_457), zs.draw(123_457, 176_543)]), a)
+
+
+def test_workload_stream_chunks_equal_whole_draws():
+    w = synth.make_workload("c2", scale=0.001)
+    st = synth.WorkloadStream("c2", scale=0.001)
+    assert st.dims == w["dims"] and st.nnz == len(w["vals"]) and st.ranks == w["ranks"]
+    parts = [st.chunk(a, min(30_000, st.nnz - a)) for a in range(0, st.nnz, 30_000)]
+    for n in range(3):
+        np.testing.assert_array_equal(np.concatenate([p[0][n] for p in parts]), w["idx"][n])
+    np.testing.assert_array_equal(np.concatenate([p[1] for p in parts]), w["vals"])
+    for a, b in zip(st.initial_factors(), w["F0"]):
+        np.testing.assert_array_equal(a, b)
