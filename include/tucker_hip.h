@@ -199,6 +199,26 @@ tk_status tk_ttm_shape(tk_ctx* ctx, int n, int64_t* R_n, int64_t* Khat_n);
  * row_slice (may be NULL) gets their slice ids (int32).  With prec = TK_BF16
  * the Kronecker tiles are BF16 on the matrix cores (where such a kernel runs). */
 tk_status tk_ttm_chain(tk_ctx* ctx, int n, float* Y, int32_t* row_slice, tk_mem mem);
+/* Size of the library's static scratch array per GPU (bytes), used by
+ * tk_ttm_chain_noalloc. */
+#define TK_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * TTM-chain as tk_ttm_chain (same kernels, same results bit for bit), with no
+ * allocation of any kind (no hipMalloc, hipFree or allocating library call,
+ * and no memset node).  Y (R_n x Khat_n FP32) and row_slice (R_n int32, may be
+ * NULL) must be device memory of the context's GPU.  The partial rows of
+ * slices split across bins live in a static array of
+ * TK_NOALLOC_SCRATCH_BYTES per GPU (set up by tk_create, held until the
+ * process ends): a mode whose split slices need more (Khat_n * 4 bytes per
+ * partial row) gives TK_ERR_UNSUPPORTED and nothing is launched.  Every call
+ * on one GPU shares that array: calls that overlap on one GPU (other streams,
+ * other contexts, other threads) race and must be ordered by the caller.
+ * Nothing in the array needs to start at zero (every partial row is written
+ * before it is read). */
+tk_status tk_ttm_chain_noalloc(tk_ctx* ctx, int n, float* Y, int32_t* row_slice);
+
 /* Run `iters` HOOI invocations (Section 2.2): for each mode in turn, TTM-chain,
  * Gram, FP64 eigensolve, U = Y V S^-1, CholeskyQR2, new factor.  The
  * eigensolve is dense for Khat up to about 100 and a block Krylov method

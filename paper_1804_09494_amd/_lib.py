@@ -20,6 +20,7 @@ STATUS = {0: "TK_OK", 1: "TK_ERR_INVALID_ARG", 2: "TK_ERR_STATE", 3: "TK_ERR_OOM
 TK_MEM_HOST, TK_MEM_DEVICE = 0, 1
 TK_FP32, TK_BF16 = 0, 1
 TK_SWEEP_GAUSS_SEIDEL, TK_SWEEP_JACOBI = 0, 1
+TK_NOALLOC_SCRATCH_BYTES = 32 << 20
 TK_ASSUME_UNIQUE = 1
 
 
@@ -66,6 +67,7 @@ SIGNATURES = [
     ("tk_get_factor", c_int, [c_void_p, c_int, c_void_p, c_int]),
     ("tk_ttm_shape", c_int, [c_void_p, c_int, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     ("tk_ttm_chain", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
+    ("tk_ttm_chain_noalloc", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("tk_hooi_iterate", c_int, [c_void_p, c_int, c_void_p]),
     ("tk_core", c_int, [c_void_p, c_void_p, ctypes.POINTER(c_f64), c_int]),
     ("tk_get_timings", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int)]),

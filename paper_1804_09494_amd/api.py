@@ -250,6 +250,15 @@ class TuckerContext:
         self._check(self._L.tk_ttm_chain(self._h, n, _ptr(Y), _ptr(row_slice), mem))
         return Y, row_slice
 
+    def ttm_chain_noalloc(self, n, Y, row_slice=None):
+        """tk_ttm_chain_noalloc into caller-allocated device tensors (Y: R_n x
+        Khat_n float32, row_slice: R_n int32 or None); nothing is allocated."""
+        _check_dtype(Y, np.float32, "Y")
+        if row_slice is not None:
+            _check_dtype(row_slice, np.int32, "row_slice")
+        self._check(self._L.tk_ttm_chain_noalloc(self._h, n, _ptr(Y), _ptr(row_slice)))
+        return Y, row_slice
+
     def hooi_iterate(self, iters):
         fits = np.zeros(max(iters, 1), np.float64)
         self._check(self._L.tk_hooi_iterate(self._h, iters, _ptr(fits)))

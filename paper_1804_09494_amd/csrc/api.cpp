@@ -283,6 +283,7 @@ tk_status tk_create(int device, void* hip_stream, const tk_allocator* allocator,
     TK_HIP(hipSetDevice(device));
     c->device = device;
     if (allocator) c->allocator = *allocator;
+    noalloc_scratch_init(device);
     c->stream = (hipStream_t)hip_stream;
     tk_default_options(&c->opt);
     int v = 0;
@@ -547,6 +548,32 @@ tk_status tk_ttm_chain(tk_ctx* c, int n, float* Y, int32_t* row_slice, tk_mem me
       copy_out(c, row_slice, pl.row_slice.as<int32_t>(), (size_t)pl.L_nz, mem);
       if (mem == TK_MEM_HOST) c->sync();
     }
+  });
+}
+
+static bool is_device_ptr(const void* p, int device) {
+  hipPointerAttribute_t at{};
+  if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return at.type == hipMemoryTypeDevice && at.device == device;
+}
+
+tk_status tk_ttm_chain_noalloc(tk_ctx* c, int n, float* Y, int32_t* row_slice) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    TK_REQUIRE(c->have_ranks, TK_ERR_STATE, "set ranks first");
+    TK_REQUIRE(n >= 0 && n < c->N, TK_ERR_INVALID_ARG, "mode out of range");
+    const ModePlan& pl = c->plan[n];
+    if (pl.L_nz > 0) {
+      TK_REQUIRE(Y && is_device_ptr(Y, c->device), TK_ERR_INVALID_ARG, "Y must be device memory of the context's GPU");
+      TK_REQUIRE(!row_slice || is_device_ptr(row_slice, c->device), TK_ERR_INVALID_ARG,
+                 "row_slice must be device memory of the context's GPU");
+    }
+    TK_HIP(hipSetDevice(c->device));
+    ttm_chain_noalloc(c, n, Y);
+    if (row_slice && pl.L_nz > 0) copy_out(c, row_slice, pl.row_slice.as<int32_t>(), (size_t)pl.L_nz, TK_MEM_DEVICE);
   });
 }
 

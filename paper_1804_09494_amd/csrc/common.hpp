@@ -313,6 +313,8 @@ void refresh_factor_copies(Ctx* c, int n);
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
              const float* lay_val, int64_t m, float* Y, bool bf16 = false, float* partial = nullptr);
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial = nullptr);
+void noalloc_scratch_init(int device);
+void ttm_chain_noalloc(Ctx* c, int n, float* Y);
 void hooi_iterate(Ctx* c, int iters, double* fits);
 void core_and_fit(Ctx* c, double* core_dev, double* fit);
 

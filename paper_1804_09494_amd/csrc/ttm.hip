@@ -12,6 +12,7 @@
 //   * k_ttm4_mfma: four modes, other ranks <= 16, on the matrix cores;
 //   * k_ttm_cols:  every other shape, on the vector ALUs.
 // None of them uses atomics: every sum runs in a fixed order.
+#include <mutex>
 
 #include "common.hpp"
 
@@ -977,6 +978,46 @@ void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial) {
   const float* F[8];
   for (int j = 0; j < c->N; ++j) F[j] = c->F32[j].as<float>();
   ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y, bf16, partial);
+}
+
+// ---- the allocation-free TTM-chain -------------------------------------------------------------
+//
+// tk_ttm_chain_noalloc keeps the partial rows of split slices in this array
+// instead of a context buffer.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in symbol): its device address is
+// taken once per device, at context creation, and kept below.
+static __device__ __align__(256) float scratch[TK_NOALLOC_SCRATCH_BYTES / sizeof(float)];
+
+namespace {
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {nullptr};
+}  // namespace
+
+void noalloc_scratch_init(int device) {
+  TK_REQUIRE(device >= 0 && device < 64, TK_ERR_UNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  // the caller has made `device` current
+  TK_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  TK_REQUIRE(ptr != nullptr, TK_ERR_DEVICE, "no device address for the TTM-chain scratch array");
+  g_scratch_ptr[device] = ptr;
+}
+
+void ttm_chain_noalloc(Ctx* c, int n, float* Y) {
+  void* ptr = nullptr;
+  {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    ptr = g_scratch_ptr[c->device];
+  }
+  TK_REQUIRE(ptr != nullptr, TK_ERR_STATE, "scratch array not set up on this device");
+  const ModePlan& pl = c->plan[n];
+  const int64_t need = std::max<int64_t>(pl.fix_rows, 1) * pl.khat * (int64_t)sizeof(float);
+  TK_REQUIRE(need <= (int64_t)TK_NOALLOC_SCRATCH_BYTES, TK_ERR_UNSUPPORTED,
+             "tk_ttm_chain_noalloc: mode " + std::to_string(n) + " needs " + std::to_string(need) +
+                 " bytes of partial rows for its split slices, above the " +
+                 std::to_string((long long)TK_NOALLOC_SCRATCH_BYTES) + "-byte scratch array");
+  ttm_chain(c, n, Y, c->opt.prec == TK_BF16, static_cast<float*>(ptr));
 }
 
 }  // namespace tk
