@@ -217,6 +217,124 @@ def stream_load(ctx, stream, torch):
     return gen_s
 
 
+def run_completion(args):
+    """The differentiation form at its configuration's scale: Tucker completion
+    on 500,000 x 500,000 x 50,000 with 2e8 observations (Zipf 1.0 per mode),
+    ranks 16.  A step is one forward (model values at every observation) and
+    one adjoint (gradients of the squared loss for the core and the three
+    factors).  The targets are the values of a planted rank-16 model (core
+    N(0,1), factors N(0, 1/16)), formed by the library's forward, plus
+    N(0, 0.01^2) noise; the timed parameters are another seeded model."""
+    import torch
+    import synth
+    import paper_1804_09494_amd as P
+    torch.cuda.set_device(0)
+    dims, n_obs, ranks = (500_000, 500_000, 50_000), int(2e8 * args.scale), (16, 16, 16)
+    dims = tuple(max(2, int(round(d * (args.scale if args.scale < 1 else 1)))) for d in dims)
+    t = time.perf_counter()
+    obs = synth.make_completion(dims, n_obs, ranks, with_values=False)
+    idx = [torch.from_numpy(i).cuda() for i in obs["idx"]]
+    ctx = P.TuckerContext(0)
+    ctx.load_obs(idx, dims, ranks)
+    del idx
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t
+    Gt = torch.tensor(obs["G_true"].ravel(order="F"), dtype=torch.float32, device="cuda")
+    Ft = [torch.tensor(f, dtype=torch.float32, device="cuda") for f in obs["F_true"]]
+    noise = torch.from_numpy(synth.normal(4949, synth.S_NOISE, n_obs).astype(np.float32)).cuda()
+    v = ctx.tucker_eval(Gt, Ft) + 0.01 * noise
+    del noise
+    rng = np.random.default_rng(7)
+    G = torch.tensor(rng.standard_normal(int(np.prod(ranks))), dtype=torch.float32, device="cuda")
+    F = [torch.tensor(rng.standard_normal((d, k)) / np.sqrt(k), dtype=torch.float32, device="cuda")
+         for d, k in zip(dims, ranks)]
+
+    def step():
+        m = ctx.tucker_eval(G, F)
+        g = 2.0 * (m - v)
+        return ctx.tucker_adjoint(g, G, F)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    e = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    fwd = adj = 0.0
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        e[0].record()
+        m = ctx.tucker_eval(G, F)
+        e[1].record()
+        ctx.tucker_adjoint(2.0 * (m - v), G, F)
+        e[2].record()
+        torch.cuda.synchronize()
+        fwd += e[0].elapsed_time(e[1])
+        adj += e[1].elapsed_time(e[2])
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    out = {"metric": "Tucker-completion forward + adjoint, observations per second", "value": round(n_obs / ms / 1e6, 3),
+           "unit": "Gobs/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": f"c4: completion on {'x'.join(str(d) for d in dims)}, {n_obs} Zipf(1.0) "
+                                  f"observations, ranks 16x16x16, one forward + adjoint per step"},
+           "forward_ms": round(fwd / args.steps, 3), "adjoint_ms": round(adj / args.steps, 3),
+           "setup_s": round(setup_s, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def run_ablation(args):
+    """Partition ablations on one GPU: the TTM-chain of c2-shaped tensors
+    (1,000,000 x 500,000 x 200,000, 1e8 draws, Zipf 1.1 or 1.5 on every mode,
+    ranks 10) under Lite bins with the matrix-core kernel, Lite bins with the
+    vector-ALU kernel, CoarseG bins (whole slices, random order, contiguous
+    blocks) with the vector-ALU kernel, and no partition (atomics).  Reports
+    Section 4's metrics E_max and R_max and the kernel time per mode."""
+    import torch
+    import synth
+    import paper_1804_09494_amd as P
+    torch.cuda.set_device(0)
+    dims, nnz, ranks = (1_000_000, 500_000, 200_000), int(1e8 * args.scale), (10, 10, 10)
+    out = {"metric": "TTM-chain ms per mode under each partition", "config": {"dims": dims, "draws": nnz,
+                                                                               "ranks": ranks}, "runs": []}
+    for s in (1.1, 1.5):
+        idx, vals = synth.make_tensor(dims, nnz, "zipf", (s, s, s), "lognormal", seed=1811)
+        F0 = synth.orthonormal_init(9511, dims, ranks)
+        idx_d = [torch.from_numpy(i).cuda() for i in idx]
+        vals_d = torch.from_numpy(vals).cuda()
+        for scheme, kernel in (("lite", "auto"), ("lite", "vector"), ("coarse", "vector"), ("none", "atomic")):
+            ctx = P.TuckerContext(0, keep_elem_order=0, partition="coarse" if scheme == "coarse" else "lite",
+                                  ttm_kernel=kernel)
+            ctx.load_coo(idx_d, vals_d, dims)
+            if scheme == "coarse":
+                for n, L in enumerate(dims):
+                    ctx.set_slice_order(n, synth.permutation(61, 700 + n, L))
+            ctx.set_ranks(ranks)
+            for n, F in enumerate(F0):
+                ctx.set_factor(n, np.ascontiguousarray(F))
+            m, _ = ctx.tensor_info()
+            run = {"zipf": s, "partition": scheme, "kernel": kernel, "m": m, "modes": []}
+            for n in range(3):
+                R, kh = ctx.ttm_shape(n)
+                Y = torch.empty((R, kh), dtype=torch.float32, device="cuda")
+                ctx.ttm_chain(n, Y)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(max(1, args.steps)):
+                    ctx.ttm_chain(n, Y)
+                e1.record()
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1) / max(1, args.steps)
+                st = ctx.partition_stats(n)
+                run["modes"].append({"ms": round(ms, 3), "Gnnz_s": round(m / ms / 1e6, 2), "E_max": st["E_max"],
+                                     "R_max": st["R_max"], "R_sum": st["R_sum"], "n_bad": st["n_bad"], "P": st["P"]})
+                del Y
+            print(json.dumps(run), file=sys.stderr, flush=True)
+            out["runs"].append(run)
+            del ctx
+            torch.cuda.empty_cache()
+        del idx_d, vals_d
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -229,6 +347,7 @@ def main():
     ap.add_argument("--rows-cap", type=int, default=0, help="LDS rows per Lite bin (0 = library default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profile", metavar="DIR")
+    ap.add_argument("--ablation", action="store_true", help="partition ablations (Lite, CoarseG, atomics)")
     args = ap.parse_args()
     if args.summarize_profile:
         import synth
@@ -239,6 +358,12 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only: no figure at several GPUs is measured; "
                                    "DESIGN.md describes how the path would shard", "n_gpus": args.gpus}))
         sys.exit(2)
+    if args.workload == "c4":
+        run_completion(args)
+        return
+    if args.ablation:
+        run_ablation(args)
+        return
 
     import torch
     import synth
@@ -306,6 +431,8 @@ def main():
     print(f"# per-step ms fp32: " + ", ".join(f"{k}={v / K:.3f}" for k, v in tm.items()), file=sys.stderr, flush=True)
     print(f"# per-step ms bf16: " + ", ".join(f"{k}={v / K:.3f}" for k, v in bf_tm.items()), file=sys.stderr,
           flush=True)
+    counters = ctx.counters()
+    print(f"# counters {counters}", file=sys.stderr, flush=True)
     del ctx
     torch.cuda.empty_cache()
 
@@ -349,6 +476,7 @@ def main():
                      "kernel": f"{kernel} (TTM-chain)",
                      "bytes_per_launch": [int(b) for b in B]},
         "device_copy_GBps": round(copy_gbs, 1),
+        "counters": counters,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -66,6 +66,22 @@ typedef enum {
 typedef enum { TK_MEM_HOST = 0, TK_MEM_DEVICE = 1 } tk_mem;
 typedef enum { TK_FP32 = 0, TK_BF16 = 1 } tk_prec;
 typedef enum { TK_SWEEP_GAUSS_SEIDEL = 0, TK_SWEEP_JACOBI = 1 } tk_sweep;
+/* How each mode's elements are split over the workgroups ("bins"). */
+typedef enum {
+  TK_PART_LITE = 0,    /* Lite (Section 6): the default */
+  TK_PART_COARSE = 1   /* CoarseG (Section 5, coarse grained schemes): the mode's slices in a caller-given
+                          random order (tk_set_slice_order), cut into contiguous blocks of whole slices, the
+                          block of slice t holding the slices whose element prefix starts in
+                          [p m / P, (p+1) m / P); an ablation baseline */
+} tk_partition;
+/* Which TTM-chain kernel runs. */
+typedef enum {
+  TK_TTM_AUTO = 0,     /* matrix-core kernels where they apply, else the vector-ALU one */
+  TK_TTM_VECTOR = 1,   /* the vector-ALU kernel for every shape (and whatever the bin sizes) */
+  TK_TTM_ATOMIC = 2    /* no partition: the merged element list in canonical order, each wave's
+                          running row sums added to Y with FP32 atomics when the mode-n index changes
+                          (not deterministic); an ablation baseline */
+} tk_ttm_kernel;
 
 typedef struct {
   int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16 (the precision form): the
@@ -87,6 +103,8 @@ typedef struct {
                                      subspace error sqrt(2) * residual * theta_1 / (theta_K - theta_{K+1})
                                      (sin-theta theorem); a larger estimate reruns the mode's eigensolve
                                      with the dense solver.  0 (default) = 1e-7 */
+  int32_t partition;              /* tk_partition (default TK_PART_LITE); read by tk_set_ranks */
+  int32_t ttm_kernel;             /* tk_ttm_kernel (default TK_TTM_AUTO) */
 } tk_options;
 
 /* Lite statistics of one mode (Section 4 metrics 1-3; Theorem 6.1). */
@@ -171,6 +189,10 @@ tk_status tk_get_coo(tk_ctx* ctx, int32_t* const* idx, float* vals, tk_mem mem);
  * columns of the identity; set them with tk_set_factor. */
 tk_status tk_set_ranks(tk_ctx* ctx, const int32_t* K);
 tk_status tk_get_partition_stats(tk_ctx* ctx, int n, tk_part_stats* out);
+/* The random order of mode n's slice ids used by partition = TK_PART_COARSE:
+ * perm holds L_n distinct ids in [0, L_n) (checked on the device; copied).
+ * Needed for every mode before tk_set_ranks with that partition. */
+tk_status tk_set_slice_order(tk_ctx* ctx, int n, const int32_t* perm, tk_mem mem);
 /* Export mode n's partition (sizes from tk_get_partition_stats, S = R_sum):
  *   bin_ptr[P+1]   layout offset of each bin (int64)
  *   elem_order[m]  canonical element index at each layout position (int64; NULL to skip;
@@ -235,7 +257,8 @@ tk_status tk_core(tk_ctx* ctx, double* core, double* fit, tk_mem mem);
 tk_status tk_get_timings(tk_ctx* ctx, double* ms, const char** names, int* count);
 
 /* Event counts since the context was created (names[i] static strings):
- *   eig_krylov_solves, eig_krylov_cycles, eig_dense_fallbacks.
+ *   eig_krylov_solves, eig_krylov_cycles, eig_dense_fallbacks, rank_completions (factors
+ *   completed after a rank-deficient penultimate matrix).
  * *count is in/out: capacity in, entries written out. */
 tk_status tk_get_counters(tk_ctx* ctx, int64_t* values, const char** names, int* count);
 

@@ -159,14 +159,15 @@ class Partition:
     lite: LiteResult
 
 
-def partition_mode(idx_n, L_n: int, P: int) -> Partition:
-    """Lite along one mode for coalesced elements in canonical order.
+def partition_mode(idx_n, L_n: int, P: int, coarse_order=None) -> Partition:
+    """Lite (or, given a random slice order, CoarseG) along one mode for
+    coalesced elements in canonical order.
 
     idx_n: the mode-n coordinate of every element (canonical order)."""
     idx_n = np.asarray(idx_n, dtype=np.int64)
     m = idx_n.shape[0]
     sizes = np.bincount(idx_n, minlength=L_n) if m else np.zeros(L_n, np.int64)
-    res = lite(sizes.tolist(), P)
+    res = lite(sizes.tolist(), P) if coarse_order is None else coarse_g(sizes.tolist(), P, coarse_order)
     # Elements of each slice in canonical order (stable sort by slice id).
     by_slice = np.argsort(idx_n, kind="stable")
     start = np.zeros(L_n + 1, np.int64)
@@ -193,3 +194,42 @@ def partition_mode(idx_n, L_n: int, P: int) -> Partition:
                      seg_bin=arr[:, 0].astype(np.int32), seg_slice=arr[:, 1].astype(np.int32),
                      seg_begin=arr[:, 2].copy(), seg_end=arr[:, 3].copy(),
                      seg_bad=arr[:, 4].astype(np.uint8), stats=res.stats, lite=res)
+
+
+# ---------------------------------------------------------------------------------------------
+# CoarseG (Section 5, "Coarse Grained Schemes"): a prior scheme, kept as the
+# baseline Lite is compared with.  Along mode n each slice goes whole to one
+# processor: the slices are arranged in a random order and contiguous blocks
+# of them are allocated to the processors.  Reading (the paper does not say
+# where the blocks end): the block boundaries balance elements, the slice whose
+# elements start at prefix x (in the random order) going to bin
+# min(P - 1, floor(x P / m)).  Empty slices are left out.  The random order is
+# an input (the caller draws it).
+# ---------------------------------------------------------------------------------------------
+
+def coarse_g(slice_sizes, P: int, order) -> LiteResult:
+    sizes = [int(s) for s in slice_sizes]
+    m = sum(sizes)
+    if P < 1:
+        raise ValueError("P must be >= 1")
+    if sorted(int(l) for l in order) != list(range(len(sizes))):
+        raise ValueError("order must be a permutation of the slice ids")
+    load = [0] * P
+    pieces = {}
+    bin_slices = [[] for _ in range(P)]
+    x = 0
+    for l in order:
+        l = int(l)
+        if sizes[l] == 0:
+            continue
+        p = min(P - 1, x * P // m)
+        load[p] += sizes[l]
+        pieces[l] = [(p, sizes[l])]
+        bin_slices[p].append((l, sizes[l]))
+        x += sizes[l]
+    nonempty = [int(l) for l in order if sizes[int(l)] > 0]
+    res = LiteResult(P=P, limit=ceil_div(m, P) if m > 0 else 0, m=m, L_nonempty=len(nonempty),
+                     n_stage1=len(nonempty), order=nonempty, pieces=pieces, bin_slices=bin_slices, load=load)
+    res.stats = metrics_from_bins(bin_slices, load)
+    res.stats.update(P=P, limit=res.limit, m=m, L_nonempty=len(nonempty), n_stage1=len(nonempty))
+    return res

@@ -22,12 +22,15 @@ TK_FP32, TK_BF16 = 0, 1
 TK_SWEEP_GAUSS_SEIDEL, TK_SWEEP_JACOBI = 0, 1
 TK_NOALLOC_SCRATCH_BYTES = 32 << 20
 TK_ASSUME_UNIQUE = 1
+TK_PART_LITE, TK_PART_COARSE = 0, 1
+TK_TTM_AUTO, TK_TTM_VECTOR, TK_TTM_ATOMIC = 0, 1, 2
 
 
 class tk_options(ctypes.Structure):
     _fields_ = [("prec", c_i32), ("sweep", c_i32), ("wg_nnz_target", c_i64), ("lds_rows_cap", c_i32),
                 ("refine", c_i32), ("mem_limit_bytes", c_i64),
-                ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32), ("eig_tol", c_f64)]
+                ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32), ("eig_tol", c_f64),
+                ("partition", c_i32), ("ttm_kernel", c_i32)]
 
 
 TK_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
@@ -60,6 +63,7 @@ SIGNATURES = [
     ("tk_get_tensor_info", c_int, [c_void_p, ctypes.POINTER(c_i64), ctypes.POINTER(c_f64)]),
     ("tk_get_coo", c_int, [c_void_p, ctypes.POINTER(c_void_p), c_void_p, c_int]),
     ("tk_set_ranks", c_int, [c_void_p, ctypes.POINTER(c_i32)]),
+    ("tk_set_slice_order", c_int, [c_void_p, c_int, c_void_p, c_int]),
     ("tk_get_partition_stats", c_int, [c_void_p, c_int, ctypes.POINTER(tk_part_stats)]),
     ("tk_get_partition", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                  c_int]),

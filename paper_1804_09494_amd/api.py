@@ -129,6 +129,13 @@ class TuckerContext:
         prec = kw.pop("prec", None)
         if prec is not None:
             o.prec = {"fp32": _lib.TK_FP32, "bf16": _lib.TK_BF16}.get(prec, prec)
+        part = kw.pop("partition", None)
+        if part is not None:
+            o.partition = {"lite": _lib.TK_PART_LITE, "coarse": _lib.TK_PART_COARSE}.get(part, part)
+        kern = kw.pop("ttm_kernel", None)
+        if kern is not None:
+            o.ttm_kernel = {"auto": _lib.TK_TTM_AUTO, "vector": _lib.TK_TTM_VECTOR,
+                            "atomic": _lib.TK_TTM_ATOMIC}.get(kern, kern)
         sweep = kw.pop("sweep", None)
         if sweep is not None:
             o.sweep = {"gauss_seidel": _lib.TK_SWEEP_GAUSS_SEIDEL, "jacobi": _lib.TK_SWEEP_JACOBI}.get(sweep, sweep)
@@ -195,6 +202,11 @@ class TuckerContext:
         K = (c_i32 * self.N)(*[int(k) for k in ranks])
         self._check(self._L.tk_set_ranks(self._h, K))
         self.ranks = tuple(int(k) for k in ranks)
+
+    def set_slice_order(self, n, perm):
+        """The random slice order of mode n for the CoarseG partition."""
+        _check_dtype(perm, np.int32, "perm")
+        self._check(self._L.tk_set_slice_order(self._h, n, _ptr(perm), _mem_of(perm)))
 
     def partition_stats(self, n):
         s = tk_part_stats()

@@ -260,6 +260,8 @@ tk_status tk_default_options(tk_options* o) {
   o->complete_rank_deficient = 1;
   o->keep_elem_order = 1;
   o->eig_tol = 0.0;
+  o->partition = TK_PART_LITE;
+  o->ttm_kernel = TK_TTM_AUTO;
   return TK_OK;
 }
 
@@ -316,6 +318,8 @@ tk_status tk_set_options(tk_ctx* c, const tk_options* o) {
     TK_REQUIRE(o->sweep == TK_SWEEP_GAUSS_SEIDEL || o->sweep == TK_SWEEP_JACOBI, TK_ERR_INVALID_ARG, "sweep");
     TK_REQUIRE(o->wg_nnz_target >= 0 && o->mem_limit_bytes >= 0, TK_ERR_INVALID_ARG, "negative size");
     TK_REQUIRE(o->eig_tol >= 0.0, TK_ERR_INVALID_ARG, "negative eig_tol");
+    TK_REQUIRE(o->partition == TK_PART_LITE || o->partition == TK_PART_COARSE, TK_ERR_INVALID_ARG, "partition");
+    TK_REQUIRE(o->ttm_kernel >= TK_TTM_AUTO && o->ttm_kernel <= TK_TTM_ATOMIC, TK_ERR_INVALID_ARG, "ttm_kernel");
     c->opt = *o;
   });
 }
@@ -336,7 +340,10 @@ static void drop_tensor(Ctx* c) {
     c->eig_warm[j].release();
     c->eig_warm_k[j] = 0;
   }
-  for (int j = 0; j < 8; ++j) c->idx_c[j].release();
+  for (int j = 0; j < 8; ++j) {
+    c->idx_c[j].release();
+    c->slice_order[j].release();
+  }
   c->val_c.release();
   c->m = 0;
 }
@@ -447,10 +454,16 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       TK_REQUIRE(c->bytes_in_use + need <= c->opt.mem_limit_bytes, TK_ERR_OOM,
                  "the plan needs about " + std::to_string(need) + " bytes, above mem_limit_bytes");
     }
+    const bool coarse = c->opt.partition == TK_PART_COARSE;
+    if (coarse)
+      for (int n = 0; n < N; ++n)
+        TK_REQUIRE(c->slice_order[n].bytes() == sizeof(int32_t) * (size_t)c->dims[n], TK_ERR_STATE,
+                   "the CoarseG partition needs tk_set_slice_order for every mode");
     for (int n = 0; n < N; ++n) {
       const int tw = ttm_tile_width(N, K, n);
       build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
-                 ttm_default_bin_nnz(N, K, n), c->opt.keep_elem_order != 0);
+                 ttm_default_bin_nnz(N, K, n), c->opt.keep_elem_order != 0,
+                 coarse ? c->slice_order[n].as<int32_t>() : nullptr);
     }
     for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);
     for (int n = 0; n < N; ++n) {
@@ -466,6 +479,40 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       c->sync();
     }
     c->have_ranks = true;
+  });
+}
+
+__global__ void k_count_ids(const int32_t* __restrict__ p, int64_t L, int32_t* __restrict__ seen,
+                            int32_t* __restrict__ flag) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L; i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = p[i];
+    if (v < 0 || (int64_t)v >= L) {
+      atomicOr(flag, 1);
+    } else if (atomicAdd(seen + v, 1) != 0) {
+      atomicOr(flag, 1);
+    }
+  }
+}
+
+tk_status tk_set_slice_order(tk_ctx* c, int n, const int32_t* perm, tk_mem mem) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    TK_REQUIRE(c->have_tensor, TK_ERR_STATE, "load a tensor first");
+    TK_REQUIRE(n >= 0 && n < c->N && perm, TK_ERR_INVALID_ARG, "mode out of range or perm is NULL");
+    TK_REQUIRE(mem == TK_MEM_HOST || mem == TK_MEM_DEVICE, TK_ERR_INVALID_ARG, "mem");
+    TK_HIP(hipSetDevice(c->device));
+    const int64_t L = c->dims[n];
+    Buf p(c, sizeof(int32_t) * (size_t)L), seen(c, sizeof(int32_t) * (size_t)(L + 1));
+    copy_in(c, p.as<int32_t>(), perm, (size_t)L, mem);
+    TK_HIP(hipMemsetAsync(seen.get(), 0, sizeof(int32_t) * (size_t)(L + 1), c->stream));
+    hipLaunchKernelGGL(k_count_ids, dim3(grid_for(L, 256, 4096)), dim3(256), 0, c->stream, p.as<int32_t>(), L,
+                       seen.as<int32_t>(), seen.as<int32_t>() + L);
+    TK_CHECK_LAUNCH();
+    int32_t bad = 0;
+    d2h(c, &bad, seen.as<int32_t>() + L, 1);
+    c->sync();
+    TK_REQUIRE(bad == 0, TK_ERR_INVALID_ARG, "tk_set_slice_order: not a permutation of [0, L_n)");
+    c->slice_order[n] = std::move(p);
   });
 }
 
@@ -623,10 +670,11 @@ tk_status tk_get_timings(tk_ctx* c, double* ms, const char** names, int* count) 
 
 tk_status tk_get_counters(tk_ctx* c, int64_t* values, const char** names, int* count) {
   if (!c || !count) return TK_ERR_INVALID_ARG;
-  static const char* const kNames[] = {"eig_krylov_solves", "eig_krylov_cycles", "eig_dense_fallbacks"};
+  static const char* const kNames[] = {"eig_krylov_solves", "eig_krylov_cycles", "eig_dense_fallbacks",
+                                       "rank_completions"};
   const int64_t v[] = {c->counters.eig_krylov_solves, c->counters.eig_krylov_cycles,
-                       c->counters.eig_dense_fallbacks};
-  const int w = std::min(*count, 3);
+                       c->counters.eig_dense_fallbacks, c->counters.rank_completions};
+  const int w = std::min(*count, 4);
   for (int i = 0; i < w; ++i) {
     if (values) values[i] = v[i];
     if (names) names[i] = kNames[i];

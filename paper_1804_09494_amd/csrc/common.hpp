@@ -80,7 +80,9 @@ struct ModePlan {
   int64_t n_bad = 0, n_slots = 0, E_max = 0, R_max = 0;
   int64_t khat = 0;
   int rows_cap = 0;       // LDS rows per bin the TTM kernel was sized for
+  bool whole_slices = false;  // CoarseG: bins of whole slices, of any size (vector-ALU kernel only)
   Buf row_slice;          // int32[L_nz]  slice id of each compact row (ascending)
+  Buf row_of;             // int32[L]     compact row of each slice id (valid for nonempty slices)
   Buf label;              // int32[L]     storage row of each index in the working factor copies:
                           //              descending slice size (hot rows packed first)
   Buf bin_ptr;            // int64[P+1]
@@ -127,6 +129,7 @@ struct Counters {
   int64_t eig_krylov_solves = 0;     // block-Krylov eigensolves
   int64_t eig_krylov_cycles = 0;     // their restart cycles
   int64_t eig_dense_fallbacks = 0;   // Krylov results replaced by the dense solver (estimate above eig_tol)
+  int64_t rank_completions = 0;      // factors completed after a rank-deficient penultimate matrix
 };
 
 // A streamed load in progress (tk_load_coo_begin .. tk_load_coo_end): the raw
@@ -175,6 +178,7 @@ struct Ctx {
   Buf val_c;              // float[m]
   bool have_tensor = false;
   LoadState load;
+  Buf slice_order[8];     // int32[L_n] caller-given random slice order (CoarseG)
 
   // ranks / plans / factors
   int32_t K[8] = {0};
@@ -300,7 +304,7 @@ void load_begin(Ctx* c, int N, const int64_t* dims, int64_t nnz, unsigned flags)
 void load_append(Ctx* c, int64_t count, const int32_t* const* idx, const float* vals, tk_mem mem);
 void load_end(Ctx* c);
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
-                int64_t khat, int tile_w, int64_t wg_default, bool keep_order);
+                int64_t khat, int tile_w, int64_t wg_default, bool keep_order, const int32_t* coarse_order = nullptr);
 void relabel_layout(Ctx* c, ModePlan& pl, int N, int n, const ModePlan* plans, int64_t m);
 void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t* elem_order, int32_t* seg_bin,
                       int32_t* seg_slice, int64_t* seg_begin, uint8_t* seg_bad, tk_mem mem);

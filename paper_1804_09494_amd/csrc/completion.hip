@@ -14,6 +14,9 @@
 
 namespace tk {
 
+int uw_product(Ctx* c, const float* Y, int64_t R, int khat, const double* W, int K, double* U, double* part);
+int uw_product_parts(int64_t R);
+
 __global__ void k_obs_validate(const int32_t* __restrict__ idx, int64_t m, int64_t L, int32_t* __restrict__ flag) {
   int bad = 0;
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < m; i += (int64_t)gridDim.x * blockDim.x) {
@@ -129,6 +132,63 @@ __global__ __launch_bounds__(256) void k_eval(FPtrs F, IPtrs ip, int N, int32_t 
   }
 }
 
+typedef float floatx4_e __attribute__((ext_vector_type(4)));
+
+// Three modes, every rank <= 16, on the matrix cores.  For 16 observations
+// i at a time, D = A B with A[i][(b, c)] = F_1[l_1(i)][b] F_2[l_2(i)][c] (the
+// Kronecker row, zero past the ranks) and B[(b, c)][a] = G[a + K_0 (b + K_1 c)]:
+// 64 steps of v_mfma_f32_16x16x4_f32 (step (c, s) contracts b = 4s .. 4s+3),
+// lane l supplying A[l%16][4s + l/16] and B[4s + l/16][l%16].  B is held in
+// 64 registers per lane for the whole kernel.  Then
+// m_i = sum_a D[i][a] F_0[l_0(i)][a], a sum over the 16 lanes of a row group.
+// Rows are read from the caller's factors (row stride K_j).
+__global__ __launch_bounds__(256) void k_eval3_mfma(const float* __restrict__ F0, const float* __restrict__ F1,
+                                                    const float* __restrict__ F2, const int32_t* __restrict__ i0,
+                                                    const int32_t* __restrict__ i1, const int32_t* __restrict__ i2,
+                                                    int K0, int K1, int K2, const float* __restrict__ G,
+                                                    int64_t n_obs, float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  const int i16 = lane & 15, q = lane >> 4;
+  float bg[16][4];   // B for step (c, s): G[i16 + K0 (4s + q + K1 c)]
+#pragma unroll
+  for (int c = 0; c < 16; ++c)
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) {
+      const int b = 4 * s4 + q;
+      bg[c][s4] = (i16 < K0 && b < K1 && c < K2) ? G[i16 + K0 * (b + K1 * c)] : 0.f;
+    }
+  const int64_t nblk = (n_obs + 15) >> 4;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  const int64_t nwaves = (int64_t)gridDim.x * 4;
+  for (int64_t blk = wave; blk < nblk; blk += nwaves) {
+    const int64_t e = blk * 16 + i16;            // this lane's observation for the A operand
+    const bool ok = e < n_obs;
+    const int64_t ee = ok ? e : n_obs - 1;
+    const float* r1 = F1 + (int64_t)i1[ee] * K1;
+    const float* r2 = F2 + (int64_t)i2[ee] * K2;
+    float f1[4], f2[16];
+#pragma unroll
+    for (int s4 = 0; s4 < 4; ++s4) f1[s4] = (ok && 4 * s4 + q < K1) ? r1[4 * s4 + q] : 0.f;
+#pragma unroll
+    for (int c = 0; c < 16; ++c) f2[c] = c < K2 ? r2[c] : 0.f;
+    floatx4_e D = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int c = 0; c < 16; ++c)
+#pragma unroll
+      for (int s4 = 0; s4 < 4; ++s4) D = __builtin_amdgcn_mfma_f32_16x16x4f32(f1[s4] * f2[c], bg[c][s4], D, 0, 0, 0);
+    // D[4q + r][i16] in register r: times F_0[l_0(obs 4q+r)][a = i16], summed over the 16 lanes of the group
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t er = blk * 16 + 4 * q + r;
+      const bool okr = er < n_obs;
+      float v = (okr && i16 < K0) ? D[r] * F0[(int64_t)i0[okr ? er : n_obs - 1] * K0 + i16] : 0.f;
+#pragma unroll
+      for (int w = 8; w >= 1; w >>= 1) v += __shfl_xor(v, w, 16);
+      if (i16 == 0 && okr) out[er] = v;
+    }
+  }
+}
+
 static const float* dev_copy_f32(Ctx* c, Buf& tmp, const float* src, size_t n, tk_mem mem) {
   if (mem == TK_MEM_DEVICE) return src;
   tmp.alloc(c, sizeof(float) * std::max<size_t>(n, 1));
@@ -155,7 +215,11 @@ void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk
     tOut.alloc(c, sizeof(float) * (size_t)std::max<int64_t>(o.n_obs, 1));
     out = tOut.as<float>();
   }
-  if (o.n_obs > 0) {
+  if (o.n_obs > 0 && N == 3 && o.K[0] <= 16 && o.K[1] <= 16 && o.K[2] <= 16) {
+    hipLaunchKernelGGL(k_eval3_mfma, dim3(grid_for(ceil_div(o.n_obs, 16), 4, 16384)), dim3(256), 0, c->stream,
+                       fp.p[0], fp.p[1], fp.p[2], ip.p[0], ip.p[1], ip.p[2], o.K[0], o.K[1], o.K[2], G, o.n_obs, out);
+    TK_CHECK_LAUNCH();
+  } else if (o.n_obs > 0) {
     const int use_lds = (size_t)pK * 4 <= std::min<size_t>(c->lds_per_block, 65536) ? 1 : 0;
     const size_t lds = use_lds ? (size_t)pK * 4 : 0;
     if (o.K[0] <= 16)
@@ -171,6 +235,11 @@ void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk
 }
 
 // ---- adjoint ----------------------------------------------------------------------------------
+
+__global__ void k_fill_zero_f(float* __restrict__ p, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = 0.f;
+}
 
 __global__ void k_pad_copy(const float* __restrict__ src, int64_t L, int K, float* __restrict__ dst, int kp) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * kp; i += (int64_t)gridDim.x * blockDim.x) {
@@ -206,6 +275,7 @@ __device__ __forceinline__ int64_t core_lin(int N, const int32_t* K, int n, int 
 }
 
 // dF[row_slice[r]][k] = sum_col Yg[r][col] * G_(n)[k][col]; G_(n) staged in LDS.
+// The general path (K_n above 16); FP64 accumulation.
 __global__ __launch_bounds__(256) void k_dF(const float* __restrict__ Yg, int64_t R, int khat,
                                             const float* __restrict__ G, int N, const int32_t* __restrict__ Kd, int n,
                                             const int32_t* __restrict__ row_slice, float* __restrict__ dF) {
@@ -230,7 +300,31 @@ __global__ __launch_bounds__(256) void k_dF(const float* __restrict__ Yg, int64_
   }
 }
 
-// dcore[c0 + K0 * col] = sum_r F0[slice(r)][c0] * Yg[r][col]  (FP64 accumulation, fixed order per entry)
+// W = G_(n)^T as a Khat x K_n FP64 matrix (the right operand of dF_n = Y^g_(n) G_(n)^T).
+__global__ void k_core_unfold_t(const float* __restrict__ G, int N, const int32_t* __restrict__ Kd, int n, int khat,
+                                double* __restrict__ W) {
+  int32_t K[8];
+  for (int j = 0; j < N; ++j) K[j] = Kd[j];
+  const int Kn = K[n];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)khat * Kn;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t col = i / Kn;
+    const int k = (int)(i - col * Kn);
+    W[i] = (double)G[core_lin(N, K, n, k, col)];
+  }
+}
+
+// dF rows from U = Y^g W (R x K, FP64): dF[row_slice[r]] = U[r], FP32.
+__global__ void k_scatter_rows(const double* __restrict__ U, int64_t R, int K, const int32_t* __restrict__ row_slice,
+                               float* __restrict__ dF) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < R * K; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = i / K;
+    const int k = (int)(i - r * K);
+    dF[(int64_t)row_slice[r] * K + k] = (float)U[i];
+  }
+}
+
+// dcore[c0 + K0 * col] = sum_r F0[slice(r)][c0] * Yg[r][col] (the general path, K_0 above 16).
 __global__ __launch_bounds__(256) void k_dcore(const float* __restrict__ Yg, int64_t R, int khat,
                                                const float* __restrict__ F0, int K0, int kp0,
                                                const int32_t* __restrict__ row_slice, float* __restrict__ dcore) {
@@ -240,6 +334,59 @@ __global__ __launch_bounds__(256) void k_dcore(const float* __restrict__ Yg, int
     const int64_t col = i / K0;
     double s = 0.0;
     for (int64_t r = 0; r < R; ++r) s += (double)F0[(int64_t)row_slice[r] * kp0 + c0] * (double)Yg[r * khat + col];
+    dcore[i] = (float)s;
+  }
+}
+
+typedef float floatx4_c __attribute__((ext_vector_type(4)));
+
+// dG as A^T Y on the matrix cores (K_0 <= 16): A[r] = F0[row_slice[r]] (16
+// floats, zero past K_0), Y = Y^g_(1) (R x khat).  Workgroup w takes rows
+// [w*rpw, (w+1)*rpw) and column tiles blockIdx.y*4 + wave (16 columns each):
+// v_mfma_f32_16x16x4_f32 with lane l supplying A[r0 + 4s + l/16][l%16] as the
+// left operand (i over K_0) and Y[r0 + 4s + l/16][16 t + l%16] as the right
+// one (j over columns), so D[4(l/16)+q][l%16] = sum_r A[r][4(l/16)+q] Y[r][16t + l%16].
+// Each workgroup writes its FP32 partial tile; k_dcore_sum adds the partials
+// in workgroup order in FP64.
+__global__ __launch_bounds__(256) void k_dcore_mfma(const float* __restrict__ Yg, int64_t R, int khat,
+                                                    const float* __restrict__ F0, int kp0,
+                                                    const int32_t* __restrict__ row_slice, int64_t rpw,
+                                                    float* __restrict__ part) {
+  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int t = blockIdx.y * 4 + wave;           // column tile
+  const int i16 = lane & 15, q = lane >> 4;
+  const int col = 16 * t + i16;
+  const int64_t r0 = (int64_t)blockIdx.x * rpw, r1 = min(r0 + rpw, R);
+  floatx4_c acc = {0.f, 0.f, 0.f, 0.f};
+  if (16 * t < khat) {
+    // the loop is uniform over the wave; rows past r1 contribute zero
+    for (int64_t r4 = r0; r4 < r1; r4 += 4) {
+      const int64_t r = r4 + q;
+      const bool ok = r < r1;
+      const float a = ok ? F0[(int64_t)row_slice[r] * kp0 + i16] : 0.f;
+      const float b = ok && col < khat ? Yg[r * khat + col] : 0.f;
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  }
+  // partial tile of this workgroup: part[(wg * ntiles + t) * 256 + (row i)*16 + col j]
+  const int ntiles = (khat + 15) >> 4;
+  if (t < ntiles) {
+    float* dst = part + ((int64_t)blockIdx.x * ntiles + t) * 256;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) dst[(4 * q + r) * 16 + i16] = acc[r];
+  }
+}
+
+// dcore[c0 + K0 * col] = sum over workgroups (in order) of the partial tiles, FP64.
+__global__ void k_dcore_sum(const float* __restrict__ part, int nwg, int khat, int K0, float* __restrict__ dcore) {
+  const int ntiles = (khat + 15) >> 4;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < (int64_t)K0 * khat;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int c0 = (int)(i % K0);
+    const int col = (int)(i / K0);
+    const int t = col >> 4, j = col & 15;
+    double s = 0.0;
+    for (int w = 0; w < nwg; ++w) s += (double)part[((int64_t)w * ntiles + t) * 256 + c0 * 16 + j];
     dcore[i] = (float)s;
   }
 }
@@ -277,8 +424,25 @@ void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* 
       tdF.alloc(c, sizeof(float) * (size_t)o.dims[n] * o.K[n]);
       dFn = tdF.as<float>();
     }
-    TK_HIP(hipMemsetAsync(dFn, 0, sizeof(float) * (size_t)o.dims[n] * o.K[n], c->stream));
-    if (pl.L_nz > 0) {
+    {
+      const int64_t nd = o.dims[n] * (int64_t)o.K[n];
+      hipLaunchKernelGGL(k_fill_zero_f, dim3(grid_for(nd, 256, 4096)), dim3(256), 0, c->stream, dFn, nd);
+      TK_CHECK_LAUNCH();
+    }
+    if (pl.L_nz > 0 && o.K[n] <= 16) {
+      // dF_n = Y^g_(n) G_(n)^T on the matrix cores, then scattered to the slices' rows
+      const int Kn = o.K[n];
+      ensure(c, c->small64, sizeof(double) * ((size_t)khat * Kn + (size_t)uw_product_parts(pl.L_nz) * Kn * Kn));
+      ensure(c, c->U64, sizeof(double) * (size_t)pl.L_nz * Kn);
+      double* W = c->small64.as<double>();
+      hipLaunchKernelGGL(k_core_unfold_t, dim3(grid_for((int64_t)khat * Kn, 256, 256)), dim3(256), 0, c->stream, G, N,
+                         tK.as<int32_t>(), n, khat, W);
+      TK_CHECK_LAUNCH();
+      uw_product(c, Yg, pl.L_nz, khat, W, Kn, c->U64.as<double>(), W + (size_t)khat * Kn);
+      hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(pl.L_nz * Kn, 256)), dim3(256), 0, c->stream,
+                         c->U64.as<double>(), pl.L_nz, Kn, pl.row_slice.as<int32_t>(), dFn);
+      TK_CHECK_LAUNCH();
+    } else if (pl.L_nz > 0) {
       const size_t lds = sizeof(float) * (size_t)o.K[n] * khat;
       TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "adjoint: K_n x Khat too large for LDS");
       hipLaunchKernelGGL(k_dF, dim3(grid_for(pl.L_nz * o.K[n], 256, 16384)), dim3(256), lds, c->stream, Yg, pl.L_nz,
@@ -293,12 +457,27 @@ void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* 
         tdc.alloc(c, sizeof(float) * (size_t)pK);
         dc = tdc.as<float>();
       }
-      if (pl.L_nz > 0) {
+      if (pl.L_nz > 0 && o.K[0] <= 16 && o.kp[0] == 16) {
+        // A^T Y on the matrix cores, partials summed in workgroup order in FP64
+        const int ntiles = (khat + 15) >> 4;
+        const int64_t rpw = std::max<int64_t>(256, ceil_div(ceil_div(pl.L_nz, 512), 4) * 4);
+        const int nwg = (int)ceil_div(pl.L_nz, rpw);
+        Buf part(c, sizeof(float) * (size_t)nwg * ntiles * 256);
+        hipLaunchKernelGGL(k_dcore_mfma, dim3(nwg, (unsigned)ceil_div(ntiles, 4)), dim3(256), 0, c->stream, Yg,
+                           pl.L_nz, khat, o.F32[0].as<float>(), o.kp[0], pl.row_slice.as<int32_t>(), rpw,
+                           part.as<float>());
+        TK_CHECK_LAUNCH();
+        hipLaunchKernelGGL(k_dcore_sum, dim3(grid_for(pK, 256)), dim3(256), 0, c->stream, part.as<float>(), nwg,
+                           khat, o.K[0], dc);
+        TK_CHECK_LAUNCH();
+        c->sync();
+      } else if (pl.L_nz > 0) {
         hipLaunchKernelGGL(k_dcore, dim3(grid_for(pK, 256)), dim3(256), 0, c->stream, Yg, pl.L_nz, khat,
                            o.F32[0].as<float>(), o.K[0], o.kp[0], pl.row_slice.as<int32_t>(), dc);
         TK_CHECK_LAUNCH();
       } else {
-        TK_HIP(hipMemsetAsync(dc, 0, sizeof(float) * (size_t)pK, c->stream));
+        hipLaunchKernelGGL(k_fill_zero_f, dim3(grid_for(pK, 256)), dim3(256), 0, c->stream, dc, pK);
+        TK_CHECK_LAUNCH();
       }
       if (mem == TK_MEM_HOST) d2h(c, dcore, dc, (size_t)pK);
       c->sync();

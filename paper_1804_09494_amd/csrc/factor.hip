@@ -361,11 +361,14 @@ __global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__
 // W = V_K diag(lam)^(-1/2); a column with a non-positive or negligible
 // eigenvalue (relative to the largest) is zeroed and flagged (bit 1).
 // W = V_K diag(lam)^(-1/2).  A column whose eigenvalue is at or below the
-// Gram's rounding floor is not a direction of Y: the FP32 Gram carries an
-// error of about c u ||Y||_F^2 (u = 2^-24), so eigenvalues up to
-// RANK_FLOOR * trace(G) cannot be told from zero.  Such a column sets flag
-// bit 2 (rank deficiency) and gets W = 0.
-constexpr double RANK_FLOOR = 16.0 / 16777216.0;   // 16 u
+// Gram's rounding floor is not a direction of Y: an exactly zero singular
+// value of Y shows up in the FP32 Gram as an eigenvalue of the size of the
+// Gram's rounding error, below u ||Y||_F^2 (u = 2^-24), so eigenvalues up to
+// RANK_FLOOR * trace(G) are taken as zero.  Such a column sets flag bit 2
+// (rank deficiency) and gets W = 0.  Above the floor a small eigenvalue is
+// kept: its vector is only as accurate as the Gram allows, but it lies in the
+// range of Y.
+constexpr double RANK_FLOOR = 4.0 / 16777216.0;   // 4 u
 
 __global__ __launch_bounds__(256) void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam,
                                                 const double* __restrict__ G, int khat, int K, double* __restrict__ W,
@@ -480,6 +483,26 @@ static void complete_on_host(Ctx* c, int n) {
 }
 
 void complete_factor(Ctx* c, int n);
+
+// U = Y W (R x K, FP64 out) on the matrix cores for K <= 16, W khat x K in
+// FP64 (rounded to FP32 for the MFMA operands); `part` receives nwg x K x K
+// partial U^T U blocks (unused by callers that only want U).  Returns nwg.
+int uw_product(Ctx* c, const float* Y, int64_t R, int khat, const double* W, int K, double* U, double* part) {
+  TK_REQUIRE(K <= 16, TK_ERR_UNSUPPORTED, "Y W on the matrix cores: K above 16");
+  const int64_t ntile = std::max<int64_t>(1, ceil_div(R, 16));
+  const int nwg = (int)std::min<int64_t>(2048, ceil_div(ntile, 4));
+  const int kpad = (khat + 15) & ~15;
+  const size_t lds = sizeof(float) * (size_t)kpad * 16;
+  TK_REQUIRE(lds + 2048 <= c->lds_per_block, TK_ERR_UNSUPPORTED, "Y W: Khat too large for LDS");
+  if (khat % 4 == 0)
+    hipLaunchKernelGGL(k_uw_mfma<true>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+  else
+    hipLaunchKernelGGL(k_uw_mfma<false>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+  TK_CHECK_LAUNCH();
+  return nwg;
+}
+
+int uw_product_parts(int64_t R) { return (int)std::min<int64_t>(2048, ceil_div(std::max<int64_t>(1, ceil_div(R, 16)), 4)); }
 
 // zero a buffer (2-byte units) unless an earlier mode of this invocation failed
 __global__ void k_clear_unless(uint16_t* __restrict__ p, int64_t n16, const int* __restrict__ abort) {
@@ -611,6 +634,7 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
 
 // Complete factor n (rank-deficient penultimate matrix) on the host.
 void complete_factor(Ctx* c, int n) {
+  ++c->counters.rank_completions;
   complete_on_host(c, n);
   c->fac_dirty[n] = true;   // completion may use rows of empty slices
 }

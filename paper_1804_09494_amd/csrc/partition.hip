@@ -298,6 +298,64 @@ __global__ void k_bin_pptr(const int32_t* __restrict__ seg_ptr, const int64_t* _
   }
 }
 
+// ---- CoarseG (Section 5, coarse grained schemes): whole slices in a given
+// random order, cut into contiguous blocks; the slice at position t (element
+// prefix x_t in that order) goes to bin min(P-1, floor(x_t P / m)).
+
+__global__ void k_coarse_sizes(const int32_t* __restrict__ order, const int64_t* __restrict__ count, int64_t L,
+                               int64_t* __restrict__ csize, int32_t* __restrict__ nz) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t c = count[order[t]];
+    csize[t] = c;
+    nz[t] = c > 0;
+  }
+}
+
+// One segment per nonempty slice, in the given order.
+__global__ void k_coarse_segments(const int32_t* __restrict__ order, const int64_t* __restrict__ count,
+                                  const int64_t* __restrict__ cpre, const int32_t* __restrict__ sidx,
+                                  const int32_t* __restrict__ row_of, int64_t L, int64_t m, int64_t P,
+                                  int32_t* __restrict__ seg_row, int64_t* __restrict__ seg_begin,
+                                  int32_t* __restrict__ seg_slot, int64_t* __restrict__ seg_bin,
+                                  int32_t* __restrict__ seg_of_slice) {
+  for (int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; t < L; t += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t l = order[t];
+    if (count[l] == 0) continue;
+    const int32_t k = sidx[t];
+    seg_row[k] = row_of[l];
+    seg_begin[k] = cpre[t];
+    seg_slot[k] = -1;
+    const int64_t b = cpre[t] * P / m;
+    seg_bin[k] = b < P - 1 ? b : P - 1;
+    seg_of_slice[l] = k;
+  }
+}
+
+// seg_ptr[p] = number of segments in bins below p (segment bins never
+// decrease); bin_ptr[p] = the layout offset of its first segment.
+__global__ void k_coarse_bins(const int64_t* __restrict__ seg_bin, const int64_t* __restrict__ seg_begin, int64_t S,
+                              int64_t P, int64_t m, int32_t* __restrict__ seg_ptr, int64_t* __restrict__ bin_ptr,
+                              int64_t* __restrict__ load, int64_t* __restrict__ nseg) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p <= P; p += (int64_t)gridDim.x * blockDim.x) {
+    int64_t lo = 0, hi = S;
+    while (lo < hi) {
+      const int64_t mid = lo + ((hi - lo) >> 1);
+      if (seg_bin[mid] < p) lo = mid + 1; else hi = mid;
+    }
+    seg_ptr[p] = (int32_t)lo;
+    bin_ptr[p] = lo < S ? seg_begin[lo] : m;
+    if (p < P) {
+      int64_t lo2 = lo, hi2 = S;   // first segment in a bin above p
+      while (lo2 < hi2) {
+        const int64_t mid = lo2 + ((hi2 - lo2) >> 1);
+        if (seg_bin[mid] <= p) lo2 = mid + 1; else hi2 = mid;
+      }
+      nseg[p] = lo2 - lo;
+      load[p] = (lo2 < S ? seg_begin[lo2] : m) - bin_ptr[p];
+    }
+  }
+}
+
 static int bits_for_len(int64_t L) {
   int b = 0;
   while (b < 32 && ((int64_t)1 << b) < L) ++b;
@@ -312,8 +370,12 @@ static T fetch(Ctx* c, const T* d) {
   return h;
 }
 
+static void build_plan_coarse(Ctx* c, ModePlan& pl, int N, int n, int64_t L, int64_t m, Buf* idx, const float* vals,
+                              bool keep_order, const int32_t* order, Buf& skey, Buf& sperm, Buf& sstart, Buf& count,
+                              Buf& row_of);
+
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
-                int64_t khat, int tile_w, int64_t wg_default, bool keep_order) {
+                int64_t khat, int tile_w, int64_t wg_default, bool keep_order, const int32_t* coarse_order) {
   const int B = 256;
   const int64_t L = dims[n];
   pl = ModePlan();
@@ -367,7 +429,6 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   hipLaunchKernelGGL(k_labels, dim3(grid_for(L, B)), dim3(B), 0, c->stream, rank_of.as<int32_t>(),
                      row_of.as<int32_t>(), count.as<int64_t>(), L, Lnz, pl.label.as<int32_t>());
   TK_CHECK_LAUNCH();
-  count.release();
 
   // 3. number of bins and the limit
   const int cap = c->opt.lds_rows_cap >= 3 ? std::min(c->opt.lds_rows_cap, ttm_rows_cap(c, tile_w))
@@ -378,6 +439,12 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   pl.P = P;
   pl.limit = limit;
   pl.rows_cap = cap;
+  if (coarse_order) {
+    build_plan_coarse(c, pl, N, n, L, m, idx, vals, keep_order, coarse_order, skey, sperm, sstart, count, row_of);
+    pl.row_of = std::move(row_of);
+    return;
+  }
+  count.release();
 
   // 4. stage 1
   Buf cand(c, 8 * (size_t)P), tmin(c, 8);
@@ -567,6 +634,119 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
                      pl.bin_ptr.as<int64_t>(), t_hat, P, pl.seg_ptr.as<int32_t>(), pl.seg_begin.as<int64_t>(),
                      pl.seg_pbegin.as<int64_t>(), ii, no, vals, oo, vals ? pl.lay_val.as<float>() : nullptr,
                      keep_order ? pl.elem_order.as<uint32_t>() : nullptr,
+                     vals ? nullptr : pl.order_pad.as<uint32_t>());
+  TK_CHECK_LAUNCH();
+  c->sync();
+  pl.row_of = std::move(row_of);
+}
+
+__global__ void k_coarse_layout(const uint32_t* __restrict__ skey, const uint32_t* __restrict__ sperm, int64_t m,
+                                const int64_t* __restrict__ sstart, const int32_t* __restrict__ seg_of_slice,
+                                const int64_t* __restrict__ seg_begin, const int64_t* __restrict__ seg_pbegin,
+                                IdxIn in_idx, int n_other, const float* __restrict__ vals, IdxOut out_idx,
+                                float* __restrict__ out_val, uint32_t* __restrict__ elem_order,
+                                uint32_t* __restrict__ order_pad) {
+  for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
+    const uint32_t l = skey[s];
+    const uint32_t e = sperm[s];
+    const int64_t r = s - sstart[l];
+    const int32_t k = seg_of_slice[l];
+    const int64_t pd = seg_pbegin[k] + r;
+    for (int j = 0; j < n_other; ++j) out_idx.p[j][pd] = in_idx.p[j][e];
+    if (out_val) out_val[pd] = vals[e];
+    if (elem_order) elem_order[seg_begin[k] + r] = e;
+    if (order_pad) order_pad[pd] = e;
+  }
+}
+
+static void build_plan_coarse(Ctx* c, ModePlan& pl, int N, int n, int64_t L, int64_t m, Buf* idx, const float* vals,
+                              bool keep_order, const int32_t* order, Buf& skey, Buf& sperm, Buf& sstart, Buf& count,
+                              Buf& row_of) {
+  const int B = 256;
+  const int64_t P = pl.P;
+  const int64_t S = pl.L_nz;              // one segment per nonempty slice
+  const int64_t S1 = S > 0 ? S : 1;
+  pl.whole_slices = true;
+  pl.n_stage1 = S;
+  pl.n_bad = 0;
+  pl.n_slots = 0;
+  pl.fix_rows = 0;
+  pl.S = S;
+  Buf csize(c, 8 * (size_t)L), cpre(c, 8 * (size_t)L), nz(c, 4 * (size_t)L), sidx(c, 4 * (size_t)L);
+  hipLaunchKernelGGL(k_coarse_sizes, dim3(grid_for(L, B)), dim3(B), 0, c->stream, order, count.as<int64_t>(), L,
+                     csize.as<int64_t>(), nz.as<int32_t>());
+  TK_CHECK_LAUNCH();
+  exclusive_scan_i64(c, csize.as<int64_t>(), cpre.as<int64_t>(), L);
+  exclusive_scan_i32(c, nz.as<int32_t>(), sidx.as<int32_t>(), L);
+  pl.seg_row.alloc(c, 4 * (size_t)S1);
+  pl.seg_begin.alloc(c, 8 * (size_t)(S + 1));
+  pl.seg_slot.alloc(c, 4 * (size_t)S1);
+  pl.seg_ptr.alloc(c, 4 * (size_t)(P + 1));
+  pl.bin_ptr.alloc(c, 8 * (size_t)(P + 1));
+  Buf seg_bin(c, 8 * (size_t)S1), seg_of_slice(c, 4 * (size_t)L), load(c, 8 * (size_t)P), nseg(c, 8 * (size_t)P),
+      mx(c, 8);
+  hipLaunchKernelGGL(k_coarse_segments, dim3(grid_for(L, B)), dim3(B), 0, c->stream, order, count.as<int64_t>(),
+                     cpre.as<int64_t>(), sidx.as<int32_t>(), row_of.as<int32_t>(), L, m > 0 ? m : 1, P,
+                     pl.seg_row.as<int32_t>(), pl.seg_begin.as<int64_t>(), pl.seg_slot.as<int32_t>(),
+                     seg_bin.as<int64_t>(), seg_of_slice.as<int32_t>());
+  TK_CHECK_LAUNCH();
+  h2d(c, pl.seg_begin.as<int64_t>() + S, &m, 1);
+  hipLaunchKernelGGL(k_coarse_bins, dim3(grid_for(P + 1, B)), dim3(B), 0, c->stream, seg_bin.as<int64_t>(),
+                     pl.seg_begin.as<int64_t>(), S, P, m, pl.seg_ptr.as<int32_t>(), pl.bin_ptr.as<int64_t>(),
+                     load.as<int64_t>(), nseg.as<int64_t>());
+  TK_CHECK_LAUNCH();
+  reduce_max_i64(c, nseg.as<int64_t>(), mx.as<int64_t>(), P);
+  pl.R_max = fetch(c, mx.as<int64_t>());
+  reduce_max_i64(c, load.as<int64_t>(), mx.as<int64_t>(), P);
+  pl.E_max = fetch(c, mx.as<int64_t>());
+  csize.release();
+  cpre.release();
+  nz.release();
+  sidx.release();
+  count.release();
+
+  // padded segment offsets, then the layout
+  {
+    Buf plen(c, 8 * (size_t)S1), bsize(c, 8 * (size_t)P);
+    pl.seg_pbegin.alloc(c, 8 * (size_t)(S + 1));
+    hipLaunchKernelGGL(k_seg_padlen, dim3(grid_for(S, B)), dim3(B), 0, c->stream, pl.seg_begin.as<int64_t>(), S,
+                       plen.as<int64_t>());
+    TK_CHECK_LAUNCH();
+    exclusive_scan_i64(c, plen.as<int64_t>(), pl.seg_pbegin.as<int64_t>(), S);
+    pl.m_pad = S > 0 ? fetch(c, pl.seg_pbegin.as<int64_t>() + S - 1) + fetch(c, plen.as<int64_t>() + S - 1) : 0;
+    h2d(c, pl.seg_pbegin.as<int64_t>() + S, &pl.m_pad, 1);
+    c->sync();
+    pl.bin_pptr.alloc(c, 8 * (size_t)(P + 1));
+    hipLaunchKernelGGL(k_bin_pptr, dim3(grid_for(P + 1, B)), dim3(B), 0, c->stream, pl.seg_ptr.as<int32_t>(),
+                       pl.seg_pbegin.as<int64_t>(), P, pl.bin_pptr.as<int64_t>(), bsize.as<int64_t>());
+    TK_CHECK_LAUNCH();
+    reduce_max_i64(c, bsize.as<int64_t>(), mx.as<int64_t>(), P);
+    pl.E_pad_max = fetch(c, mx.as<int64_t>());
+  }
+  const int64_t m1 = pl.m_pad > 0 ? pl.m_pad : 1;
+  IdxIn ii{};
+  IdxOut oo{};
+  int no = 0;
+  for (int j = 0; j < N; ++j) {
+    if (j == n) continue;
+    pl.lay_idx[no].alloc(c, 4 * (size_t)m1);
+    ii.p[no] = idx[j].as<int32_t>();
+    oo.p[no] = pl.lay_idx[no].as<int32_t>();
+    ++no;
+  }
+  for (int j = 0; j < no; ++j) TK_HIP(hipMemsetAsync(oo.p[j], 0, 4 * (size_t)m1, c->stream));
+  if (vals) {
+    pl.lay_val.alloc(c, 4 * (size_t)m1);
+    TK_HIP(hipMemsetAsync(pl.lay_val.get(), 0, 4 * (size_t)m1, c->stream));
+  } else {
+    pl.order_pad.alloc(c, 4 * (size_t)m1);
+    TK_HIP(hipMemsetAsync(pl.order_pad.get(), 0xff, 4 * (size_t)m1, c->stream));
+  }
+  if (keep_order) pl.elem_order.alloc(c, 4 * (size_t)(m > 0 ? m : 1));
+  hipLaunchKernelGGL(k_coarse_layout, dim3(grid_for(m, B)), dim3(B), 0, c->stream, skey.as<uint32_t>(),
+                     sperm.as<uint32_t>(), m, sstart.as<int64_t>(), seg_of_slice.as<int32_t>(),
+                     pl.seg_begin.as<int64_t>(), pl.seg_pbegin.as<int64_t>(), ii, no, vals, oo,
+                     vals ? pl.lay_val.as<float>() : nullptr, keep_order ? pl.elem_order.as<uint32_t>() : nullptr,
                      vals ? nullptr : pl.order_pad.as<uint32_t>());
   TK_CHECK_LAUNCH();
   c->sync();

@@ -225,6 +225,91 @@ __global__ __launch_bounds__(256) void k_ttm_cols(TtmArgs A) {
   }
 }
 
+// ---- TTM-chain without a partition (ablation baseline) ---------------------------------------
+//
+// The merged element list in canonical order, cut into contiguous chunks of
+// TTMA_CHUNK elements per wave; lanes over columns as in k_ttm_cols.  A wave
+// keeps the running sum of the current mode-n slice in registers and adds it
+// to Y with FP32 atomics when the slice changes (in canonical order the
+// mode-1 index changes rarely, the others almost every element).  The order
+// of the atomic additions depends on timing: results are not deterministic.
+constexpr int TTMA_CHUNK = 512;
+
+struct TtmAtomicArgs {
+  const int32_t* idx[8];    // canonical coordinates of every mode
+  const int32_t* label[8];  // storage label of each index (the factor copies' row order)
+  const float* val;
+  const float* F[8];
+  int fstride[8];
+  int Kj[8];
+  int N, n;
+  const int32_t* row_of;    // compact row of each mode-n slice
+  int khat;
+  int64_t m;
+  float* Y;
+};
+
+template <int NO>
+__global__ __launch_bounds__(256) void k_ttm_atomic(TtmAtomicArgs A) {
+  const int no = NO > 0 ? NO : A.N - 1;
+  const int lane = threadIdx.x & 63;
+  const int64_t wave_id = (int64_t)blockIdx.x * 4 + uni(threadIdx.x >> 6);
+  const int col0 = blockIdx.y * TTMV_TILE;
+  const int64_t cs = wave_id * TTMA_CHUNK;
+  if (cs >= A.m) return;
+  const int64_t ce = min(cs + (int64_t)TTMA_CHUNK, A.m);
+  int oj[7];                // the other modes, ascending
+  {
+    int q = 0;
+    for (int j = 0; j < A.N; ++j)
+      if (j != A.n) oj[q++] = j;
+  }
+  int off[TTMV_CPL][7];
+  bool colok[TTMV_CPL];
+#pragma unroll
+  for (int u = 0; u < TTMV_CPL; ++u) {
+    const int col = col0 + lane + 64 * u;
+    colok[u] = col < A.khat;
+    int rest = colok[u] ? col : 0;
+    for (int q = 0; q < no; ++q) {
+      off[u][q] = rest % A.Kj[oj[q]];
+      rest /= A.Kj[oj[q]];
+    }
+  }
+  float acc[TTMV_CPL] = {};
+  int cur = -1;
+  auto flush = [&]() __attribute__((always_inline)) {
+    if (cur >= 0) {
+      float* y = A.Y + (int64_t)A.row_of[cur] * A.khat + col0 + lane;
+#pragma unroll
+      for (int u = 0; u < TTMV_CPL; ++u)
+        if (colok[u]) atomicAdd(y + 64 * u, acc[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < TTMV_CPL; ++u) acc[u] = 0.f;
+  };
+  for (int64_t e = cs; e < ce; ++e) {
+    const int l = A.idx[A.n][e];            // uniform: every lane reads the same element
+    if (l != cur) {
+      flush();
+      cur = l;
+    }
+    const float v = A.val[e];
+    float p[TTMV_CPL];
+#pragma unroll
+    for (int u = 0; u < TTMV_CPL; ++u) p[u] = v;
+    for (int q = 0; q < no; ++q) {
+      const int j = oj[q];
+      const int64_t r = (int64_t)A.label[j][A.idx[j][e]] * A.fstride[j];
+#pragma unroll
+      for (int u = 0; u < TTMV_CPL; ++u) p[u] *= A.F[j][r + off[u][q]];
+    }
+#pragma unroll
+    for (int u = 0; u < TTMV_CPL; ++u) acc[u] += p[u];
+  }
+  flush();
+}
+
 // ---- three-mode TTM-chain on the matrix cores ----------------------------------------------
 //
 // For the elements of one slice, Y[row] viewed as K_a x K_b is
@@ -868,6 +953,43 @@ __global__ void k_fill_zero(float* __restrict__ p, int64_t n) {
     p[i] = 0.f;
 }
 
+// TTM-chain of the whole merged list along mode n with atomics (TK_TTM_ATOMIC).
+static void ttm_atomic(Ctx* c, int n, float* Y) {
+  const ModePlan& pl = c->plan[n];
+  TtmAtomicArgs a{};
+  for (int j = 0; j < c->N; ++j) {
+    a.idx[j] = c->idx_c[j].as<int32_t>();
+    a.label[j] = c->plan[j].label.as<int32_t>();
+    a.F[j] = c->F32[j].as<float>();
+    a.fstride[j] = c->kp32[j];
+    a.Kj[j] = c->K[j];
+  }
+  a.val = c->val_c.as<float>();
+  a.N = c->N;
+  a.n = n;
+  a.row_of = pl.row_of.as<int32_t>();
+  a.khat = (int)pl.khat;
+  a.m = c->m;
+  a.Y = Y;
+  const int64_t ny = pl.L_nz * pl.khat;
+  if (ny > 0) {
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(ny, 256, 4096)), dim3(256), 0, c->stream, Y, ny);
+    TK_CHECK_LAUNCH();
+  }
+  if (c->m == 0) return;
+  if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
+  const int64_t waves = ceil_div(c->m, TTMA_CHUNK);
+  const dim3 g((unsigned)ceil_div(waves, 4), (unsigned)ceil_div(pl.khat, TTMV_TILE)), b(256);
+  switch (c->N - 1) {
+    case 1: hipLaunchKernelGGL(k_ttm_atomic<1>, g, b, 0, c->stream, a); break;
+    case 2: hipLaunchKernelGGL(k_ttm_atomic<2>, g, b, 0, c->stream, a); break;
+    case 3: hipLaunchKernelGGL(k_ttm_atomic<3>, g, b, 0, c->stream, a); break;
+    default: hipLaunchKernelGGL(k_ttm_atomic<0>, g, b, 0, c->stream, a); break;
+  }
+  TK_CHECK_LAUNCH();
+  if (c->ev_ttm[1]) TK_HIP(hipEventRecord(c->ev_ttm[1], c->stream));
+}
+
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
              const float* lay_val, int64_t m, float* Y, bool bf16, float* partial) {
   TtmArgs a{};
@@ -908,7 +1030,8 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     return;
   }
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
-  if (ttm_uses_mfma(N, K, n, kp)) {
+  const bool vector_only = pl.whole_slices || c->opt.ttm_kernel == TK_TTM_VECTOR;
+  if (!vector_only && ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const size_t lds = 12 * (size_t)Epad + sizeof(float) * 512 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
@@ -917,7 +1040,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
     else
       hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
     TK_CHECK_LAUNCH();
-  } else if (ttm_uses_mfma4(N, K, n, kp)) {
+  } else if (!vector_only && ttm_uses_mfma4(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const int nseg_pad = (int)((pl.R_max + 3) & ~(int64_t)3);
     const size_t lds = 3 * sizeof(int) * (size_t)nseg_pad + 16 * (size_t)Epad + sizeof(float) * 4 * 768 +
@@ -975,6 +1098,10 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
 // bf16: the precision form's BF16 Kronecker tiles on the matrix cores (where a
 // matrix-core kernel runs; other shapes stay FP32).
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial) {
+  if (c->opt.ttm_kernel == TK_TTM_ATOMIC) {
+    ttm_atomic(c, n, Y);
+    return;
+  }
   const float* F[8];
   for (int j = 0; j < c->N; ++j) F[j] = c->F32[j].as<float>();
   ttm_run(c, c->plan[n], c->N, n, c->K, F, c->kp32, c->plan[n].lay_val.as<float>(), c->m, Y, bf16, partial);

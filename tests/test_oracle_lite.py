@@ -199,3 +199,35 @@ def test_cpp_lite_zipf_sizes():
     rng = np.random.default_rng(4)
     sizes = (rng.zipf(1.3, 20_000) % 5000).tolist()
     _cpp_equals_python(sizes, 997)
+
+
+# ---- CoarseG (Section 5) ----------------------------------------------------------------------
+
+def test_coarse_g_hand_example():
+    """Sizes 5,1,3,1 (m = 10) in the order 2,0,3,1 over P = 3 bins: prefixes
+    0, 3, 8, 9 give bins floor(0*3/10)=0, floor(9/10)=0, floor(24/10)=2,
+    floor(27/10)=2; bin 1 stays empty although bin 0 holds 8 elements."""
+    r = lite.coarse_g([5, 1, 3, 1], 3, [2, 0, 3, 1])
+    assert r.bin_slices == [[(2, 3), (0, 5)], [], [(3, 1), (1, 1)]]
+    assert r.load == [8, 0, 2]
+    assert r.stats["E_max"] == 8 and r.stats["R_sum"] == 4 and r.stats["R_max"] == 2 and r.stats["n_bad"] == 0
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.lists(st.integers(min_value=0, max_value=60), min_size=1, max_size=80),
+       st.integers(min_value=1, max_value=40), st.randoms(use_true_random=False))
+def test_coarse_g_properties(sizes, P, rnd):
+    """Every slice whole in one bin (no bad slices, R_sum = L_nonempty, the
+    optimum the paper states for coarse grained schemes), blocks contiguous
+    in the given order, every element placed."""
+    order = list(range(len(sizes)))
+    rnd.shuffle(order)
+    r = lite.coarse_g(sizes, P, order)
+    nz = [l for l in order if sizes[l] > 0]
+    assert r.stats["n_bad"] == 0
+    assert r.stats["R_sum"] == len(nz)
+    assert sum(r.load) == sum(sizes)
+    flat = [s for b in r.bin_slices for s, _ in b]
+    assert flat == nz                                   # bins in order hold the slices in the given order
+    bins = [r.pieces[l][0][0] for l in nz]
+    assert bins == sorted(bins)
