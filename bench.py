@@ -335,6 +335,53 @@ def run_ablation(args):
     print(json.dumps(out), flush=True)
 
 
+def run_eig_ablation(args):
+    """The SVD step's two routes on one GPU: the Gram formed (then dense or
+    block Krylov on G) against matrix-free block Krylov on Y, for a
+    four-mode tensor of the precision form's shape at a tenth of its size
+    (200,000 x 100,000 x 10,000 x 500, 5e7 draws, Zipf 0.9/1.1/1.3/0.7,
+    lognormal values) at ranks 10 (Khat = 1000) and 16 (Khat = 4096).
+    Reports the HOOI invocation time, its SVD-step part and the fits."""
+    import torch
+    import synth
+    import paper_1804_09494_amd as P
+    torch.cuda.set_device(0)
+    dims, nnz = (200_000, 100_000, 10_000, 500), int(5e7 * args.scale)
+    idx, vals = synth.make_tensor(dims, nnz, "zipf", (0.9, 1.1, 1.3, 0.7), "lognormal", seed=2020)
+    idx_d = [torch.from_numpy(i).cuda() for i in idx]
+    vals_d = torch.from_numpy(vals).cuda()
+    out = {"metric": "HOOI invocation ms, Gram route vs matrix-free SVD step",
+           "config": {"dims": dims, "draws": nnz}, "runs": []}
+    iters = max(1, args.steps)
+    for K in (10, 16):
+        ranks = (K,) * 4
+        F0 = synth.orthonormal_init(2121, dims, ranks)
+        for method in ("gram", "matfree"):
+            ctx = P.TuckerContext(0, keep_elem_order=0, eig_method=method)
+            ctx.load_coo(idx_d, vals_d, dims)
+            ctx.set_ranks(ranks)
+            for n, F in enumerate(F0):
+                ctx.set_factor(n, np.ascontiguousarray(F))
+            ctx.hooi_iterate(1)   # warm-up
+            for n, F in enumerate(F0):
+                ctx.set_factor(n, np.ascontiguousarray(F))
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fits = ctx.hooi_iterate(iters)
+            torch.cuda.synchronize()
+            ms = (time.perf_counter() - t0) * 1e3 / iters
+            tm = ctx.timings()
+            run = {"ranks": K, "khat": K ** 3, "method": method, "ms_per_invocation": round(ms, 3),
+                   "gram_ms": round(tm.get("gram", 0.0) / iters, 3), "eig_ms": round(tm.get("eig", 0.0) / iters, 3),
+                   "ttm_ms": round(sum(v for k, v in tm.items() if k.startswith("ttm[")) / iters, 3),
+                   "fits": fits, "counters": ctx.counters()}
+            print(json.dumps(run), file=sys.stderr, flush=True)
+            out["runs"].append(run)
+            del ctx
+            torch.cuda.empty_cache()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -348,6 +395,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--ablation", action="store_true", help="partition ablations (Lite, CoarseG, atomics)")
+    ap.add_argument("--eig-ablation", action="store_true", help="SVD step: Gram route vs matrix-free")
     args = ap.parse_args()
     if args.summarize_profile:
         import synth
@@ -363,6 +411,9 @@ def main():
         return
     if args.ablation:
         run_ablation(args)
+        return
+    if args.eig_ablation:
+        run_eig_ablation(args)
         return
 
     import torch
@@ -431,6 +482,19 @@ def main():
     print(f"# per-step ms fp32: " + ", ".join(f"{k}={v / K:.3f}" for k, v in tm.items()), file=sys.stderr, flush=True)
     print(f"# per-step ms bf16: " + ", ".join(f"{k}={v / K:.3f}" for k, v in bf_tm.items()), file=sys.stderr,
           flush=True)
+    # HOSVD initialisation (Kronecker-sketched range finder, one Jacobi sweep
+    # over Gaussian sketches), then one invocation from it
+    sk = [torch.from_numpy(S).cuda() for S in synth.gaussian_factors(7331, dims, ranks)]
+    ctx.set_options(prec="fp32")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hosvd_fit = ctx.init_hosvd(sk)
+    torch.cuda.synchronize()
+    hosvd_ms = (time.perf_counter() - t0) * 1e3
+    del sk
+    hosvd_next = ctx.hooi_iterate(1)[0]
+    print(f"# HOSVD init {hosvd_ms:.1f} ms, fit {hosvd_fit:.8f}, after one invocation {hosvd_next:.8f} "
+          f"(from the random init: {fits[0]:.8f})", file=sys.stderr, flush=True)
     counters = ctx.counters()
     print(f"# counters {counters}", file=sys.stderr, flush=True)
     del ctx
@@ -466,6 +530,8 @@ def main():
         "ttm_ms_per_mode": [round(x, 4) for x in ttm_ms],
         "ttm_kernel_ms_per_mode": [round(x, 4) for x in kern_ms],
         "step_ms": {k: round(v / K, 4) for k, v in tm.items()},
+        "hosvd_init": {"ms": round(hosvd_ms, 3), "fit": hosvd_fit, "fit_after_one_invocation": hosvd_next,
+                       "random_init_fit_after_one_invocation": fits[0] if fits else None},
         "load_s": round(load_s, 2),
         "partition_s": round(part_s, 3),
         "partition_stats": stats,

@@ -82,6 +82,15 @@ typedef enum {
                           running row sums added to Y with FP32 atomics when the mode-n index changes
                           (not deterministic); an ablation baseline */
 } tk_ttm_kernel;
+/* How the SVD step of HOOI reaches the eigenpairs of Y^T Y (Section 3, "SVD Component"). */
+typedef enum {
+  TK_EIG_AUTO = 0,     /* the Gram route below Khat = TK_MATFREE_MIN_KHAT, matrix-free from there (K <= 31) */
+  TK_EIG_GRAM = 1,     /* form G = Y^T Y (Khat x Khat, matrix cores), then the dense solver (Khat up to
+                          about 100) or block Krylov on G */
+  TK_EIG_MATFREE = 2   /* block Krylov on Y itself, never squared: each block product is Y^T (Y X), two
+                          passes over Y; Khat >= 192 and K <= 31 (smaller Khat takes the Gram route) */
+} tk_eig_method;
+#define TK_MATFREE_MIN_KHAT 4096
 
 typedef struct {
   int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16 (the precision form): the
@@ -102,9 +111,11 @@ typedef struct {
   double eig_tol;                 /* block-Krylov eigensolve (Khat >= 192): bound on the estimated
                                      subspace error sqrt(2) * residual * theta_1 / (theta_K - theta_{K+1})
                                      (sin-theta theorem); a larger estimate reruns the mode's eigensolve
-                                     with the dense solver.  0 (default) = 1e-7 */
+                                     with the dense solver (the matrix-free route first forms G and takes
+                                     the Gram route).  0 (default) = 1e-7 */
   int32_t partition;              /* tk_partition (default TK_PART_LITE); read by tk_set_ranks */
   int32_t ttm_kernel;             /* tk_ttm_kernel (default TK_TTM_AUTO) */
+  int32_t eig_method;             /* tk_eig_method (default TK_EIG_AUTO) */
 } tk_options;
 
 /* Lite statistics of one mode (Section 4 metrics 1-3; Theorem 6.1). */
@@ -249,6 +260,22 @@ tk_status tk_ttm_chain_noalloc(tk_ctx* ctx, int n, float* Y, int32_t* row_slice)
  * fit_per_iter (host, may be NULL) gets 1 - sqrt(max(0, ||T||^2 - ||G||^2))/||T||
  * after each invocation. */
 tk_status tk_hooi_iterate(tk_ctx* ctx, int iters, double* fit_per_iter);
+
+/* Initial factors from a higher-order SVD of T (Section 2.2: HOOI starts from
+ * HOSVD factors or from random ones).  F_n becomes the leading K_n left
+ * singular vectors of T_(n) Omega_n, where Omega_n is the Kronecker product of
+ * the sketch matrices Omega_j, j != n: a randomized range finder for T_(n)
+ * whose test matrix is applied through the TTM-chain (eq. 1), so
+ * T_(n) Omega_n = Y_(n) with the sketches in place of the factors.  sketch[j]
+ * is L_j x K_j row-major FP64 (host or device per mem), drawn by the caller
+ * (e.g. independent standard normal entries); it is read, not kept.  For a
+ * tensor of multilinear rank at most (K_1..K_N) and sketches in general
+ * position the result spans exactly the column space of every T_(n), i.e. it
+ * is the truncated HOSVD.  All modes use the sketches (a Jacobi sweep) in FP32
+ * whatever the options say; rank-deficient modes are completed as in
+ * tk_hooi_iterate.  fit (host, may be NULL) gets the fit of the initial
+ * decomposition.  Errors as tk_hooi_iterate; TK_ERR_STATE before tk_set_ranks. */
+tk_status tk_init_hosvd(tk_ctx* ctx, const double* const* sketch, tk_mem mem, double* fit);
 /* Core G = T x_1 F_1^T ... x_N F_N^T with the current factors (FP64, prod K
  * entries, first index fastest) and the fit; either output may be NULL. */
 tk_status tk_core(tk_ctx* ctx, double* core, double* fit, tk_mem mem);

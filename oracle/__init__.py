@@ -13,6 +13,8 @@ Modules
               (Section 4 metrics 1-3, Section 6, Figure "Lite", Theorem 6.1)
   ttm         the TTM-chain through the Kronecker reformulation (eq. 1, Appendix A)
   hooi        SVD step, HOOI invocation, core and fit (Section 2.2, Figure "HOOI")
+  hosvd       HOSVD initialisation through a Kronecker-sketched range finder
+              (Section 1 "HOOI Procedure", Section 2.2)
   completion  Tucker-completion loss and its gradient (the differentiation form;
               not in the paper, plain calculus on the Tucker model of Section 2.2)
 
@@ -24,4 +26,4 @@ Parity status: every function is pinned by a test outside itself (dense
 unfoldings with numpy.kron, brute force, the paper's worked Lite example,
 Theorem 6.1's bounds, LAPACK, finite differences).  None is "parity unpinned".
 """
-from . import coo, lite, ttm, hooi, completion  # noqa: F401
+from . import coo, lite, ttm, hooi, hosvd, completion  # noqa: F401

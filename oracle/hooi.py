@@ -124,14 +124,3 @@ def projector_distance(U, V):
     # ||UU^T - VV^T||_F^2 = ||U^TU||^2 + ||V^TV||^2 - 2||U^TV||^2 (no L x L matrices)
     a = np.linalg.norm(U.T @ U) ** 2 + np.linalg.norm(V.T @ V) ** 2 - 2 * np.linalg.norm(U.T @ V) ** 2
     return float(np.sqrt(max(a, 0.0)) / np.linalg.norm(V.T @ V))
-
-
-def canonical_signs(U):
-    """Flip columns so that each column's largest-magnitude entry is positive
-    (ties: lowest row)."""
-    U = np.array(U, np.float64)
-    for k in range(U.shape[1]):
-        i = int(np.argmax(np.abs(U[:, k])))
-        if U[i, k] < 0:
-            U[:, k] = -U[:, k]
-    return U

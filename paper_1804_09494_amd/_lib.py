@@ -24,13 +24,15 @@ TK_NOALLOC_SCRATCH_BYTES = 32 << 20
 TK_ASSUME_UNIQUE = 1
 TK_PART_LITE, TK_PART_COARSE = 0, 1
 TK_TTM_AUTO, TK_TTM_VECTOR, TK_TTM_ATOMIC = 0, 1, 2
+TK_EIG_AUTO, TK_EIG_GRAM, TK_EIG_MATFREE = 0, 1, 2
+TK_MATFREE_MIN_KHAT = 4096
 
 
 class tk_options(ctypes.Structure):
     _fields_ = [("prec", c_i32), ("sweep", c_i32), ("wg_nnz_target", c_i64), ("lds_rows_cap", c_i32),
                 ("refine", c_i32), ("mem_limit_bytes", c_i64),
                 ("complete_rank_deficient", c_i32), ("keep_elem_order", c_i32), ("eig_tol", c_f64),
-                ("partition", c_i32), ("ttm_kernel", c_i32)]
+                ("partition", c_i32), ("ttm_kernel", c_i32), ("eig_method", c_i32)]
 
 
 TK_ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
@@ -73,6 +75,7 @@ SIGNATURES = [
     ("tk_ttm_chain", c_int, [c_void_p, c_int, c_void_p, c_void_p, c_int]),
     ("tk_ttm_chain_noalloc", c_int, [c_void_p, c_int, c_void_p, c_void_p]),
     ("tk_hooi_iterate", c_int, [c_void_p, c_int, c_void_p]),
+    ("tk_init_hosvd", c_int, [c_void_p, c_void_p, c_int, c_void_p]),
     ("tk_core", c_int, [c_void_p, c_void_p, ctypes.POINTER(c_f64), c_int]),
     ("tk_get_timings", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int)]),
     ("tk_get_counters", c_int, [c_void_p, c_void_p, c_void_p, ctypes.POINTER(c_int)]),

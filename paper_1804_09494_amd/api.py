@@ -136,6 +136,10 @@ class TuckerContext:
         if kern is not None:
             o.ttm_kernel = {"auto": _lib.TK_TTM_AUTO, "vector": _lib.TK_TTM_VECTOR,
                             "atomic": _lib.TK_TTM_ATOMIC}.get(kern, kern)
+        eig = kw.pop("eig_method", None)
+        if eig is not None:
+            o.eig_method = {"auto": _lib.TK_EIG_AUTO, "gram": _lib.TK_EIG_GRAM,
+                            "matfree": _lib.TK_EIG_MATFREE}.get(eig, eig)
         sweep = kw.pop("sweep", None)
         if sweep is not None:
             o.sweep = {"gauss_seidel": _lib.TK_SWEEP_GAUSS_SEIDEL, "jacobi": _lib.TK_SWEEP_JACOBI}.get(sweep, sweep)
@@ -275,6 +279,22 @@ class TuckerContext:
         fits = np.zeros(max(iters, 1), np.float64)
         self._check(self._L.tk_hooi_iterate(self._h, iters, _ptr(fits)))
         return fits[:iters].tolist()
+
+    def init_hosvd(self, sketches):
+        """tk_init_hosvd: factors from the Kronecker-sketched HOSVD; sketches[j]
+        is L_j x K_j float64 (all host arrays or all device tensors).
+        Returns the fit of the initial decomposition."""
+        if len(sketches) != self.N:
+            raise ValueError(f"need {self.N} sketch matrices")
+        mem = _mem_of(sketches[0])
+        for j, S in enumerate(sketches):
+            _check_dtype(S, np.float64, "sketch")
+            if tuple(S.shape) != (self.dims[j], self.ranks[j]) or _mem_of(S) != mem:
+                raise ValueError(f"sketch {j} must be {self.dims[j]} x {self.ranks[j]}, all on one side")
+        ptrs = (c_void_p * self.N)(*[_ptr(S) for S in sketches])
+        fit = c_f64()
+        self._check(self._L.tk_init_hosvd(self._h, ptrs, mem, ctypes.byref(fit)))
+        return fit.value
 
     def core(self):
         out = np.empty(int(np.prod(self.ranks)), np.float64)

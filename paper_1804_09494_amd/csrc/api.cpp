@@ -21,7 +21,10 @@ namespace tk {
 
 void gram(Ctx* c, const float* Y, int64_t R, int khat, double* G, bool bf16);
 void eig_topk(Ctx* c, const double* G, int n0, int K, double* lam_k, double* VK, int mode);
-bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* Gfull, const double* lam_k,
+void eig_topk_matfree(Ctx* c, const float* Y, int64_t R, int khat, int K, double* lam_k, double* VK, int mode,
+                      double* diag);
+bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* gdiag, int64_t dstride,
+                 const double* lam_k,
                  const double* VK, int* flag_dev, bool deferred);
 void complete_factor(Ctx* c, int n);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
@@ -100,13 +103,23 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
     sm.marks.push_back({name, {a, b}});
     return b;
   };
-  int64_t maxY = 0, maxKh = 0;
+  // the SVD step's route per mode: the Gram formed, or matrix-free on Y
+  auto matfree = [&](int n) {
+    const int64_t kh = c->plan[n].khat;
+    if (kh < 192 || c->K[n] > 31) return false;
+    if (c->opt.eig_method == TK_EIG_MATFREE) return true;
+    if (c->opt.eig_method == TK_EIG_GRAM) return false;
+    return kh >= TK_MATFREE_MIN_KHAT;
+  };
+  int64_t maxY = 0, maxKh = 0, maxKhG = 0;
   for (int n = 0; n < N; ++n) {
     maxY = std::max(maxY, c->plan[n].L_nz * c->plan[n].khat);
     maxKh = std::max(maxKh, c->plan[n].khat);
+    if (!matfree(n)) maxKhG = std::max(maxKhG, c->plan[n].khat);
   }
   ensure(c, c->Y, sizeof(float) * (size_t)std::max<int64_t>(maxY, 1));
-  ensure(c, c->gram64, sizeof(double) * (size_t)maxKh * maxKh);
+  ensure(c, c->gram64, sizeof(double) * (size_t)std::max<int64_t>(maxKhG * maxKhG, 1));
+  if (maxKhG < maxKh) ensure(c, c->diag64, sizeof(double) * (size_t)maxKh);
   ensure(c, c->eig_val, sizeof(double) * 64 + sizeof(double) * (size_t)maxKh * 64);
   ensure(c, c->flag, sizeof(int) * 4);
   int64_t core_n = 1;
@@ -127,8 +140,10 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
     // Gauss-Seidel sweeps check for a failed (rank-deficient) factor once, at
     // the end of the invocation, instead of stopping the stream after every
     // mode; a failure skips the later modes' factor writes and those modes are
-    // run again below, after the failed factor is completed
-    const bool defer = c->opt.sweep == TK_SWEEP_GAUSS_SEIDEL;
+    // run again below, after the failed factor is completed.  Once a factor
+    // of this tensor has needed completion, later invocations check after
+    // every mode instead (one host wait per mode, no reruns).
+    const bool defer = c->opt.sweep == TK_SWEEP_GAUSS_SEIDEL && !c->completed_once;
     if (defer) TK_HIP(hipMemsetAsync(c->flag.as<int>() + 1, 0, sizeof(int), c->stream));
     auto run_mode = [&](int n, bool deferred) {
       ModePlan& pl = c->plan[n];
@@ -159,14 +174,24 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
         TK_HIP(hipEventRecord(k1, c->stream));
       }
       hipEvent_t t1 = mark("ttm[" + std::to_string(n) + "]", t0);
-      gram(c, Y, pl.L_nz, khat, c->gram64.as<double>(), low);
-      hipEvent_t t2 = mark("gram", t1);
       double* lam_k = c->eig_val.as<double>();
       double* VK = lam_k + 64;
-      eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK, n);
-      hipEvent_t t3 = mark("eig", t2);
-      form_factor(c, n, Y, pl.L_nz, khat, c->gram64.as<double>(), lam_k, VK, c->flag.as<int>(), deferred);
-      mark("factor", t3);
+      if (matfree(n)) {
+        // block Krylov on Y (the diagonal of Y^T Y, for the rank floor, on the way)
+        hipEvent_t t2 = mark("gram", t1);
+        eig_topk_matfree(c, Y, pl.L_nz, khat, K, lam_k, VK, n, c->diag64.as<double>());
+        hipEvent_t t3 = mark("eig", t2);
+        form_factor(c, n, Y, pl.L_nz, khat, c->diag64.as<double>(), 1, lam_k, VK, c->flag.as<int>(), deferred);
+        mark("factor", t3);
+      } else {
+        gram(c, Y, pl.L_nz, khat, c->gram64.as<double>(), low);
+        hipEvent_t t2 = mark("gram", t1);
+        eig_topk(c, c->gram64.as<double>(), khat, K, lam_k, VK, n);
+        hipEvent_t t3 = mark("eig", t2);
+        form_factor(c, n, Y, pl.L_nz, khat, c->gram64.as<double>(), (int64_t)khat + 1, lam_k, VK, c->flag.as<int>(),
+                    deferred);
+        mark("factor", t3);
+      }
     };
     for (int n = 0; n < N; ++n) run_mode(n, defer);
     if (defer) {
@@ -262,6 +287,7 @@ tk_status tk_default_options(tk_options* o) {
   o->eig_tol = 0.0;
   o->partition = TK_PART_LITE;
   o->ttm_kernel = TK_TTM_AUTO;
+  o->eig_method = TK_EIG_AUTO;
   return TK_OK;
 }
 
@@ -320,6 +346,7 @@ tk_status tk_set_options(tk_ctx* c, const tk_options* o) {
     TK_REQUIRE(o->eig_tol >= 0.0, TK_ERR_INVALID_ARG, "negative eig_tol");
     TK_REQUIRE(o->partition == TK_PART_LITE || o->partition == TK_PART_COARSE, TK_ERR_INVALID_ARG, "partition");
     TK_REQUIRE(o->ttm_kernel >= TK_TTM_AUTO && o->ttm_kernel <= TK_TTM_ATOMIC, TK_ERR_INVALID_ARG, "ttm_kernel");
+    TK_REQUIRE(o->eig_method >= TK_EIG_AUTO && o->eig_method <= TK_EIG_MATFREE, TK_ERR_INVALID_ARG, "eig_method");
     c->opt = *o;
   });
 }
@@ -346,6 +373,7 @@ static void drop_tensor(Ctx* c) {
   }
   c->val_c.release();
   c->m = 0;
+  c->completed_once = false;
 }
 
 tk_status tk_load_coo_begin(tk_ctx* c, int N, const int64_t* dims, int64_t nnz, unsigned flags) {
@@ -631,6 +659,33 @@ tk_status tk_hooi_iterate(tk_ctx* c, int iters, double* fits) {
     TK_REQUIRE(iters >= 0, TK_ERR_INVALID_ARG, "iters < 0");
     TK_HIP(hipSetDevice(c->device));
     hooi_iterate(c, iters, fits);
+  });
+}
+
+tk_status tk_init_hosvd(tk_ctx* c, const double* const* sketch, tk_mem mem, double* fit) {
+  if (!c) return TK_ERR_INVALID_ARG;
+  return guard(c, [&] {
+    TK_REQUIRE(c->have_ranks, TK_ERR_STATE, "set ranks first");
+    TK_REQUIRE(sketch != nullptr, TK_ERR_INVALID_ARG, "sketch is NULL");
+    for (int j = 0; j < c->N; ++j) TK_REQUIRE(sketch[j] != nullptr, TK_ERR_INVALID_ARG, "a sketch matrix is NULL");
+    TK_HIP(hipSetDevice(c->device));
+    // the sketches go where the factors are read from: the TTM-chain then
+    // forms T_(n) times their Kronecker product
+    for (int j = 0; j < c->N; ++j) {
+      copy_in(c, c->F64[j].as<double>(), sketch[j], (size_t)c->dims[j] * c->K[j], mem);
+      refresh_factor_copies(c, j);
+      c->fac_dirty[j] = true;
+    }
+    struct Restore {
+      Ctx* c;
+      tk_options o;
+      ~Restore() { c->opt = o; }
+    } restore{c, c->opt};
+    c->opt.sweep = TK_SWEEP_JACOBI;
+    c->opt.prec = TK_FP32;
+    double f = 0.0;
+    hooi_iterate(c, 1, &f);
+    if (fit) *fit = f;
   });
 }
 

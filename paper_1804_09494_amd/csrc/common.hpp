@@ -200,6 +200,8 @@ struct Ctx {
   Buf U64;                // double[R_n x K_n]
   Buf small64;            // double scratch for K x K matrices, reductions
   Buf kr_work;            // block-Krylov eigensolver workspace (large Khat)
+  Buf mf_work;            // matrix-free eigensolve: Y X and the row-range partials of Y^T (Y X)
+  Buf diag64;             // diag(Y^T Y) on the matrix-free route
   Buf eig_warm[8];        // last eigenvectors of each mode's Gram (Krylov warm start)
   int eig_warm_k[8] = {0};
   bool fac_dirty[8] = {true, true, true, true, true, true, true, true};   // rows of empty slices may be nonzero
@@ -208,6 +210,7 @@ struct Ctx {
 
   Timings timings;
   Counters counters;
+  bool completed_once = false;   // a factor of this tensor was completed (rank deficiency) at least once
   hipEvent_t ev_ttm[2] = {nullptr, nullptr};  // when set, bracket the TTM-chain kernel launch
   ObsSet obs;
   bool have_obs = false;

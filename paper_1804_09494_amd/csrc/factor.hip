@@ -14,6 +14,8 @@
 
 namespace tk {
 
+void tall_times_small(Ctx* c, const float* Y, int64_t R, int khat, const double* W, int K, double* U);
+
 constexpr int FT_ROWS = 64;  // rows of Y per workgroup
 
 // U = Y W and per-workgroup partial of U^T U.  W (khat x K, FP64) is in LDS;
@@ -370,12 +372,14 @@ __global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__
 // range of Y.
 constexpr double RANK_FLOOR = 4.0 / 16777216.0;   // 4 u
 
+// diag[i * dstride], i < khat: the Gram's diagonal (dstride = khat + 1 in the
+// Gram itself, 1 for a separate vector).
 __global__ __launch_bounds__(256) void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam,
-                                                const double* __restrict__ G, int khat, int K, double* __restrict__ W,
-                                                int* __restrict__ flag) {
+                                                const double* __restrict__ diag, int64_t dstride, int khat, int K,
+                                                double* __restrict__ W, int* __restrict__ flag) {
   __shared__ double red[256];
   double t = 0.0;
-  for (int i = threadIdx.x; i < khat; i += 256) t += G[(int64_t)i * khat + i];
+  for (int i = threadIdx.x; i < khat; i += 256) t += diag[(int64_t)i * dstride];
   red[threadIdx.x] = t;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
@@ -428,56 +432,242 @@ void refresh_factor_copies(Ctx* c, int n) {
   TK_CHECK_LAUNCH();
 }
 
-// Host-side completion of a rank-deficient factor (rare): orthonormalise the
-// computed columns by modified Gram-Schmidt with reorthogonalisation, drop the
-// ones that vanish, and fill the rest with unit vectors e_i (lowest i first).
-static void complete_on_host(Ctx* c, int n) {
+// ---- completion of a rank-deficient factor ----------------------------------------------------
+//
+// The factor's computed columns are orthonormalised, the ones that vanish are
+// dropped, and the missing columns come from unit vectors e_i (lowest i first)
+// made orthogonal to everything before them.  The columns are not unique; only
+// their span with the computed ones and their orthonormality are fixed.
+//
+// On the device: two passes of (Gram F^T F, FP64 over the L rows; Gram-Schmidt
+// of the columns in coefficient space on the host, K x K; F <- F T in place).
+// The unit-vector columns then need only the rows i of F that are tried: a new
+// column is Q b + sum_r a_r e_{i_r}, with Q the orthonormal computed columns,
+// so its coefficients follow from those rows, F <- F B adds the Q parts, and
+// the few tried rows are written from the host.
+
+constexpr int CG_ROWS = 64;   // rows per LDS tile
+
+// part[b] = sum over block b's rows of F[i, :]^T F[i, :]  (K x K, row-major)
+__global__ __launch_bounds__(256) void k_gram64_parts(const double* __restrict__ F, int64_t L, int K,
+                                                      int64_t rows_per_block, double* __restrict__ part) {
+  __shared__ double tile[CG_ROWS * 32];
+  const int KK = K * K;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
+  const int64_t r1 = std::min<int64_t>(L, r0 + rows_per_block);
+  for (int64_t t0 = r0; t0 < r1; t0 += CG_ROWS) {
+    const int nr = (int)std::min<int64_t>(CG_ROWS, r1 - t0);
+    for (int i = threadIdx.x; i < nr * K; i += 256) tile[i] = F[t0 * K + i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = threadIdx.x + 256 * q;
+      if (e < KK) {
+        const int a = e / K, b = e - a * K;
+        double s = 0.0;
+        for (int r = 0; r < nr; ++r) s += tile[r * K + a] * tile[r * K + b];
+        acc[q] += s;
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int e = threadIdx.x + 256 * q;
+    if (e < KK) part[(int64_t)blockIdx.x * KK + e] = acc[q];
+  }
+}
+
+// F[i, :] <- F[i, :] T  (T: K x K row-major), in place
+__global__ __launch_bounds__(256) void k_rows_times(double* __restrict__ F, int64_t L, int K,
+                                                    const double* __restrict__ T) {
+  __shared__ double Ts[32 * 32];
+  __shared__ double in[CG_ROWS * 32];
+  __shared__ double out[CG_ROWS * 32];
+  for (int i = threadIdx.x; i < K * K; i += 256) Ts[i] = T[i];
+  for (int64_t t0 = (int64_t)blockIdx.x * CG_ROWS; t0 < L; t0 += (int64_t)gridDim.x * CG_ROWS) {
+    const int nr = (int)std::min<int64_t>(CG_ROWS, L - t0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * K; i += 256) in[i] = F[t0 * K + i];
+    __syncthreads();
+    for (int o = threadIdx.x; o < nr * K; o += 256) {
+      const int r = o / K, b = o - r * K;
+      double s = 0.0;
+      for (int a = 0; a < K; ++a) s += in[r * K + a] * Ts[a * K + b];
+      out[o] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nr * K; i += 256) F[t0 * K + i] = out[i];
+  }
+}
+
+namespace {
+
+// Gram of F64[n] (K x K, FP64) on the host.
+std::vector<double> factor_gram(Ctx* c, int n, double* dev) {
   const int64_t L = c->dims[n];
   const int K = c->K[n];
-  std::vector<double> F((size_t)L * K);
-  d2h(c, F.data(), c->F64[n].as<double>(), F.size());
+  const int KK = K * K;
+  const int nb = (int)std::max<int64_t>(1, std::min<int64_t>(1024, ceil_div(L, 4096)));
+  const int64_t rpb = ceil_div(L, nb);
+  double* part = dev + 2 * KK;
+  hipLaunchKernelGGL(k_gram64_parts, dim3(nb), dim3(256), 0, c->stream, c->F64[n].as<double>(), L, K, rpb, part);
+  TK_CHECK_LAUNCH();
+  hipLaunchKernelGGL(k_sum_parts, dim3(std::min(KK, 1024)), dim3(256), 0, c->stream, part, nb, KK, dev);
+  TK_CHECK_LAUNCH();
+  std::vector<double> A((size_t)KK);
+  d2h(c, A.data(), dev, A.size());
   c->sync();
-  std::vector<std::vector<double>> cols;
+  return A;
+}
+
+// Modified Gram-Schmidt, twice per column, of the columns of F in the inner
+// product of their Gram A: T's columns 0..g-1 give F T orthonormal columns;
+// a column whose remainder is at most 1e-6 of its norm is dropped.
+int coeff_gram_schmidt(const std::vector<double>& A, int K, std::vector<double>& T) {
+  auto dot = [&](const std::vector<double>& x, const std::vector<double>& y) {
+    double s = 0.0;
+    for (int a = 0; a < K; ++a) {
+      if (x[a] == 0.0) continue;
+      double t = 0.0;
+      for (int b = 0; b < K; ++b) t += A[(size_t)a * K + b] * y[b];
+      s += x[a] * t;
+    }
+    return s;
+  };
+  std::vector<std::vector<double>> acc;
   for (int k = 0; k < K; ++k) {
-    std::vector<double> v(L);
-    double n0 = 0;
-    for (int64_t i = 0; i < L; ++i) { v[i] = F[i * K + k]; n0 += v[i] * v[i]; }
-    n0 = std::sqrt(n0);
-    if (n0 == 0) continue;
+    const double n0 = std::sqrt(std::max(A[(size_t)k * K + k], 0.0));
+    if (!(n0 > 0.0)) continue;
+    std::vector<double> v((size_t)K, 0.0);
+    v[k] = 1.0;
     for (int pass = 0; pass < 2; ++pass)
-      for (auto& u : cols) {
-        double d = 0;
-        for (int64_t i = 0; i < L; ++i) d += u[i] * v[i];
-        for (int64_t i = 0; i < L; ++i) v[i] -= d * u[i];
+      for (const auto& u : acc) {
+        const double d = dot(u, v);
+        for (int a = 0; a < K; ++a) v[a] -= d * u[a];
       }
-    double nv = 0;
-    for (int64_t i = 0; i < L; ++i) nv += v[i] * v[i];
-    nv = std::sqrt(nv);
+    const double nv = std::sqrt(std::max(dot(v, v), 0.0));
     if (nv > 1e-6 * n0) {
-      for (auto& x : v) x /= nv;
-      cols.push_back(std::move(v));
+      for (double& x : v) x /= nv;
+      acc.push_back(std::move(v));
     }
   }
-  for (int64_t e = 0; (int)cols.size() < K && e < L; ++e) {
-    std::vector<double> v(L, 0.0);
-    v[e] = 1.0;
-    for (int pass = 0; pass < 2; ++pass)
-      for (auto& u : cols) {
-        double d = 0;
-        for (int64_t i = 0; i < L; ++i) d += u[i] * v[i];
-        for (int64_t i = 0; i < L; ++i) v[i] -= d * u[i];
+  T.assign((size_t)K * K, 0.0);
+  for (size_t j = 0; j < acc.size(); ++j)
+    for (int a = 0; a < K; ++a) T[(size_t)a * K + j] = acc[j][a];
+  return (int)acc.size();
+}
+
+void apply_rows_times(Ctx* c, int n, const std::vector<double>& T, double* dev) {
+  const int64_t L = c->dims[n];
+  const int K = c->K[n];
+  h2d(c, dev + K * K, T.data(), T.size());
+  hipLaunchKernelGGL(k_rows_times, dim3(grid_for(ceil_div(L, CG_ROWS), 1, 4096)), dim3(256), 0, c->stream,
+                     c->F64[n].as<double>(), L, K, dev + K * K);
+  TK_CHECK_LAUNCH();
+  c->sync();   // T's host copy may go
+}
+
+}  // namespace
+
+static void complete_on_device(Ctx* c, int n) {
+  const int64_t L = c->dims[n];
+  const int K = c->K[n];
+  const int KK = K * K;
+  TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "completion: rank above 32");
+  ensure(c, c->small64, sizeof(double) * (size_t)KK * (2 + 1024));
+  double* dev = c->small64.as<double>();
+  // orthonormal computed columns: two passes
+  int g = K;
+  for (int pass = 0; pass < 2; ++pass) {
+    const std::vector<double> A = factor_gram(c, n, dev);
+    std::vector<double> T;
+    g = coeff_gram_schmidt(A, K, T);
+    apply_rows_times(c, n, T, dev);
+  }
+  if (g == K) {
+    refresh_factor_copies(c, n);
+    c->sync();
+    return;
+  }
+  // unit vectors e_i, lowest i first.  A column is (b, a): Q b + sum_r a[r] e_{cand[r]}.
+  struct Col {
+    std::vector<double> b, a;
+  };
+  std::vector<int64_t> cand;            // tried rows, in order
+  std::vector<std::vector<double>> qrow; // Q[cand[r], 0..g-1]
+  std::vector<Col> added;
+  auto inner = [&](const Col& x, const Col& y) {
+    double s = 0.0;
+    for (int j = 0; j < g; ++j) s += x.b[j] * y.b[j];
+    for (size_t r = 0; r < cand.size(); ++r) {
+      double qx = 0.0, qy = 0.0;
+      for (int j = 0; j < g; ++j) {
+        qx += qrow[r][j] * x.b[j];
+        qy += qrow[r][j] * y.b[j];
       }
-    double nv = 0;
-    for (int64_t i = 0; i < L; ++i) nv += v[i] * v[i];
-    nv = std::sqrt(nv);
+      s += y.a[r] * qx + x.a[r] * qy + x.a[r] * y.a[r];
+    }
+    return s;
+  };
+  std::vector<double> rows_h;
+  int64_t rows_at = 0, rows_n = 0;
+  for (int64_t i = 0; g + (int)added.size() < K; ++i) {
+    TK_REQUIRE(i < L, TK_ERR_NUMERIC, "completion: unit vectors exhausted");
+    if (i >= rows_at + rows_n) {   // read the next rows of Q
+      rows_at = i;
+      rows_n = std::min<int64_t>(256, L - i);
+      rows_h.resize((size_t)rows_n * K);
+      d2h(c, rows_h.data(), c->F64[n].as<double>() + i * K, rows_h.size());
+      c->sync();
+    }
+    cand.push_back(i);
+    qrow.emplace_back(rows_h.begin() + (i - rows_at) * K, rows_h.begin() + (i - rows_at) * K + g);
+    for (auto& col : added) col.a.push_back(0.0);
+    Col v{std::vector<double>((size_t)g), std::vector<double>(cand.size(), 0.0)};
+    v.a.back() = 1.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      // against Q's columns: <Q e_j, v> = v.b[j] + sum_r v.a[r] Q[cand[r], j]
+      std::vector<double> d((size_t)g, 0.0);
+      for (int j = 0; j < g; ++j) {
+        double t = v.b[j];
+        for (size_t r = 0; r < cand.size(); ++r) t += v.a[r] * qrow[r][j];
+        d[j] = t;
+      }
+      for (int j = 0; j < g; ++j) v.b[j] -= d[j];
+      for (const auto& u : added) {
+        const double t = inner(u, v);
+        for (int j = 0; j < g; ++j) v.b[j] -= t * u.b[j];
+        for (size_t r = 0; r < cand.size(); ++r) v.a[r] -= t * u.a[r];
+      }
+    }
+    const double nv = std::sqrt(std::max(inner(v, v), 0.0));
     if (nv > 0.5) {
-      for (auto& x : v) x /= nv;
-      cols.push_back(std::move(v));
+      for (double& x : v.b) x /= nv;
+      for (double& x : v.a) x /= nv;
+      added.push_back(std::move(v));
     }
   }
-  for (int k = 0; k < K; ++k)
-    for (int64_t i = 0; i < L; ++i) F[i * K + k] = cols[k][i];
-  h2d(c, c->F64[n].as<double>(), F.data(), F.size());
+  // F <- F B: column j < g stays, column g + t = Q b_t (columns g.. of F are zero)
+  std::vector<double> B((size_t)KK, 0.0);
+  for (int j = 0; j < g; ++j) B[(size_t)j * K + j] = 1.0;
+  for (size_t t = 0; t < added.size(); ++t)
+    for (int j = 0; j < g; ++j) B[(size_t)j * K + g + t] = added[t].b[j];
+  apply_rows_times(c, n, B, dev);
+  // the tried rows: Q[i] B + the unit-vector parts
+  std::vector<double> patch(cand.size() * (size_t)K);
+  for (size_t r = 0; r < cand.size(); ++r) {
+    double* row = patch.data() + r * K;
+    for (int j = 0; j < g; ++j) row[j] = qrow[r][j];
+    for (size_t t = 0; t < added.size(); ++t) {
+      double s = added[t].a[r];
+      for (int j = 0; j < g; ++j) s += qrow[r][j] * added[t].b[j];
+      row[g + t] = s;
+    }
+  }
+  // the tried rows are 0 .. cand.size()-1, contiguous
+  h2d(c, c->F64[n].as<double>(), patch.data(), patch.size());
   refresh_factor_copies(c, n);
   c->sync();
 }
@@ -525,8 +715,8 @@ __global__ void k_flag_record(int* flag, int n) {
 // set, this call leaves factor n as it was (the caller runs the mode again
 // after completing the failed factor); a failure of this mode sets it when
 // R >= K, and is completed at once when R < K.
-bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* Gfull, const double* lam_k,
-                 const double* VK, int* flag_dev, bool deferred) {
+bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* gdiag, int64_t dstride,
+                 const double* lam_k, const double* VK, int* flag_dev, bool deferred) {
   const int* abort = deferred ? flag_dev + 1 : nullptr;
   const bool check_flag = !deferred || R < c->K[n];
   const int K = c->K[n];
@@ -544,8 +734,8 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   double* U = c->U64.as<double>();
   const ModePlan& pl = c->plan[n];
   TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
-  hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, Gfull,
-                     khat, K, W, flag_dev);
+  hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, gdiag,
+                     dstride, khat, K, W, flag_dev);
   TK_CHECK_LAUNCH();
   // rows of empty slices (never written below) must be zero: clear the copies
   // only when something else may have written them (tk_set_factor, completion)
@@ -598,9 +788,16 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
     TK_CHECK_LAUNCH();
   } else if (R > 0) {
     size_t lds = sizeof(double) * ((size_t)khat * K + FT_ROWS * K) + sizeof(float) * FT_ROWS * (size_t)(khat + 1);
-    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat x K too large for LDS");
-    hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, tiles, U, part);
-    TK_CHECK_LAUNCH();
+    if (lds <= c->lds_per_block) {
+      hipLaunchKernelGGL(k_uw, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, tiles, U, part);
+      TK_CHECK_LAUNCH();
+    } else {
+      // W too large for LDS: U = Y W as a tall-skinny product, then the
+      // workgroups' row ranges of U^T U
+      tall_times_small(c, Y, R, khat, W, K, U);
+      hipLaunchKernelGGL(k_gram64_parts, dim3(nwg), dim3(256), 0, c->stream, U, R, K, ceil_div(R, nwg), part);
+      TK_CHECK_LAUNCH();
+    }
     for (int pass = 0; pass < 2; ++pass) {
       reduce_chol();
       hipLaunchKernelGGL(k_apply_rinv, dim3(nwg), dim3(256), sizeof(double) * ((size_t)K * K + 2 * FT_ROWS * K),
@@ -635,7 +832,8 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
 // Complete factor n (rank-deficient penultimate matrix) on the host.
 void complete_factor(Ctx* c, int n) {
   ++c->counters.rank_completions;
-  complete_on_host(c, n);
+  c->completed_once = true;
+  complete_on_device(c, n);
   c->fac_dirty[n] = true;   // completion may use rows of empty slices
 }
 

@@ -74,7 +74,7 @@ def test_c5_coalesce(c5):
     ctx = c5["ctx"]
     m, norm_sq = ctx.tensor_info()
     assert m == c5["m_o"]
-    assert m >= (1 << 31)            # beyond 32-bit signed element offsets
+    assert c5["stream"].nnz >= (1 << 31)   # draws beyond 32-bit signed element counts
     ic, vc = ctx.get_coo()
     # merged values of the sampled coordinates: canonical order is lexicographic,
     # so locate each one by nested binary searches
