@@ -80,6 +80,64 @@ def _counter_rows(path):
     return [rows[k] for k in sorted(rows)]
 
 
+SQ_PASSES = {
+    "sqa": "SQ_WAVES SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_WAIT_INST_ANY SQ_ACTIVE_INST_ANY SQ_INSTS_VALU SQ_INSTS_LDS "
+           "SQ_INSTS_VMEM_RD GRBM_GUI_ACTIVE",
+    "sqb": "SQ_INSTS_MFMA SQ_VALU_MFMA_BUSY_CYCLES SQ_WAIT_INST_LDS SQ_ACTIVE_INST_LDS SQ_ACTIVE_INST_VALU "
+           "SQ_LDS_BANK_CONFLICT SQ_INSTS_SALU GRBM_GUI_ACTIVE MfmaUtil",
+}
+
+
+def _summarize_sq(d, workload, regex):
+    """Per-kernel means of the SQ counter passes (sqa/, sqb/ under d) of
+    `bench.py --workload <w> --steps 1 --warmup 0 --no-cpu-baseline`."""
+    import csv
+    import glob
+    per = {}
+    for name in SQ_PASSES:
+        f = glob.glob(os.path.join(d, name, "*counter_collection.csv"))
+        if not f:
+            continue
+        disp = {}
+        for r in csv.DictReader(open(f[0])):
+            ent = disp.setdefault(int(r["Dispatch_Id"]), {"kernel": r["Kernel_Name"], "c": {}})
+            ent["c"][r["Counter_Name"]] = ent["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        for ent in disp.values():
+            k = ent["kernel"].split("(")[0].replace("void ", "")
+            agg = per.setdefault(k, {})
+            for c, v in ent["c"].items():
+                agg.setdefault(c, []).append(v)
+    if not per:
+        return
+    lines = [f"SQ counters per dispatch (mean over dispatches), `bench.py --workload {workload} --steps 1 --warmup 0 "
+             "--no-cpu-baseline`, kernels matching " + regex]
+    for name, cs in SQ_PASSES.items():
+        lines.append(f"command ({name}): cd /tmp && rocprofv3 --pmc {cs} --kernel-include-regex '{regex}' "
+                     f"--output-format csv -d <dir>/{name} -o run -- python3 -u <repo>/bench.py --workload {workload} "
+                     "--steps 1 --warmup 0 --no-cpu-baseline")
+    lines.append("")
+    for k, agg in sorted(per.items()):
+        m = {c: sum(v) / len(v) for c, v in agg.items()}
+        n = max(len(v) for v in agg.values())
+        lines.append(f"{k}  ({n} dispatches)")
+        for c in sorted(m):
+            lines.append(f"    {c:28s} {m[c]:.6g}")
+        wc = m.get("SQ_WAVE_CYCLES")
+        if wc:
+            for c in ("SQ_ACTIVE_INST_ANY", "SQ_WAIT_INST_ANY", "SQ_ACTIVE_INST_VALU", "SQ_ACTIVE_INST_LDS",
+                      "SQ_WAIT_INST_LDS"):
+                if c in m:
+                    lines.append(f"    {c} / SQ_WAVE_CYCLES = {m[c] / wc:.3f}")
+        w = m.get("SQ_WAVES")
+        if w:
+            for c in ("SQ_INSTS_VALU", "SQ_INSTS_LDS", "SQ_INSTS_MFMA", "SQ_INSTS_VMEM_RD", "SQ_INSTS_SALU"):
+                if c in m:
+                    lines.append(f"    {c} per wave = {m[c] / w:.1f}")
+        lines.append("")
+    with open(os.path.join(ROOT, "profiles", f"sq_counters_{workload}.txt"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+
+
 def summarize_profile(d, workload, kernel):
     """profiles/ summaries from rocprofv3 CSV output under d: trace/ (kernel
     trace + stats of a bench run), fetch/ and write/ (FETCH_SIZE and WRITE_SIZE
@@ -102,6 +160,7 @@ def summarize_profile(d, workload, kernel):
                          f"{float(r['AverageNs']) / 1e3:10.1f}  {r['Name'][:110]}")
         with open(os.path.join(out_dir, f"hooi_{workload}_kernel_stats.txt"), "w") as f:
             f.write("\n".join(lines) + "\n")
+    _summarize_sq(d, workload, f"{kernel}|k_gram")
     fetch_f = glob.glob(os.path.join(d, "fetch", "*counter_collection.csv"))
     write_f = glob.glob(os.path.join(d, "write", "*counter_collection.csv"))
     if not (fetch_f and write_f):
@@ -115,14 +174,18 @@ def summarize_profile(d, workload, kernel):
     w_scale = copy_kib / (sum(r["value"] for r in bigw) / len(bigw))
     tf = [r["value"] for r in fetch if kernel in r["kernel"]]
     tw = [r["value"] for r in write if kernel in r["kernel"]]
-    per_mode = [round((a * f_scale + b * w_scale) * 1024) for a, b in zip(tf, tw)]
-    res = {"kernel": kernel, "workload": workload, "note": "one launch per mode",
+    every = [round((a * f_scale + b * w_scale) * 1024) for a, b in zip(tf, tw)]
+    N = {"k_ttm3_mfma": 3, "k_ttm4_mfma": 4}.get(kernel, len(every))
+    res = {"kernel": kernel, "workload": workload,
+           "note": "hbm_bytes_per_mode: the first invocation's launches, modes 0..N-1 in order (FP32); "
+                   "every_launch: all launches of the run in order (later invocations, BF16 tiles, the HOSVD "
+                   "initialisation's Jacobi sweep and its core)",
            "source_sha256": _sha256(TTM_SOURCE),
-           "fetch_kib_per_mode": tf, "write_kib_per_mode": tw,
+           "fetch_kib_every_launch": tf, "write_kib_every_launch": tw, "hbm_bytes_every_launch": every,
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": sum(r["value"] for r in big) / len(big),
                                 "write_kib": sum(r["value"] for r in bigw) / len(bigw),
                                 "fetch_scale": round(f_scale, 4), "write_scale": round(w_scale, 4)},
-           "hbm_bytes_per_mode": per_mode,
+           "hbm_bytes_per_mode": every[:N],
            "commands": [f"cd /tmp && rocprofv3 --pmc {c} --kernel-include-regex '{kernel}|copyBuffer' "
                         f"--output-format csv -d <dir>/{d_} -o run -- python3 -u <repo>/bench.py --workload {workload} "
                         "--steps 1 --warmup 0 --no-cpu-baseline" for c, d_ in (("FETCH_SIZE", "fetch"),

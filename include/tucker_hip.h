@@ -90,7 +90,7 @@ typedef enum {
   TK_EIG_MATFREE = 2   /* block Krylov on Y itself, never squared: each block product is Y^T (Y X), two
                           passes over Y; Khat >= 192 and K <= 31 (smaller Khat takes the Gram route) */
 } tk_eig_method;
-#define TK_MATFREE_MIN_KHAT 4096
+#define TK_MATFREE_MIN_KHAT 8192
 
 typedef struct {
   int32_t prec;                   /* tk_prec (default TK_FP32).  TK_BF16 (the precision form): the
@@ -108,11 +108,15 @@ typedef struct {
   int64_t mem_limit_bytes;        /* 0 = no limit; plans above it fail with TK_ERR_OOM before allocating */
   int32_t complete_rank_deficient;/* 1 (default) = complete U with unit vectors; 0 = TK_ERR_NUMERIC */
   int32_t keep_elem_order;        /* 1 (default) = keep each mode's element order for tk_get_partition */
-  double eig_tol;                 /* block-Krylov eigensolve (Khat >= 192): bound on the estimated
+  double eig_tol;                 /* block-Krylov eigensolve (Khat >= 192): when its result is accepted.
+                                     0 (default): once the relative residual ||A v - theta v|| / theta_1
+                                     is at the rounding level of the FP32 data the operator is formed
+                                     from (4 u, u = 2^-24); below it the dense solver on the same data
+                                     would not fix the subspace any better.  > 0: only when the estimated
                                      subspace error sqrt(2) * residual * theta_1 / (theta_K - theta_{K+1})
-                                     (sin-theta theorem); a larger estimate reruns the mode's eigensolve
-                                     with the dense solver (the matrix-free route first forms G and takes
-                                     the Gram route).  0 (default) = 1e-7 */
+                                     (sin-theta theorem) is at most eig_tol.  A rejected result reruns the
+                                     mode's eigensolve with the dense solver (the matrix-free route first
+                                     forms G and takes the Gram route) */
   int32_t partition;              /* tk_partition (default TK_PART_LITE); read by tk_set_ranks */
   int32_t ttm_kernel;             /* tk_ttm_kernel (default TK_TTM_AUTO) */
   int32_t eig_method;             /* tk_eig_method (default TK_EIG_AUTO) */

@@ -25,7 +25,7 @@ TK_ASSUME_UNIQUE = 1
 TK_PART_LITE, TK_PART_COARSE = 0, 1
 TK_TTM_AUTO, TK_TTM_VECTOR, TK_TTM_ATOMIC = 0, 1, 2
 TK_EIG_AUTO, TK_EIG_GRAM, TK_EIG_MATFREE = 0, 1, 2
-TK_MATFREE_MIN_KHAT = 4096
+TK_MATFREE_MIN_KHAT = 8192
 
 
 class tk_options(ctypes.Structure):

@@ -128,7 +128,7 @@ struct Timings {
 struct Counters {
   int64_t eig_krylov_solves = 0;     // block-Krylov eigensolves
   int64_t eig_krylov_cycles = 0;     // their restart cycles
-  int64_t eig_dense_fallbacks = 0;   // Krylov results replaced by the dense solver (estimate above eig_tol)
+  int64_t eig_dense_fallbacks = 0;   // Krylov results replaced by the dense solver (not accepted)
   int64_t rank_completions = 0;      // factors completed after a rank-deficient penultimate matrix
 };
 
@@ -218,7 +218,11 @@ struct Ctx {
   void* alloc_raw(size_t bytes);
   void free_raw(void* p, size_t bytes);
   void sync() { TK_HIP(hipStreamSynchronize(stream)); }
-  double eig_tol() const { return opt.eig_tol > 0.0 ? opt.eig_tol : 1e-7; }
+  // Krylov acceptance: a positive eig_tol bounds the estimated subspace error;
+  // 0 accepts a residual at the FP32 input's rounding level (4 u)
+  bool krylov_accepts(double res, double err) const {
+    return opt.eig_tol > 0.0 ? err <= opt.eig_tol : res <= 4.0 / 16777216.0;
+  }
 };
 
 inline void Buf::alloc(Ctx* c, size_t bytes) {

@@ -770,12 +770,19 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   if (R > 0 && mfma) {
     const int kpad = (khat + 15) & ~15;
     const size_t lds = sizeof(float) * (size_t)kpad * 16;
-    TK_REQUIRE(lds + 2048 <= c->lds_per_block, TK_ERR_UNSUPPORTED, "factor step: Khat too large for LDS");
-    if (khat % 4 == 0)
-      hipLaunchKernelGGL(k_uw_mfma<true>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
-    else
-      hipLaunchKernelGGL(k_uw_mfma<false>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
-    TK_CHECK_LAUNCH();
+    if (lds + 2048 <= c->lds_per_block) {
+      if (khat % 4 == 0)
+        hipLaunchKernelGGL(k_uw_mfma<true>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+      else
+        hipLaunchKernelGGL(k_uw_mfma<false>, dim3(nwg), dim3(256), lds, c->stream, Y, R, khat, W, K, U, part);
+      TK_CHECK_LAUNCH();
+    } else {
+      // W too large for LDS: U = Y W as a tall-skinny FP64 product, then the
+      // workgroups' row ranges of U^T U
+      tall_times_small(c, Y, R, khat, W, K, U);
+      hipLaunchKernelGGL(k_gram64_parts, dim3(nwg), dim3(256), 0, c->stream, U, R, K, ceil_div(R, nwg), part);
+      TK_CHECK_LAUNCH();
+    }
     reduce_chol();
     hipLaunchKernelGGL(k_rinv_mfma<false>, dim3(nwg), dim3(256), 0, c->stream, U, R, K, Rinv, part, nullptr, nullptr,
                        nullptr, nullptr, 0, nullptr);

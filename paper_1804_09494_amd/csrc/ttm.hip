@@ -353,15 +353,13 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 
-// FP32 -> BF16, round to nearest even (finite inputs)
-__device__ __forceinline__ uint32_t bf16_bits(float f) {
-  const uint32_t b = __float_as_uint(f);
-  return (b + 0x7FFFu + ((b >> 16) & 1u)) >> 16;
-}
-// four FP32 values as the four BF16 halves of an MFMA operand, in order
+typedef __bf16 bf16x4_h __attribute__((ext_vector_type(4)));
+typedef float floatx4_c __attribute__((ext_vector_type(4)));
+// four FP32 values as the four BF16 halves of an MFMA operand, in order,
+// rounded to nearest even (two v_cvt_pk_bf16_f32)
 __device__ __forceinline__ bf16x4_t bf16x4_of(float a, float b, float c, float d) {
-  const uint32_t lo = bf16_bits(a) | (bf16_bits(b) << 16), hi = bf16_bits(c) | (bf16_bits(d) << 16);
-  return __builtin_bit_cast(bf16x4_t, (uint64_t)lo | ((uint64_t)hi << 32));
+  const floatx4_c f = {a, b, c, d};
+  return __builtin_bit_cast(bf16x4_t, __builtin_convertvector(f, bf16x4_h));
 }
 
 // Three-mode TTM-chain on the matrix cores, one wave per Lite bin.

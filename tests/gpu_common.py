@@ -50,6 +50,17 @@ def factor_tolerance(sv, K, tol=1e-5):
     return max(tol, np.sqrt(2.0) * 4.0 * U32 * cond), cond
 
 
+def factor_tolerance_y(sv, K, tol=1e-5):
+    """Allowed projector distance for an SVD step that never squares Y (the
+    matrix-free route: products with Y in FP64 from its FP32 entries).  The
+    perturbation is Y's own rounding, ||E|| <= c u sigma_1, and Wedin's
+    sin-theta theorem bounds the subspace error by
+    sqrt(2) c u sigma_1 / (sigma_K - sigma_{K+1}); c = 4 as above."""
+    if len(sv) <= K or sv[K] == 0.0:
+        return tol
+    return max(tol, np.sqrt(2.0) * 4.0 * U32 * sv[0] / max(sv[K - 1] - sv[K], 1e-300))
+
+
 def fit_noise(fit):
     """Rounding noise of the fit 1 - sqrt(||T||^2 - ||G||^2)/||T|| when
     ||G||^2 carries a relative FP32 error of c u (c = 4, from Y and the core's

@@ -1,18 +1,22 @@
 """The matrix-free SVD step (block Krylov on Y itself, X -> Y^T (Y X), never
 forming the Gram; Section 3 "SVD Component") against the FP64 oracle's HOOI,
 and against the Gram route on the same tensor: wide Khat on four modes
-(ranks 10, Khat = 1000) and ranks above 16 (K = 20, the 32-column block)."""
+(ranks 10, Khat = 1000) and ranks above 16 (K = 20, the 32-column block).
+The matrix-free factors are held to Wedin's bound for a perturbation of Y of
+its FP32 rounding (they never square Y), the Gram route's to its own."""
 import numpy as np
 import pytest
 
 import synth
 from oracle import coo, hooi, ttm
-from tests.gpu_common import factor_tolerance, fit_noise
+from tests.gpu_common import factor_tolerance, factor_tolerance_y, fit_noise
 
 pytestmark = pytest.mark.gpu
 
 CASES = {"4mode_k10": ((1500, 1000, 400, 60), 120_000, (0.9, 1.1, 1.3, 0.7), (10, 10, 10, 10), 2),
-         "3mode_k20": ((1200, 900, 600), 150_000, (1.0, 1.1, 1.2), (20, 20, 20), 2)}
+         "3mode_k20": ((1200, 900, 600), 150_000, (1.0, 1.1, 1.2), (20, 20, 20), 2),
+         # Khat = 4096: W of the factor step no longer fits in LDS (tall-skinny product route)
+         "4mode_k16": ((400, 300, 150, 60), 12_000, (0.9, 1.0, 1.1, 0.8), (16, 16, 16, 16), 1)}
 
 
 def _run(tk, idx, vals, dims, ranks, F0, iters, method):
@@ -46,12 +50,14 @@ def test_matfree_hooi_matches_oracle_and_gram_route(tk, name):
         F = ctx.get_factor(n)
         np.testing.assert_allclose(F.T @ F, np.eye(ranks[n]), atol=1e-12)
         sv = np.linalg.svd(ttm.ttm_chain(ic, vc, o["factors"], n, dims), compute_uv=False)
-        allowed, cond = factor_tolerance(sv, ranks[n])
+        allowed = factor_tolerance_y(sv, ranks[n])
+        allowed_g, _ = factor_tolerance(sv, ranks[n])
         d = hooi.projector_distance(F, o["factors"][n])
-        dg = hooi.projector_distance(F, ctx_g.get_factor(n))
-        print(f"  mode {n}: vs oracle {d:.2e}, vs Gram route {dg:.2e} (allowed {allowed:.2e})", flush=True)
+        dg = hooi.projector_distance(ctx_g.get_factor(n), o["factors"][n])
+        print(f"  mode {n}: matrix-free vs oracle {d:.2e} (allowed {allowed:.2e}), Gram route vs oracle "
+              f"{dg:.2e}", flush=True)
         assert d <= allowed
-        assert dg <= 2 * allowed
+        assert dg <= allowed_g
 
 
 def test_matfree_small_khat_takes_gram_route(tk):
