@@ -398,6 +398,61 @@ def run_ablation(args):
     print(json.dumps(out), flush=True)
 
 
+def run_fiber_ablation(args):
+    """The fiber-factored TTM-chain against the default kernels on the
+    precision form's tensor (4 modes, 2,000,000 x 1,000,000 x 100,000 x 5,000,
+    5e8 draws, Zipf 0.9/1.1/1.3/0.7, ranks 10) and on a three-mode tensor with
+    long fibers (2,000 x 200 x 500, 1e8 draws, Zipf 0.5 on every mode, ranks
+    10: hundreds of elements share each pair of the first two coordinates):
+    TTM-chain kernel time per mode."""
+    import torch
+    import synth
+    import paper_1804_09494_amd as P
+    torch.cuda.set_device(0)
+    out = {"metric": "TTM-chain kernel ms per mode, default kernel vs fiber-factored", "runs": []}
+    cases = [("c3", None), ("long", ((2_000, 200, 500), int(1e8 * args.scale), (0.5, 0.5, 0.5)))]
+    for name, spec in cases:
+        if spec is None:
+            stream = synth.WorkloadStream("c3", scale=args.scale)
+            dims, ranks = stream.dims, stream.ranks
+            idx, vals = stream.chunk(0, stream.nnz)
+        else:
+            dims, nnz, z = spec
+            ranks = (10,) * len(dims)
+            idx, vals = synth.make_tensor(dims, nnz, "zipf", z, "lognormal", seed=3131)
+        idx_d = [torch.from_numpy(np.ascontiguousarray(i)).cuda() for i in idx]
+        vals_d = torch.from_numpy(np.ascontiguousarray(vals)).cuda()
+        del idx, vals
+        F0 = synth.orthonormal_init(3232, dims, ranks)
+        for kernel in ("auto", "fiber"):
+            ctx = P.TuckerContext(0, keep_elem_order=0, ttm_kernel=kernel)
+            ctx.load_coo(idx_d, vals_d, dims)
+            ctx.set_ranks(ranks)
+            for n, F in enumerate(F0):
+                ctx.set_factor(n, np.ascontiguousarray(F))
+            m, _ = ctx.tensor_info()
+            run = {"tensor": name, "dims": dims, "m": m, "kernel": kernel, "ms": []}
+            for n in range(len(dims)):
+                R, kh = ctx.ttm_shape(n)
+                Y = torch.empty((R, kh), dtype=torch.float32, device="cuda")
+                ctx.ttm_chain(n, Y)
+                torch.cuda.synchronize()
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(max(1, args.steps)):
+                    ctx.ttm_chain(n, Y)
+                e1.record()
+                torch.cuda.synchronize()
+                run["ms"].append(round(e0.elapsed_time(e1) / max(1, args.steps), 3))
+                del Y
+            print(json.dumps(run), file=sys.stderr, flush=True)
+            out["runs"].append(run)
+            del ctx
+            torch.cuda.empty_cache()
+        del idx_d, vals_d
+    print(json.dumps(out), flush=True)
+
+
 def run_eig_ablation(args):
     """The SVD step's two routes on one GPU: the Gram formed (then dense or
     block Krylov on G) against matrix-free block Krylov on Y, for a
@@ -459,6 +514,7 @@ def main():
     ap.add_argument("--summarize-profile", metavar="DIR")
     ap.add_argument("--ablation", action="store_true", help="partition ablations (Lite, CoarseG, atomics)")
     ap.add_argument("--eig-ablation", action="store_true", help="SVD step: Gram route vs matrix-free")
+    ap.add_argument("--fiber-ablation", action="store_true", help="TTM-chain: default kernels vs fiber-factored")
     args = ap.parse_args()
     if args.summarize_profile:
         import synth
@@ -477,6 +533,9 @@ def main():
         return
     if args.eig_ablation:
         run_eig_ablation(args)
+        return
+    if args.fiber_ablation:
+        run_fiber_ablation(args)
         return
 
     import torch

@@ -78,9 +78,13 @@ typedef enum {
 typedef enum {
   TK_TTM_AUTO = 0,     /* matrix-core kernels where they apply, else the vector-ALU one */
   TK_TTM_VECTOR = 1,   /* the vector-ALU kernel for every shape (and whatever the bin sizes) */
-  TK_TTM_ATOMIC = 2    /* no partition: the merged element list in canonical order, each wave's
+  TK_TTM_ATOMIC = 2,   /* no partition: the merged element list in canonical order, each wave's
                           running row sums added to Y with FP32 atomics when the mode-n index changes
                           (not deterministic); an ablation baseline */
+  TK_TTM_FIBER = 3     /* fiber-factored (three or four modes, other ranks <= 16; other shapes as AUTO):
+                          the elements of a slice sharing all remaining coordinates but the last are
+                          summed first, t = sum val F_c[l_c], then F_a (x) F_b (x) t is added once per
+                          fiber (eq. 1 grouped by fibers); Lite bins of 512 elements by default */
 } tk_ttm_kernel;
 /* How the SVD step of HOOI reaches the eigenpairs of Y^T Y (Section 3, "SVD Component"). */
 typedef enum {

@@ -23,7 +23,7 @@ TK_SWEEP_GAUSS_SEIDEL, TK_SWEEP_JACOBI = 0, 1
 TK_NOALLOC_SCRATCH_BYTES = 32 << 20
 TK_ASSUME_UNIQUE = 1
 TK_PART_LITE, TK_PART_COARSE = 0, 1
-TK_TTM_AUTO, TK_TTM_VECTOR, TK_TTM_ATOMIC = 0, 1, 2
+TK_TTM_AUTO, TK_TTM_VECTOR, TK_TTM_ATOMIC, TK_TTM_FIBER = 0, 1, 2, 3
 TK_EIG_AUTO, TK_EIG_GRAM, TK_EIG_MATFREE = 0, 1, 2
 TK_MATFREE_MIN_KHAT = 8192
 

@@ -135,7 +135,7 @@ class TuckerContext:
         kern = kw.pop("ttm_kernel", None)
         if kern is not None:
             o.ttm_kernel = {"auto": _lib.TK_TTM_AUTO, "vector": _lib.TK_TTM_VECTOR,
-                            "atomic": _lib.TK_TTM_ATOMIC}.get(kern, kern)
+                            "atomic": _lib.TK_TTM_ATOMIC, "fiber": _lib.TK_TTM_FIBER}.get(kern, kern)
         eig = kw.pop("eig_method", None)
         if eig is not None:
             o.eig_method = {"auto": _lib.TK_EIG_AUTO, "gram": _lib.TK_EIG_GRAM,

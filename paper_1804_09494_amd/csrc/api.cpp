@@ -345,7 +345,7 @@ tk_status tk_set_options(tk_ctx* c, const tk_options* o) {
     TK_REQUIRE(o->wg_nnz_target >= 0 && o->mem_limit_bytes >= 0, TK_ERR_INVALID_ARG, "negative size");
     TK_REQUIRE(o->eig_tol >= 0.0, TK_ERR_INVALID_ARG, "negative eig_tol");
     TK_REQUIRE(o->partition == TK_PART_LITE || o->partition == TK_PART_COARSE, TK_ERR_INVALID_ARG, "partition");
-    TK_REQUIRE(o->ttm_kernel >= TK_TTM_AUTO && o->ttm_kernel <= TK_TTM_ATOMIC, TK_ERR_INVALID_ARG, "ttm_kernel");
+    TK_REQUIRE(o->ttm_kernel >= TK_TTM_AUTO && o->ttm_kernel <= TK_TTM_FIBER, TK_ERR_INVALID_ARG, "ttm_kernel");
     TK_REQUIRE(o->eig_method >= TK_EIG_AUTO && o->eig_method <= TK_EIG_MATFREE, TK_ERR_INVALID_ARG, "eig_method");
     c->opt = *o;
   });
@@ -490,7 +490,7 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
     for (int n = 0; n < N; ++n) {
       const int tw = ttm_tile_width(N, K, n);
       build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
-                 ttm_default_bin_nnz(N, K, n), c->opt.keep_elem_order != 0,
+                 ttm_default_bin_nnz(N, K, n, c->opt.ttm_kernel), c->opt.keep_elem_order != 0,
                  coarse ? c->slice_order[n].as<int32_t>() : nullptr);
     }
     for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);

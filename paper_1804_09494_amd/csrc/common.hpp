@@ -317,7 +317,7 @@ void export_partition(Ctx* c, ModePlan& pl, int64_t m, int64_t* bin_ptr, int64_t
                       int32_t* seg_slice, int64_t* seg_begin, uint8_t* seg_bad, tk_mem mem);
 int ttm_rows_cap(Ctx* c, int64_t tile_w);
 int ttm_tile_width(int N, const int32_t* K, int n);
-int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n);
+int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n, int kernel);
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);

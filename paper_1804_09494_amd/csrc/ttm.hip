@@ -888,6 +888,188 @@ __global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __re
 
 // ---- dispatch -----------------------------------------------------------------------------------
 
+// ---- fiber-factored TTM-chain (three or four modes, other ranks <= 16) -----------------------------
+//
+// Elements of one slice that agree on every remaining coordinate but the last
+// (mode c) form a fiber; within a segment they are contiguous (the layout
+// keeps the canonical order inside each slice).  Eq. 1 then factors by fibers:
+//   Y[l] = sum over fibers f of slice l of  F_a[l_a(f)] (x) F_b[l_b(f)] (x) t_f,
+//   t_f = sum over elements e of f of val(e) F_c[l_c(e)],
+// with F_b absent for three modes.  A fiber costs K_c multiply-adds per
+// element and one rank-one update of K_a K_b K_c entries, instead of a
+// Kronecker row of K-hat entries per element.
+//
+// One wave per Lite bin.  The bin's coordinates and values are staged in LDS
+// and its fiber starts found with ballots.  Fibers go in batches of sixteen:
+// lane group g (four lanes, lane q holding columns 4q..4q+3 of a 16-float
+// row) forms t of fiber 16i + g with 16-byte gathers of the F_c rows and
+// gathers the fiber's F_a and F_b rows; the three rows go to an LDS stage.
+// Then every lane updates its accumulators for the batch's fibers in order,
+// one (a, b) pair per lane and pair slot (pair = a + K_a b), reading the
+// fiber's rows from the stage as broadcasts.  A segment's row goes straight
+// from the accumulators to Y (or to its partial slot when the slice is split
+// across bins) when the next fiber belongs to a later segment; the column of
+// entry (pair, c) is pair + K_a K_b c, the first remaining mode fastest.  Sums
+// run in element order within a fiber and in fiber order within a slice:
+// deterministic.
+constexpr int TTMF_MAXP = 4;   // pair slots per lane: K_a K_b <= 256
+constexpr int TTMF_BATCH = 16; // fibers per batch (one per four-lane group)
+
+template <int NP>
+__global__ __launch_bounds__(64) void k_ttm_fiber(TtmArgs A, int Epad) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
+  const int64_t e0 = A.bin_ptr[bin];
+  const int E = (int)(A.bin_ptr[bin + 1] - e0);   // multiple of 4
+  const int s0 = A.seg_ptr[bin];
+  const int nseg = A.seg_ptr[bin + 1] - s0;
+  if (nseg == 0) return;
+  const bool four = A.n_other == 3;
+  const int ka = A.Kj[0], kb = four ? A.Kj[1] : 1, kc = A.Kj[A.n_other - 1];
+  const int P = ka * kb, khat = A.khat;
+  float* stage = reinterpret_cast<float*>(smem);            // TTMF_BATCH x 48: F_a, F_b, t rows
+  int* sia = reinterpret_cast<int*>(stage + TTMF_BATCH * 48);   // Epad
+  int* sib = sia + Epad;                     // Epad (four modes)
+  int* sic = sib + Epad;                     // Epad
+  float* sv = reinterpret_cast<float*>(sic + Epad);
+  int* fst = reinterpret_cast<int*>(sv + Epad);   // Epad + 1: fiber starts, then E
+  int* send = fst + Epad + 1;                     // nseg: segment ends (bin-relative)
+  unsigned char* sflag = reinterpret_cast<unsigned char*>(send + nseg);   // Epad: segment starts
+  const int lane = threadIdx.x;
+  {
+    const u32x4* la4 = reinterpret_cast<const u32x4*>(A.lay[0] + e0);
+    const u32x4* lb4 = reinterpret_cast<const u32x4*>(A.lay[1] + e0);
+    const u32x4* lc4 = reinterpret_cast<const u32x4*>(A.lay[A.n_other - 1] + e0);
+    const u32x4* v4 = reinterpret_cast<const u32x4*>(A.val + e0);
+    for (int i = lane; 4 * i < E; i += 64) {
+      reinterpret_cast<u32x4*>(sia)[i] = __builtin_nontemporal_load(la4 + i);
+      if (four) reinterpret_cast<u32x4*>(sib)[i] = __builtin_nontemporal_load(lb4 + i);
+      reinterpret_cast<u32x4*>(sic)[i] = __builtin_nontemporal_load(lc4 + i);
+      reinterpret_cast<u32x4*>(sv)[i] = __builtin_nontemporal_load(v4 + i);
+    }
+    for (int i = lane; i < nseg; i += 64) send[i] = (int)(A.seg_begin[s0 + i + 1] - e0);
+    for (int i = lane; i < E; i += 64) sflag[i] = 0;
+  }
+  wave_lds_sync();
+  for (int i = lane; i < nseg; i += 64) sflag[i == 0 ? 0 : send[i - 1]] = 1;
+  wave_lds_sync();
+  // fiber starts: a segment start, or a change of the coordinates other than the last
+  int nf = 0;
+  for (int b0 = 0; b0 < E; b0 += 64) {
+    const int e = b0 + lane;
+    bool start = false;
+    if (e < E) {
+      const int ep = e > 0 ? e - 1 : 0;   // e = 0 is a segment start
+      start = sflag[e] || sia[e] != sia[ep] || (four && sib[e] != sib[ep]);
+    }
+    const uint64_t m = __ballot(start);
+    if (start) fst[nf + __popcll(m & ((1ull << lane) - 1))] = e;
+    nf += __popcll(m);
+  }
+  if (lane == 0) fst[nf] = E;
+  wave_lds_sync();
+  const int g = lane >> 2, q = lane & 3;
+  const float* Fa = A.F[0];
+  const float* Fb = A.F[1];
+  const float* Fc = A.F[A.n_other - 1];
+  float acc[NP][16];
+#pragma unroll
+  for (int p = 0; p < NP; ++p)
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[p][c] = 0.f;
+  int po[NP];    // stage offsets of this lane's pairs: a | (16 + b) << 8, or -1 past K_a K_b
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int pair = lane + 64 * p;
+    po[p] = pair < P ? (pair % ka) | ((16 + pair / ka) << 8) : -1;
+  }
+  int cur = 0;   // segment of the accumulators
+  const uintptr_t ybase = reinterpret_cast<uintptr_t>(A.Y);
+  const uintptr_t pdiff = reinterpret_cast<uintptr_t>(A.partial) - ybase;
+  auto flush = [&]() __attribute__((always_inline)) {
+    const int slot = A.seg_slot[s0 + cur];
+    const int64_t r64 = slot < 0 ? A.seg_row[s0 + cur] : slot;
+    float* dst = reinterpret_cast<float*>(ybase + (slot < 0 ? 0 : pdiff) + (uintptr_t)(r64 * khat) * 4);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const int pair = lane + 64 * p;
+#pragma unroll
+      for (int c = 0; c < 16; ++c) {
+        if (c < kc && pair < P) __builtin_nontemporal_store(acc[p][c], dst + pair + P * c);
+        acc[p][c] = 0.f;
+      }
+    }
+  };
+  auto row4 = [&](const float* F, int r) __attribute__((always_inline)) {
+    return *reinterpret_cast<const floatx4_c*>(F + ((size_t)(uint32_t)r * 16 + 4 * q));
+  };
+  for (int fb = 0; fb < nf; fb += TTMF_BATCH) {
+    // phase 1: lane group g forms t of fiber fb + g and stages its rows
+    const int f = fb + g;
+    if (f < nf) {
+      const int fs = fst[f], fe = fst[f + 1];
+      const floatx4_c xa = row4(Fa, sia[fs]);
+      const floatx4_c xb = four ? row4(Fb, sib[fs]) : floatx4_c{1.f, 1.f, 1.f, 1.f};
+      floatx4_c t = {0.f, 0.f, 0.f, 0.f};
+      int e = fs;
+      for (; e + 4 <= fe; e += 4) {   // four gathers in flight, then their sum in element order
+        floatx4_c x[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) x[u] = row4(Fc, sic[e + u]);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) t += sv[e + u] * x[u];
+      }
+      for (; e < fe; ++e) t += sv[e] * row4(Fc, sic[e]);
+      float* st = stage + g * 48 + 4 * q;
+      *reinterpret_cast<floatx4_c*>(st) = xa;
+      *reinterpret_cast<floatx4_c*>(st + 16) = xb;
+      *reinterpret_cast<floatx4_c*>(st + 32) = t;
+    }
+    wave_lds_sync();
+    // phase 2: the batch's rank-one updates, in fiber order
+    const int nb = min(TTMF_BATCH, nf - fb);
+    for (int gg = 0; gg < nb; ++gg) {
+      const int fs = uni(fst[fb + gg]);
+      while (fs >= uni(send[cur])) {   // the fiber belongs to a later segment: the row is complete
+        flush();
+        ++cur;
+      }
+      const float* st = stage + gg * 48;
+      float tc[16];
+#pragma unroll
+      for (int c4 = 0; c4 < 4; ++c4) {
+        const floatx4_c v = reinterpret_cast<const floatx4_c*>(st + 32)[c4];
+        tc[4 * c4] = v[0];
+        tc[4 * c4 + 1] = v[1];
+        tc[4 * c4 + 2] = v[2];
+        tc[4 * c4 + 3] = v[3];
+      }
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+        const float fab = po[p] >= 0 ? st[po[p] & 0xff] * st[po[p] >> 8] : 0.f;
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+          if (c < kc) acc[p][c] = fmaf(fab, tc[c], acc[p][c]);
+      }
+    }
+    wave_lds_sync();   // the next batch's stage writes follow these reads
+  }
+  // the last segment (every segment holds at least one element, hence one fiber)
+  while (cur < nseg) {
+    flush();
+    ++cur;
+  }
+}
+
+// Which shapes the fiber-factored kernel takes: three or four modes, other
+// ranks <= 16 with 16-float factor rows.
+bool ttm_uses_fiber(int N, const int32_t* K, int n, const int* kp) {
+  if (N != 3 && N != 4) return false;
+  for (int j = 0; j < N; ++j)
+    if (j != n && (K[j] > 16 || kp[j] != 16)) return false;
+  return true;
+}
+
 // Three-mode tensors with both remaining ranks <= 16 and 16-float factor rows
 // take the matrix-core kernel.
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp) {
@@ -921,11 +1103,12 @@ int ttm_tile_width(int N, const int32_t* K, int n) {
 // Default elements per Lite bin for the kernel mode n takes: the one-wave
 // three-mode kernel wants small bins (one bin's start-up latency is covered by
 // the others on the CU; 384-512 elements measured best, 448 by a little), the
-// four-mode kernel's four waves share 1024, and the vector-ALU kernel
-// amortises its row tiles over 4096.
-int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n) {
+// four-mode kernel's four waves share 1024, the one-wave fiber-factored
+// kernel takes 512, and the vector-ALU kernel amortises its row tiles over 4096.
+int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n, int kernel) {
   int kp16[8];
   for (int j = 0; j < N; ++j) kp16[j] = K[j] <= 16 ? 16 : 0;
+  if (kernel == TK_TTM_FIBER && ttm_uses_fiber(N, K, n, kp16)) return 512;   // one wave per bin
   if (ttm_uses_mfma(N, K, n, kp16)) return 448;
   if (ttm_uses_mfma4(N, K, n, kp16)) return 1024;
   return 4096;
@@ -1029,7 +1212,19 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
   const bool vector_only = pl.whole_slices || c->opt.ttm_kernel == TK_TTM_VECTOR;
-  if (!vector_only && ttm_uses_mfma(N, K, n, kp)) {
+  if (!pl.whole_slices && c->opt.ttm_kernel == TK_TTM_FIBER && ttm_uses_fiber(N, K, n, kp)) {
+    const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
+    const size_t lds = 4 * (TTMF_BATCH * 48 + 5 * (size_t)Epad + 1 + (size_t)pl.R_max) + (size_t)Epad + 64;
+    TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
+    const int P = N == 4 ? a.Kj[0] * a.Kj[1] : a.Kj[0];
+    if (P <= 64)
+      hipLaunchKernelGGL(k_ttm_fiber<1>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
+    else if (P <= 128)
+      hipLaunchKernelGGL(k_ttm_fiber<2>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
+    else
+      hipLaunchKernelGGL(k_ttm_fiber<TTMF_MAXP>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
+    TK_CHECK_LAUNCH();
+  } else if (!vector_only && ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const size_t lds = 12 * (size_t)Epad + sizeof(float) * 512 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");

@@ -1,8 +1,8 @@
 """The partition ablations against the oracle: CoarseG bins (Section 5, whole
 slices in a random order, contiguous blocks) must match the oracle's
 assignment bit for bit; the TTM-chain on CoarseG bins, with the vector-ALU
-kernel forced on Lite bins, and without a partition (atomics) must match the
-FP64 oracle's Y to 1e-5."""
+kernel forced on Lite bins, with the fiber-factored kernel, and without a
+partition (atomics) must match the FP64 oracle's Y to 1e-5."""
 import numpy as np
 import pytest
 
@@ -64,7 +64,7 @@ def test_coarse_partition_and_ttm(tk, name):
         np.testing.assert_array_equal(Y, Y2)
 
 
-@pytest.mark.parametrize("kernel", ["vector", "atomic"])
+@pytest.mark.parametrize("kernel", ["vector", "atomic", "fiber"])
 @pytest.mark.parametrize("name", ["zipf15", "4mode"])
 def test_ttm_kernel_choices(tk, kernel, name):
     make, ranks, wg = CASES[name]
@@ -84,3 +84,35 @@ def test_ttm_kernel_choices(tk, kernel, name):
         err = rel_fro(Y, Yo)
         print(f"{kernel} mode {n}: rel err {err:.2e}", flush=True)
         assert err <= 1e-5
+
+
+FIBER_CASES = {
+    # long fibers: the last remaining mode has few ids, odd ranks
+    "4mode_long": (lambda: zipf_tensor((200, 100, 50, 8), 60_000, s=(1.0, 0.9, 0.8, 0.5), seed=54), (3, 5, 7, 6)),
+    "3mode_long": (lambda: zipf_tensor((3000, 400, 6), 80_000, s=(1.2, 1.0, 0.5), seed=55), (16, 9, 5)),
+    "4mode_k16": (lambda: zipf_tensor((300, 200, 60, 30), 30_000, s=(0.9, 1.1, 1.3, 0.7), seed=56), (16, 16, 16, 16)),
+}
+
+
+@pytest.mark.parametrize("name", list(FIBER_CASES))
+def test_fiber_kernel_matches_oracle_and_reruns_bit_identical(tk, name):
+    make, ranks = FIBER_CASES[name]
+    idx, vals = make()
+    dims = tuple(int(i.max()) + 1 for i in idx)
+    ctx = _ctx(tk, idx, vals, dims, ttm_kernel="fiber")
+    ctx.set_ranks(ranks)
+    ic, vc, _ = coo.coalesce_fast(idx, vals)
+    F = [synth.normal(79, 200 + n, d * k).reshape(d, k) for n, (d, k) in enumerate(zip(dims, ranks))]
+    F32 = [f.astype(np.float32).astype(np.float64) for f in F]
+    for n in range(len(dims)):
+        ctx.set_factor(n, F[n])
+    for n in range(len(dims)):
+        Y, rows = ctx.ttm_chain(n)
+        Yo, rows_o = oracle_Y(ic, vc, F32, n, dims)
+        np.testing.assert_array_equal(rows, rows_o)
+        err = rel_fro(Y, Yo)
+        st = ctx.partition_stats(n)
+        print(f"{name} fiber mode {n}: rel err {err:.2e}, split slices {st['n_bad']}", flush=True)
+        assert err <= 1e-5
+        Y2, _ = ctx.ttm_chain(n)
+        np.testing.assert_array_equal(Y, Y2)
