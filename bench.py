@@ -40,7 +40,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 COPY_BYTES = 1 << 31
-TTM_SOURCE = os.path.join(ROOT, "paper_1804_09494_amd", "csrc", "ttm.hip")
+# the sources of the Lite-bin TTM-chain kernels (the traffic summary is keyed to them)
+TTM_SOURCES = [os.path.join(ROOT, "paper_1804_09494_amd", "csrc", f) for f in ("ttm.hip", "ttm_common.hpp")]
 COPY_KERNEL = "__amd_rocclr_copyBuffer"
 TTM_KERNELS = {3: "k_ttm3_mfma", 4: "k_ttm4_mfma"}
 CHUNK = 1 << 27          # draws per streamed chunk (2 GiB of host buffers for 3 modes)
@@ -50,10 +51,13 @@ def traffic_file(workload):
     return os.path.join(ROOT, "profiles", f"ttm_{workload}_hbm_traffic.json")
 
 
-def _sha256(path):
+def _sha256(paths):
     import hashlib
-    with open(path, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()
+    h = hashlib.sha256()
+    for path in paths:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def committed_traffic(workload):
@@ -64,7 +68,7 @@ def committed_traffic(workload):
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("source_sha256") != _sha256(TTM_SOURCE):
+    if t.get("source_sha256") != _sha256(TTM_SOURCES):
         return None
     return t["hbm_bytes_per_mode"]
 
@@ -180,7 +184,7 @@ def summarize_profile(d, workload, kernel):
            "note": "hbm_bytes_per_mode: the first invocation's launches, modes 0..N-1 in order (FP32); "
                    "every_launch: all launches of the run in order (later invocations, BF16 tiles, the HOSVD "
                    "initialisation's Jacobi sweep and its core)",
-           "source_sha256": _sha256(TTM_SOURCE),
+           "source_sha256": _sha256(TTM_SOURCES),
            "fetch_kib_every_launch": tf, "write_kib_every_launch": tw, "hbm_bytes_every_launch": every,
            "copy_calibration": {"bytes": COPY_BYTES, "fetch_kib": sum(r["value"] for r in big) / len(big),
                                 "write_kib": sum(r["value"] for r in bigw) / len(bigw),
