@@ -134,57 +134,85 @@ __global__ __launch_bounds__(256) void k_eval(FPtrs F, IPtrs ip, int N, int32_t 
 
 typedef float floatx4_e __attribute__((ext_vector_type(4)));
 
-// Three modes, every rank <= 16, on the matrix cores.  For 16 observations
-// i at a time, D = A B with A[i][(b, c)] = F_1[l_1(i)][b] F_2[l_2(i)][c] (the
-// Kronecker row, zero past the ranks) and B[(b, c)][a] = G[a + K_0 (b + K_1 c)]:
-// 64 steps of v_mfma_f32_16x16x4_f32 (step (c, s) contracts b = 4s .. 4s+3),
-// lane l supplying A[l%16][4s + l/16] and B[4s + l/16][l%16].  B is held in
-// 64 registers per lane for the whole kernel.  Then
-// m_i = sum_a D[i][a] F_0[l_0(i)][a], a sum over the 16 lanes of a row group.
-// Rows are read from the caller's factors (row stride K_j).
-__global__ __launch_bounds__(256) void k_eval3_mfma(const float* __restrict__ F0, const float* __restrict__ F1,
-                                                    const float* __restrict__ F2, const int32_t* __restrict__ i0,
-                                                    const int32_t* __restrict__ i1, const int32_t* __restrict__ i2,
-                                                    int K0, int K1, int K2, const float* __restrict__ G,
-                                                    int64_t n_obs, float* __restrict__ out) {
+// dst (L x kp) = src (L x K) with zero columns past K
+__global__ void k_pad_copy(const float* __restrict__ src, int64_t L, int K, float* __restrict__ dst, int kp) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * kp; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t l = i / kp;
+    const int k = (int)(i - l * kp);
+    dst[i] = k < K ? src[l * K + k] : 0.f;
+  }
+}
+
+// Three modes, every rank <= 16, on the matrix cores, grouped by the slices
+// of one mode c (the one with the fewest nonempty slices, so each slice holds
+// many observations).  For an observation of slice l_c,
+//   m = F_a[l_a]^T M F_b[l_b],  M[a][b] = sum_c G[a, b, c] F_c[l_c][c]
+// (a < b the other two modes, G indexed with the first mode fastest).  The
+// observations are walked in the layout of mode c's plan (bins of Lite
+// segments, padded to multiples of four, a segment being one slice's run in
+// one bin).  Per segment the wave forms M once, in the B-operand layout of
+// v_mfma_f32_16x16x4_f32 (lane (q, j) holds M[4q + s][j], s = 0..3, the
+// contraction index of step s being 4q + s); per block of 16 observations
+// four MFMA steps give D = F_a-rows x M with A[i][4q + s] = F_a[l_a(i)][4q + s]
+// (one 16-byte load per lane), and m_i = sum_j D[i][j] F_b[l_b(i)][j] is a sum
+// over the 16 lanes of a row group.  Factors are the 16-float padded copies.
+// Each observation's value goes to its own index (order_pad); padding
+// positions are skipped.
+__global__ __launch_bounds__(256) void k_eval3_slab(const int64_t* __restrict__ bin_pptr,
+                                                    const int32_t* __restrict__ seg_ptr,
+                                                    const int64_t* __restrict__ seg_pbegin,
+                                                    const int32_t* __restrict__ seg_row,
+                                                    const int32_t* __restrict__ row_slice,
+                                                    const int32_t* __restrict__ lay_a, const int32_t* __restrict__ lay_b,
+                                                    const uint32_t* __restrict__ order, const float* __restrict__ Fa,
+                                                    const float* __restrict__ Fb, const float* __restrict__ Fc,
+                                                    const float* __restrict__ G, int Ka, int Kb, int Kc, int sa,
+                                                    int sb, int sc, int64_t P, float* __restrict__ out) {
   const int lane = threadIdx.x & 63;
-  const int i16 = lane & 15, q = lane >> 4;
-  float bg[16][4];   // B for step (c, s): G[i16 + K0 (4s + q + K1 c)]
+  const int j = lane & 15, q = lane >> 4;
+  const int64_t nw = (int64_t)gridDim.x * 4;
+  for (int64_t bin = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); bin < P; bin += nw) {
+    const int s0 = seg_ptr[bin], s1 = seg_ptr[bin + 1];
+    for (int sg = s0; sg < s1; ++sg) {
+      const int64_t pb = seg_pbegin[sg], pe = seg_pbegin[sg + 1];
+      const int64_t lc = row_slice[seg_row[sg]];
+      // M in the B-operand layout: Mr[s] = M[4q + s][j]
+      float fc[16];
 #pragma unroll
-  for (int c = 0; c < 16; ++c)
+      for (int c = 0; c < 16; ++c) fc[c] = Fc[lc * 16 + c];
+      float Mr[4];
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) {
-      const int b = 4 * s4 + q;
-      bg[c][s4] = (i16 < K0 && b < K1 && c < K2) ? G[i16 + K0 * (b + K1 * c)] : 0.f;
-    }
-  const int64_t nblk = (n_obs + 15) >> 4;
-  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  const int64_t nwaves = (int64_t)gridDim.x * 4;
-  for (int64_t blk = wave; blk < nblk; blk += nwaves) {
-    const int64_t e = blk * 16 + i16;            // this lane's observation for the A operand
-    const bool ok = e < n_obs;
-    const int64_t ee = ok ? e : n_obs - 1;
-    const float* r1 = F1 + (int64_t)i1[ee] * K1;
-    const float* r2 = F2 + (int64_t)i2[ee] * K2;
-    float f1[4], f2[16];
+      for (int s = 0; s < 4; ++s) {
+        const int a = 4 * q + s;
+        float t = 0.f;
+        if (a < Ka && j < Kb)
+          for (int c = 0; c < Kc; ++c) t = fmaf(G[a * sa + j * sb + c * sc], fc[c], t);
+        Mr[s] = t;
+      }
+      for (int64_t p0 = pb; p0 < pe; p0 += 16) {
+        const int64_t pi = p0 + j;   // this lane's observation for the A operand
+        const bool ok = pi < pe;
+        const int la = ok ? lay_a[pi] : 0;
+        const floatx4_e xa = ok ? *reinterpret_cast<const floatx4_e*>(Fa + (int64_t)la * 16 + 4 * q)
+                                : floatx4_e{0.f, 0.f, 0.f, 0.f};
+        floatx4_e D = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int s4 = 0; s4 < 4; ++s4) f1[s4] = (ok && 4 * s4 + q < K1) ? r1[4 * s4 + q] : 0.f;
+        for (int s = 0; s < 4; ++s) D = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[s], Mr[s], D, 0, 0, 0);
+        // D[4q + r][j] in register r: times F_b[l_b(obs 4q + r)][j], summed over the row group
 #pragma unroll
-    for (int c = 0; c < 16; ++c) f2[c] = c < K2 ? r2[c] : 0.f;
-    floatx4_e D = {0.f, 0.f, 0.f, 0.f};
+        for (int r = 0; r < 4; ++r) {
+          const int64_t pr = p0 + 4 * q + r;
+          const bool okr = pr < pe;
+          const float v = okr ? D[r] * Fb[(int64_t)lay_b[pr] * 16 + j] : 0.f;
+          float w = v;
 #pragma unroll
-    for (int c = 0; c < 16; ++c)
-#pragma unroll
-      for (int s4 = 0; s4 < 4; ++s4) D = __builtin_amdgcn_mfma_f32_16x16x4f32(f1[s4] * f2[c], bg[c][s4], D, 0, 0, 0);
-    // D[4q + r][i16] in register r: times F_0[l_0(obs 4q+r)][a = i16], summed over the 16 lanes of the group
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t er = blk * 16 + 4 * q + r;
-      const bool okr = er < n_obs;
-      float v = (okr && i16 < K0) ? D[r] * F0[(int64_t)i0[okr ? er : n_obs - 1] * K0 + i16] : 0.f;
-#pragma unroll
-      for (int w = 8; w >= 1; w >>= 1) v += __shfl_xor(v, w, 16);
-      if (i16 == 0 && okr) out[er] = v;
+          for (int x = 8; x >= 1; x >>= 1) w += __shfl_xor(w, x, 16);
+          if (j == 0 && okr) {
+            const uint32_t e = order[pr];
+            if (e != 0xffffffffu) out[e] = w;
+          }
+        }
+      }
     }
   }
 }
@@ -216,8 +244,24 @@ void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk
     out = tOut.as<float>();
   }
   if (o.n_obs > 0 && N == 3 && o.K[0] <= 16 && o.K[1] <= 16 && o.K[2] <= 16) {
-    hipLaunchKernelGGL(k_eval3_mfma, dim3(grid_for(ceil_div(o.n_obs, 16), 4, 16384)), dim3(256), 0, c->stream,
-                       fp.p[0], fp.p[1], fp.p[2], ip.p[0], ip.p[1], ip.p[2], o.K[0], o.K[1], o.K[2], G, o.n_obs, out);
+    // group by the mode with the fewest nonempty slices; factors as 16-float rows
+    int mc = 0;
+    for (int jn = 1; jn < 3; ++jn)
+      if (o.plan[jn].L_nz < o.plan[mc].L_nz) mc = jn;
+    const int ma = mc == 0 ? 1 : 0, mb = mc == 2 ? 1 : 2;
+    for (int jn = 0; jn < 3; ++jn) {
+      hipLaunchKernelGGL(k_pad_copy, dim3(grid_for(o.dims[jn] * 16, 256)), dim3(256), 0, c->stream, fp.p[jn],
+                         o.dims[jn], o.K[jn], o.F32[jn].as<float>(), 16);
+      TK_CHECK_LAUNCH();
+    }
+    const int st[3] = {1, o.K[0], o.K[0] * o.K[1]};
+    const ModePlan& pl = o.plan[mc];
+    hipLaunchKernelGGL(k_eval3_slab, dim3(grid_for(pl.P, 4, 16384)), dim3(256), 0, c->stream,
+                       pl.bin_pptr.as<int64_t>(), pl.seg_ptr.as<int32_t>(), pl.seg_pbegin.as<int64_t>(),
+                       pl.seg_row.as<int32_t>(), pl.row_slice.as<int32_t>(), pl.lay_idx[0].as<int32_t>(),
+                       pl.lay_idx[1].as<int32_t>(), pl.order_pad.as<uint32_t>(), o.F32[ma].as<float>(),
+                       o.F32[mb].as<float>(), o.F32[mc].as<float>(), G, o.K[ma], o.K[mb], o.K[mc], st[ma], st[mb],
+                       st[mc], pl.P, out);
     TK_CHECK_LAUNCH();
   } else if (o.n_obs > 0) {
     const int use_lds = (size_t)pK * 4 <= std::min<size_t>(c->lds_per_block, 65536) ? 1 : 0;
@@ -239,14 +283,6 @@ void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk
 __global__ void k_fill_zero_f(float* __restrict__ p, int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     p[i] = 0.f;
-}
-
-__global__ void k_pad_copy(const float* __restrict__ src, int64_t L, int K, float* __restrict__ dst, int kp) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < L * kp; i += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t l = i / kp;
-    const int k = (int)(i - l * kp);
-    dst[i] = k < K ? src[l * K + k] : 0.f;
-  }
 }
 
 __global__ void k_gather_layout(const float* __restrict__ g, const uint32_t* __restrict__ order, int64_t m,

@@ -431,6 +431,27 @@ def test_completion_eval_and_adjoint_match_oracle(tk):
         assert rel_fro(dF[n].double().cpu().numpy(), dFo[n]) <= TOL
 
 
+@pytest.mark.parametrize("dims,ranks", [((20, 300, 200), (5, 16, 7)), ((300, 15, 200), (9, 3, 12)),
+                                         ((120, 90, 60), (1, 2, 1))])
+def test_completion_eval_grouped_by_each_mode(tk, dims, ranks):
+    """The three-mode forward walks the observations slice by slice of the mode
+    with the fewest nonempty slices: each mode in turn, odd ranks."""
+    import torch
+    from oracle import completion
+    d = synth.make_completion(dims, 15_000, ranks, seed=5151)
+    ctx = tk.TuckerContext(0)
+    ctx.load_obs([torch.from_numpy(i).cuda() for i in d["idx"]], dims, ranks)
+    rng = np.random.default_rng(3)
+    Gt = torch.tensor(rng.standard_normal(int(np.prod(ranks))), dtype=torch.float32, device="cuda")
+    Ft = [torch.tensor(rng.standard_normal((L, K)) / np.sqrt(K), dtype=torch.float32, device="cuda")
+          for L, K in zip(dims, ranks)]
+    G32 = Gt.double().cpu().numpy().reshape(ranks, order="F")
+    F32 = [f.double().cpu().numpy() for f in Ft]
+    mv = ctx.tucker_eval(Gt, Ft).double().cpu().numpy()
+    mo = completion.model_values(G32, F32, d["idx"])
+    assert rel_fro(mv, mo) <= TOL
+
+
 def test_completion_autograd_function(tk):
     import torch
     from oracle import completion
