@@ -507,7 +507,7 @@ def run_eig_ablation(args):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="c5")
     ap.add_argument("--scale", type=float, default=1.0)
@@ -650,7 +650,7 @@ def main():
                                f"one HOOI invocation per step",
                    "m_coalesced": m, "draws": stream.nnz, "ranks": list(ranks)},
         "hooi_iter_ms": {"fp32": round(ms_per_step, 4), "bf16_gram": round(bf_ms, 4)},
-        "bf16_gram_run": f"{K - 1} invocations with BF16 Gram operands, then one refining FP32 invocation",
+        "bf16_gram_run": f"{K - 1} invocations with BF16 Kronecker tiles and Gram operands, then one refining FP32 invocation",
         "final_fit": {"fp32": fits[-1] if fits else None, "bf16_gram": bf_fits[-1] if bf_fits else None},
         "step_ms_bf16_gram": {k: round(v / K, 4) for k, v in bf_tm.items()},
         "ttm_ms_per_mode": [round(x, 4) for x in ttm_ms],

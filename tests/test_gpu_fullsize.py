@@ -14,7 +14,7 @@ import numpy as np
 import pytest
 
 import synth
-from oracle import lite, ttm
+from oracle import cpp, lite, ttm
 from tests.gpu_common import fit_noise, rel_fro
 
 pytestmark = pytest.mark.gpu
@@ -96,10 +96,13 @@ def test_fullsize_ttm_sampled_rows(c2):
         heavy = np.argsort(sizes)[::-1][:10]
         g = ctx.partition(n, elem_order=False)
         bad = np.unique(g["seg_slice"][g["seg_bad"] == 1])
-        pick = np.unique(np.concatenate([heavy, rng.choice(bad, min(20, len(bad)), replace=False),
-                                         rng.choice(rows, 100, replace=False)]))
-        # linear in the values, so the unmerged draws give the same rows
-        Yo = ttm.ttm_chain_rows(w["idx"], w["vals"], w["F0"], n, pick)
+        pick = np.unique(np.concatenate([heavy, rng.choice(bad, min(200, len(bad)), replace=False),
+                                         rng.choice(rows, 790, replace=False)]))
+        # linear in the values, so the unmerged draws give the same rows (the
+        # oracle's C++/OpenMP FP64 accumulator over every draw)
+        acc = cpp.RowAccumulator(w["F0"], n, dims[n], pick)
+        acc.add(w["idx"], w["vals"])
+        Yo = acc.rows
         Yg = Y[np.searchsorted(rows, pick)]
         err = rel_fro(Yg, Yo)
         row_err = np.linalg.norm(Yg - Yo, axis=1) / np.maximum(np.linalg.norm(Yo, axis=1), 1e-30)
