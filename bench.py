@@ -155,9 +155,9 @@ def summarize_profile(d, workload, kernel):
     if stats:
         rows = list(csv.DictReader(open(stats[0])))
         rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
-        lines = [f"kernel time of `bench.py --workload {workload} --steps 3 --warmup 1 --no-cpu-baseline`, top kernels",
+        lines = [f"kernel time of `bench.py --workload {workload} --steps 10 --warmup 1 --no-cpu-baseline`, top kernels",
                  "command: cd /tmp && rocprofv3 --kernel-trace --stats --output-format csv -d <dir>/trace -o run "
-                 f"-- python3 -u <repo>/bench.py --workload {workload} --steps 3 --warmup 1 --no-cpu-baseline",
+                 f"-- python3 -u <repo>/bench.py --workload {workload} --steps 10 --warmup 1 --no-cpu-baseline",
                  "", f"{'total ms':>10} {'calls':>6} {'avg us':>10}  kernel"]
         for r in rows[:25]:
             lines.append(f"{float(r['TotalDurationNs']) / 1e6:10.3f} {int(r['Calls']):6d} "
