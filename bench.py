@@ -47,6 +47,28 @@ TTM_KERNELS = {3: "k_ttm3_mfma", 4: "k_ttm4_mfma"}
 CHUNK = 1 << 27          # draws per streamed chunk (2 GiB of host buffers for 3 modes)
 
 
+# the sources of the kernels whose SQ counters are summarised (TTM-chain and Gram)
+SQ_SOURCES = TTM_SOURCES + [os.path.join(ROOT, "paper_1804_09494_amd", "csrc", "gram.hip")]
+
+
+def sq_file(workload):
+    return os.path.join(ROOT, "profiles", f"sq_counters_{workload}.json")
+
+
+def committed_mfma_util(workload):
+    """MfmaUtil (percent of SIMD cycles with the matrix cores busy, rocprofv3's
+    derived counter) per kernel template from the committed SQ summary of this
+    workload, or None when those kernels' sources changed since."""
+    try:
+        with open(sq_file(workload)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != _sha256(SQ_SOURCES):
+        return None
+    return {k: round(v["MfmaUtil"], 1) for k, v in t["kernels"].items() if "MfmaUtil" in v and v["MfmaUtil"] > 0}
+
+
 def traffic_file(workload):
     return os.path.join(ROOT, "profiles", f"ttm_{workload}_hbm_traffic.json")
 
@@ -140,6 +162,9 @@ def _summarize_sq(d, workload, regex):
         lines.append("")
     with open(os.path.join(ROOT, "profiles", f"sq_counters_{workload}.txt"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    means = {k: {c: sum(v) / len(v) for c, v in agg.items()} for k, agg in per.items()}
+    with open(sq_file(workload), "w") as f:
+        json.dump({"workload": workload, "source_sha256": _sha256(SQ_SOURCES), "kernels": means}, f, indent=1)
 
 
 def summarize_profile(d, workload, kernel):
@@ -666,7 +691,9 @@ def main():
                      "traffic": round(float(np.mean(traffic))) if traffic else None,
                      "traffic_bytes_per_mode": traffic,
                      "kernel": f"{kernel} (TTM-chain)",
-                     "bytes_per_launch": [int(b) for b in B]},
+                     "bytes_per_launch": [int(b) for b in B],
+                     "mfma_util_pct": committed_mfma_util(args.workload) if args.share == 1 and args.scale == 1.0
+                     else None},
         "device_copy_GBps": round(copy_gbs, 1),
         "counters": counters,
         "cpu_baseline": cpu,
