@@ -441,7 +441,13 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
 // it (lane group q supplies elements 4q .. 4q+3; other slices' lane groups get
 // a zero A operand), FP32 accumulation, as in the three-mode kernel.
 template <int NT, bool BFM>
-__global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg_pad) {
+// Up to eight output tiles, at most 170 registers per lane (three waves per
+// SIMD): at ranks 10 the BF16 form would otherwise take 194 (166 + 28
+// accumulation registers) and run at two waves, 26% slower, and the FP32 form
+// drops from 154 to 119.  Wider tiles keep the compiler's choice (the cap
+// would spill).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 3 : 1))) void k_ttm4_mfma(
+    TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.Kj[0], kb = A.Kj[1], kbc = A.Kj[1] * A.Kj[2];
   const int64_t bin = xcd_bin(blockIdx.x, gridDim.x);
@@ -651,14 +657,16 @@ __global__ __launch_bounds__(256) void k_ttm4_mfma(TtmArgs A, int Epad, int nseg
       fetch(min(cs + 16 * d, last), ring[d]);
       __builtin_amdgcn_sched_barrier(0);
     }
+    static_assert(TTM4_RING == 3, "the ring steps below are written out for three blocks");
+    auto step = [&](int gg, Blk& r) __attribute__((always_inline)) {
+      consume(gg, r);
+      __builtin_amdgcn_sched_barrier(0);
+      fetch(min(gg + 16 * TTM4_RING, last), r);
+    };
     for (int g = cs; g < ce; g += 16 * TTM4_RING) {
-#pragma unroll
-      for (int d = 0; d < TTM4_RING; ++d) {
-        const int gg = g + 16 * d;
-        consume(gg, ring[d]);
-        __builtin_amdgcn_sched_barrier(0);
-        fetch(min(gg + 16 * TTM4_RING, last), ring[d]);
-      }
+      step(g, ring[0]);
+      step(g + 16, ring[1]);
+      step(g + 32, ring[2]);
     }
     flush();
   }
