@@ -324,7 +324,7 @@ def run_completion(args):
     dims, n_obs, ranks = (500_000, 500_000, 50_000), int(2e8 * args.scale), (16, 16, 16)
     dims = tuple(max(2, int(round(d * (args.scale if args.scale < 1 else 1)))) for d in dims)
     t = time.perf_counter()
-    obs = synth.make_completion(dims, n_obs, ranks, with_values=False)
+    obs = synth.make_completion(dims, n_obs, ranks)
     idx = [torch.from_numpy(i).cuda() for i in obs["idx"]]
     ctx = P.TuckerContext(0)
     ctx.load_obs(idx, dims, ranks)

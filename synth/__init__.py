@@ -49,13 +49,12 @@ def _L():
             lib.synth_perm.argtypes = [u64, u64, i64, p]
             lib.synth_uniform_idx.argtypes = [u64, u64, i64, i64, p]
             lib.synth_zipf_idx.argtypes = [u64, u64, ctypes.c_double, i64, p, i64, p]
-            lib.synth_planted_values.argtypes = [ctypes.c_int, p, p, p, i64, p, p]
             lib.synth_zipf_table.argtypes = [ctypes.c_double, i64, p]
             lib.synth_zipf_guide.argtypes = [p, i64, ctypes.c_int, p]
             lib.synth_zipf_idx_range.argtypes = [u64, u64, p, p, ctypes.c_int, i64, p, i64, i64, p]
             lib.synth_lognormal_f32_range.argtypes = [u64, u64, i64, i64, p]
             for f in (lib.synth_u01, lib.synth_normal, lib.synth_lognormal_f32, lib.synth_uniform_f32,
-                      lib.synth_perm, lib.synth_uniform_idx, lib.synth_zipf_idx, lib.synth_planted_values,
+                      lib.synth_perm, lib.synth_uniform_idx, lib.synth_zipf_idx,
                       lib.synth_zipf_table, lib.synth_zipf_guide, lib.synth_zipf_idx_range,
                       lib.synth_lognormal_f32_range):
                 f.restype = None
@@ -183,21 +182,6 @@ def orthonormal_init(seed: int, dims, ranks):
     return out
 
 
-def planted_values(K, G, F, idx) -> np.ndarray:
-    """Values of a planted Tucker model {G; F_1..F_N} at coordinates idx (N x n)."""
-    N = len(K)
-    K64 = np.ascontiguousarray(K, dtype=np.int64)
-    G = np.ascontiguousarray(G, dtype=np.float64).ravel(order="F")
-    F = [np.ascontiguousarray(f, dtype=np.float64) for f in F]
-    idx = [np.ascontiguousarray(i, dtype=np.int32) for i in idx]
-    n = idx[0].shape[0]
-    out = np.empty(n, np.float64)
-    Fp = (ctypes.c_void_p * N)(*[f.ctypes.data for f in F])
-    Ip = (ctypes.c_void_p * N)(*[i.ctypes.data for i in idx])
-    _L().synth_planted_values(N, _ptr(K64), _ptr(G), Fp, n, Ip, _ptr(out))
-    return out
-
-
 # ----------------------------------------------------------------------------------------------
 # Workload recipes.  Tensor seed 1804 + c, factor seed 9494 + c (c = workload number),
 # planted-model seed 4949.
@@ -301,17 +285,17 @@ class WorkloadStream:
         return orthonormal_init(self.factor_seed, self.dims, self.ranks)
 
 
-def make_completion(dims, n_obs, ranks, zipf=(1.0, 1.0, 1.0), noise=0.01, seed=4949, with_values=True):
-    """Observation coordinates of a completion problem and the targets of a
-    planted model: core ~ N(0,1), factors ~ N(0, 1/K_n), plus N(0, noise^2)."""
+def make_completion(dims, n_obs, ranks, zipf=(1.0, 1.0, 1.0), noise=0.01, seed=4949):
+    """Observation coordinates of a completion problem and a planted model
+    (core ~ N(0,1), factors ~ N(0, 1/K_n)) with N(0, noise^2) draws per
+    observation.  The targets are the planted model's values plus the noise;
+    evaluating the model is the caller's (this module does no Tucker
+    arithmetic)."""
     N = len(dims)
     idx = [zipf_idx(seed, S_IDX + n, float(zipf[n]), int(dims[n]), n_obs) for n in range(N)]
     K = list(ranks)
     G = normal(seed, S_CORE, int(np.prod(K))).reshape(K, order="F")
     F = [normal(seed, S_PLANT + n, int(dims[n]) * K[n]).reshape(int(dims[n]), K[n]) / np.sqrt(K[n])
          for n in range(N)]
-    out = dict(dims=tuple(dims), idx=idx, ranks=tuple(ranks), G_true=G, F_true=F)
-    if with_values:
-        v = planted_values(K, G, F, idx) + noise * normal(seed, S_NOISE, n_obs)
-        out["vals"] = v.astype(np.float32)
-    return out
+    return dict(dims=tuple(dims), idx=idx, ranks=tuple(ranks), G_true=G, F_true=F,
+                noise=noise * normal(seed, S_NOISE, n_obs))

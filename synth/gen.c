@@ -2,8 +2,9 @@
  * Seeded synthetic inputs for sparse Tucker workloads.
  *
  * This file holds only random-number generation and the sampling recipes of
- * the synthetic tensors (coordinates, values, initial factors, a planted
- * completion model).  It contains none of the decomposition's arithmetic.
+ * the synthetic tensors (coordinates, values, initial factors, the draws of a
+ * planted completion model).  It contains none of the decomposition's
+ * arithmetic.
  * Both the FP64 checker and the GPU library consume the bytes written here,
  * so the two sides always see identical inputs.
  *
@@ -163,26 +164,4 @@ void synth_lognormal_f32_range(uint64_t seed, uint64_t stream, int64_t start, in
   uint64_t k = stream_key(seed, stream);
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < n; ++i) out[i] = (float)exp(normal_at(k, (uint64_t)(start + i)));
-}
-
-/* Planted Tucker model value at each observation:
- *   v_e = sum over core entries c of G[c] * prod_n F_n[idx_n[e], c_n]
- * with G stored first index fastest and F_n row-major (L_n x K_n).
- * Used only to synthesise completion targets; it is data generation. */
-void synth_planted_values(int N, const int64_t* K, const double* G, const double* const* F,
-                          int64_t n, const int32_t* const* idx, double* out) {
-  int64_t total = 1;
-  for (int j = 0; j < N; ++j) total *= K[j];
-#pragma omp parallel for schedule(static)
-  for (int64_t e = 0; e < n; ++e) {
-    double s = 0.0;
-    int64_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-    for (int64_t lin = 0; lin < total; ++lin) {
-      double p = G[lin];
-      for (int j = 0; j < N; ++j) p *= F[j][(int64_t)idx[j][e] * K[j] + c[j]];
-      s += p;
-      for (int j = 0; j < N; ++j) { if (++c[j] < K[j]) break; c[j] = 0; }
-    }
-    out[e] = s;
-  }
 }

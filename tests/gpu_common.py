@@ -68,3 +68,10 @@ def fit_noise(fit):
     difference of two such values at most twice that.  Fits that should not
     decrease (Gauss-Seidel HOOI) are allowed to drop by this much."""
     return max(1e-6, 4.0 * U32 / max(1.0 - fit, 1e-12))
+
+
+def completion_targets(d):
+    """Targets of a synth.make_completion problem: the planted model's values
+    (oracle) plus the generator's noise, rounded to FP32."""
+    from oracle import completion
+    return (completion.model_values(d["G_true"], d["F_true"], d["idx"]) + d["noise"]).astype(np.float32)

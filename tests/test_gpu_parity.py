@@ -8,7 +8,8 @@ import pytest
 
 import synth
 from oracle import coo, hooi, lite, ttm
-from tests.gpu_common import U32, factor_tolerance, fit_noise, oracle_Y, rel_fro, uniform_tensor, zipf_tensor
+from tests.gpu_common import (U32, completion_targets, factor_tolerance, fit_noise, oracle_Y, rel_fro,
+                              uniform_tensor, zipf_tensor)
 
 pytestmark = pytest.mark.gpu
 
@@ -422,7 +423,7 @@ def test_completion_eval_and_adjoint_match_oracle(tk):
     mv = ctx.tucker_eval(Gt, Ft).double().cpu().numpy()
     mo = completion.model_values(G32, F32, d["idx"])
     assert rel_fro(mv, mo) <= TOL
-    vals = d["vals"].astype(np.float64)
+    vals = completion_targets(d).astype(np.float64)
     g = 2.0 * (mo - vals)
     dG, dF = ctx.tucker_adjoint(torch.tensor(g, dtype=torch.float32, device="cuda"), Gt, Ft)
     dGo, dFo = completion.gradient(G32, F32, d["idx"], g=g.astype(np.float32).astype(np.float64))
@@ -462,13 +463,14 @@ def test_completion_autograd_function(tk):
     G = torch.tensor(rng.standard_normal(60), dtype=torch.float32, device="cuda", requires_grad=True)
     F = [torch.tensor(rng.standard_normal((L, K)), dtype=torch.float32, device="cuda", requires_grad=True)
          for L, K in zip(d["dims"], d["ranks"])]
-    v = torch.tensor(d["vals"], device="cuda")
+    vals = completion_targets(d)
+    v = torch.tensor(vals, device="cuda")
     m = tk.TuckerEval.apply(ctx, G, *F)
     loss = ((m - v) ** 2).sum()
     loss.backward()
     G64 = G.detach().double().cpu().numpy().reshape(d["ranks"], order="F")
     F64 = [f.detach().double().cpu().numpy() for f in F]
-    dGo, dFo = completion.gradient(G64, F64, d["idx"], vals=d["vals"])
+    dGo, dFo = completion.gradient(G64, F64, d["idx"], vals=vals)
     assert rel_fro(G.grad.double().cpu().numpy(), dGo.ravel(order="F")) <= 1e-4
     for n in range(3):
         assert rel_fro(F[n].grad.double().cpu().numpy(), dFo[n]) <= 1e-4

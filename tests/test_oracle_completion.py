@@ -60,7 +60,11 @@ def test_directional_derivative():
         assert an == pytest.approx(fd, rel=1e-6)
 
 
-def test_planted_generator_agrees_with_model_values():
-    d = synth.make_completion((20, 15, 10), 500, (3, 2, 2), noise=0.0, seed=7)
-    mv = completion.model_values(d["G_true"], d["F_true"], d["idx"])
-    np.testing.assert_allclose(d["vals"], mv.astype(np.float32), rtol=1e-6, atol=1e-6)
+def test_completion_generator_is_seeded_and_noise_scaled():
+    a = synth.make_completion((20, 15, 10), 4000, (3, 2, 2), noise=0.05, seed=7)
+    b = synth.make_completion((20, 15, 10), 4000, (3, 2, 2), noise=0.05, seed=7)
+    for x, y in zip(a["idx"], b["idx"]):
+        np.testing.assert_array_equal(x, y)
+    np.testing.assert_array_equal(a["noise"], b["noise"])
+    assert abs(np.std(a["noise"]) - 0.05) < 0.005
+    assert all(i.min() >= 0 and i.max() < L for i, L in zip(a["idx"], (20, 15, 10)))
