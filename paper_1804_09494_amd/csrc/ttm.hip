@@ -716,19 +716,48 @@ __device__ __forceinline__ float fix_sum(const float* __restrict__ buf, int a, i
   }
   return s;
 }
-__global__ void k_fixup_level(const int32_t* __restrict__ lo, const int32_t* __restrict__ hi, int64_t first,
-                              float* __restrict__ buf, int khat) {
-  const int64_t t = blockIdx.x;
-  const int a = lo[t], b = hi[t];
-  float* out = buf + (first + t) * khat;
-  for (int c = threadIdx.x; c < khat; c += blockDim.x) out[c] = fix_sum(buf, a, b, khat, c);
+// One wave per run of rows (four runs per workgroup): lane l sums columns
+// l, l + 64, ... of rows [a, b) of buf in row order into out; with khat a
+// multiple of 4, four columns per lane through 16-byte loads.  Each column's
+// adds keep fix_sum's order, so the result does not depend on the form.
+__device__ __forceinline__ void fix_sum_wave(const float* __restrict__ buf, int a, int b, int khat,
+                                             float* __restrict__ out) {
+  const int lane = threadIdx.x & 63;
+  if ((khat & 3) == 0) {
+    const int kq = khat >> 2;
+    for (int c4 = lane; c4 < kq; c4 += 64) {
+      floatx4_t s = {0.f, 0.f, 0.f, 0.f};
+      for (int a0 = a; a0 < b; a0 += 8) {
+        floatx4_t v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          v[i] = a0 + i < b ? reinterpret_cast<const floatx4_t*>(buf + (int64_t)(a0 + i) * khat)[c4]
+                            : floatx4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int i = 0; i < 8; ++i)
+          if (a0 + i < b) s += v[i];
+      }
+      reinterpret_cast<floatx4_t*>(out)[c4] = s;
+    }
+  } else {
+    for (int c = lane; c < khat; c += 64) out[c] = fix_sum(buf, a, b, khat, c);
+  }
 }
-__global__ void k_fixup(const int32_t* __restrict__ bad_row, const int32_t* __restrict__ fin, int64_t nbad,
-                        const float* __restrict__ buf, int khat, float* __restrict__ Y) {
-  const int64_t k = blockIdx.x;
-  const int a = fin[k], b = fin[nbad + k];
-  const int64_t row = bad_row[k];
-  for (int c = threadIdx.x; c < khat; c += blockDim.x) Y[row * khat + c] = fix_sum(buf, a, b, khat, c);
+constexpr int FIX_WAVES = 4;   // runs per workgroup
+__global__ __launch_bounds__(64 * FIX_WAVES) void k_fixup_level(const int32_t* __restrict__ lo,
+                                                                const int32_t* __restrict__ hi, int64_t first,
+                                                                int64_t nl, float* __restrict__ buf, int khat) {
+  const int64_t t = (int64_t)blockIdx.x * FIX_WAVES + (threadIdx.x >> 6);
+  if (t >= nl) return;
+  fix_sum_wave(buf, lo[t], hi[t], khat, buf + (first + t) * khat);
+}
+__global__ __launch_bounds__(64 * FIX_WAVES) void k_fixup(const int32_t* __restrict__ bad_row,
+                                                          const int32_t* __restrict__ fin, int64_t nbad,
+                                                          const float* __restrict__ buf, int khat,
+                                                          float* __restrict__ Y) {
+  const int64_t k = (int64_t)blockIdx.x * FIX_WAVES + (threadIdx.x >> 6);
+  if (k >= nbad) return;
+  fix_sum_wave(buf, fin[k], fin[nbad + k], khat, Y + (int64_t)bad_row[k] * khat);
 }
 
 // ---- dispatch -----------------------------------------------------------------------------------
@@ -880,18 +909,18 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   if (c->ev_ttm[1]) TK_HIP(hipEventRecord(c->ev_ttm[1], c->stream));
   if (pl.n_bad > 0) {
-    const int thr = pl.khat > 128 ? 256 : 128;
     float* buf = partial;
     int64_t first = pl.n_slots, off = 0;
     for (int64_t nl : pl.fix_n) {
       const int32_t* lohi = pl.fix_lohi.as<int32_t>() + off;
-      hipLaunchKernelGGL(k_fixup_level, dim3((unsigned)nl), dim3(thr), 0, c->stream, lohi, lohi + nl, first, buf,
-                         (int)pl.khat);
+      hipLaunchKernelGGL(k_fixup_level, dim3((unsigned)ceil_div(nl, FIX_WAVES)), dim3(64 * FIX_WAVES), 0, c->stream,
+                         lohi, lohi + nl, first, nl, buf, (int)pl.khat);
       TK_CHECK_LAUNCH();
       first += nl;
       off += 2 * nl;
     }
-    hipLaunchKernelGGL(k_fixup, dim3((unsigned)pl.n_bad), dim3(thr), 0, c->stream, pl.bad_row.as<int32_t>(),
+    hipLaunchKernelGGL(k_fixup, dim3((unsigned)ceil_div(pl.n_bad, FIX_WAVES)), dim3(64 * FIX_WAVES), 0, c->stream,
+                       pl.bad_row.as<int32_t>(),
                        pl.fix_fin.as<int32_t>(), pl.n_bad, buf, (int)pl.khat, Y);
     TK_CHECK_LAUNCH();
   }
