@@ -26,7 +26,8 @@ void eig_topk_matfree(Ctx* c, const float* Y, int64_t R, int khat, int K, double
 bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const double* gdiag, int64_t dstride,
                  const double* lam_k,
                  const double* VK, int* flag_dev, bool deferred);
-void complete_factor(Ctx* c, int n);
+void complete_factor(Ctx* c, int n, int g);
+int computed_columns(Ctx* c, const int* flag_dev, int n);
 void core_from_last(Ctx* c, const float* Y, double* core, double* out2);
 void obs_eval(Ctx* c, const float* core, const float* const* F, float* model, tk_mem mem);
 void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* F, float* dcore, float* const* dF,
@@ -121,7 +122,7 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
   ensure(c, c->gram64, sizeof(double) * (size_t)std::max<int64_t>(maxKhG * maxKhG, 1));
   if (maxKhG < maxKh) ensure(c, c->diag64, sizeof(double) * (size_t)maxKh);
   ensure(c, c->eig_val, sizeof(double) * 64 + sizeof(double) * (size_t)maxKh * 64);
-  ensure(c, c->flag, sizeof(int) * 4);
+  ensure(c, c->flag, sizeof(int) * FLAG_INTS);
   int64_t core_n = 1;
   for (int j = 0; j < N; ++j) core_n *= c->K[j];
   ensure(c, c->core64, sizeof(double) * (size_t)core_n + 2 * sizeof(double));
@@ -201,7 +202,10 @@ void hooi_iterate(Ctx* c, int iters, double* fits) {
       if (failed > 0) {
         const int n0 = failed - 1;
         if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
-        complete_factor(c, n0);
+        int bits = 0;
+        d2h(c, &bits, c->flag.as<int>() + FLAG_BITS + n0, 1);
+        c->sync();
+        complete_factor(c, n0, bits == 2 ? computed_columns(c, c->flag.as<int>(), n0) : -1);
         TK_HIP(hipMemsetAsync(c->flag.as<int>() + 1, 0, sizeof(int), c->stream));
         // the skipped modes' factor copies were not cleared on the device (the
         // clear was conditional on no earlier failure) although their host-side

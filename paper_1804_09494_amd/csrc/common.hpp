@@ -39,6 +39,13 @@ struct Error {
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// HOOI failure flags (int32, device): [0] the current mode's bits (1 = a
+// Cholesky pivot failed, 2 = a column below the rank floor), [1] 1 + the first
+// failed mode of a deferred invocation, [FLAG_BITS + n] mode n's bits, and
+// [FLAG_KVALID + n] mode n's number of columns above the floor.
+constexpr int FLAG_BITS = 2;
+constexpr int FLAG_KVALID = FLAG_BITS + 8;
+constexpr int FLAG_INTS = FLAG_KVALID + 8;
 constexpr int FIX_CHUNK = 128;  // partial rows summed per fixup block (one tree level for up to 16K)
 
 struct Ctx;

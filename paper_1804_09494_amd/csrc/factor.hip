@@ -259,6 +259,18 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* __restrict__ pa
   }
 }
 
+// Row j of A beyond the diagonal is exactly zero.  A column of U zeroed below
+// the rank floor (W = 0, so U's column is exactly 0.0) has an exactly zero row
+// and column in A = U^T U, and every earlier step leaves them so: the Cholesky
+// steps below take R[j][j] = 1 for it, so that U R^-1 keeps it zero and the
+// other columns come out orthonormal; it is not a failure (the completion adds
+// that direction).
+__device__ __forceinline__ bool zero_row(const double* A, int K, int j) {
+  for (int i = j + 1; i < K; ++i)
+    if (A[j * K + i] != 0.0) return false;
+  return true;
+}
+
 // Cholesky A = R^T R of the summed K x K matrix, Rinv = R^-1.
 // flag bit 0 set when a pivot is not positive relative to the largest diagonal.
 __global__ void k_chol_inv(const double* __restrict__ Asum, int K, double* __restrict__ Rinv, int* __restrict__ flag) {
@@ -275,6 +287,10 @@ __global__ void k_chol_inv(const double* __restrict__ Asum, int K, double* __res
     for (int j = 0; j < K && ok; ++j) {
       double d = A[j * K + j];
       for (int k = 0; k < j; ++k) d -= Rm[k * K + j] * Rm[k * K + j];
+      if (A[j * K + j] == 0.0 && d == 0.0 && zero_row(A, K, j)) {   // a zeroed column stays zero (R[j][j] = 1)
+        Rm[j * K + j] = 1.0;
+        continue;
+      }
       if (!(d > 1e-16 * dmax)) { ok = false; break; }
       const double rjj = sqrt(d);
       Rm[j * K + j] = rjj;
@@ -320,7 +336,13 @@ __global__ __launch_bounds__(64) void k_chol_inv_wave(const double* __restrict__
   // A = R^T R, R stored in the upper triangle of A (row j: R[j][j..K-1])
   for (int j = 0; j < K && okf; ++j) {
     const double d = A[j * K + j];
+    const bool zr = Asum[j * K + j] == 0.0 && d == 0.0 && zero_row(A, K, j);   // the same in every lane
     __syncthreads();
+    if (zr) {   // a zeroed column stays zero (R[j][j] = 1); its row of R is zero
+      if (l == 0) { A[j * K + j] = 1.0; rdiag[j] = 1.0; }
+      __syncthreads();
+      continue;
+    }
     if (!(d > 1e-16 * dmax)) {
       if (l == 0) okf = 0;
       __syncthreads();
@@ -376,7 +398,8 @@ constexpr double RANK_FLOOR = 4.0 / 16777216.0;   // 4 u
 // Gram itself, 1 for a separate vector).
 __global__ __launch_bounds__(256) void k_make_w(const double* __restrict__ VK, const double* __restrict__ lam,
                                                 const double* __restrict__ diag, int64_t dstride, int khat, int K,
-                                                double* __restrict__ W, int* __restrict__ flag) {
+                                                double* __restrict__ W, int* __restrict__ flag,
+                                                int* __restrict__ kvalid) {
   __shared__ double red[256];
   double t = 0.0;
   for (int i = threadIdx.x; i < khat; i += 256) t += diag[(int64_t)i * dstride];
@@ -387,6 +410,11 @@ __global__ __launch_bounds__(256) void k_make_w(const double* __restrict__ VK, c
     __syncthreads();
   }
   const double floor_ = RANK_FLOOR * red[0];
+  if (blockIdx.x == 0 && threadIdx.x == 0) {   // eigenvalues come in descending order
+    int kv = 0;
+    while (kv < K && kv < khat && lam[kv] > floor_ && lam[kv] > 0.0) ++kv;
+    *kvalid = kv;
+  }
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < khat * K; i += gridDim.x * blockDim.x) {
     const int k = i % K;
     const bool ok = k < khat && lam[k] > floor_ && lam[k] > 0.0;  // only khat eigenpairs exist
@@ -571,20 +599,25 @@ void apply_rows_times(Ctx* c, int n, const std::vector<double>& T, double* dev) 
 
 }  // namespace
 
-static void complete_on_device(Ctx* c, int n) {
+static void complete_on_device(Ctx* c, int n, int g_known) {
   const int64_t L = c->dims[n];
   const int K = c->K[n];
   const int KK = K * K;
   TK_REQUIRE(K <= 32, TK_ERR_UNSUPPORTED, "completion: rank above 32");
   ensure(c, c->small64, sizeof(double) * (size_t)KK * (2 + 1024));
   double* dev = c->small64.as<double>();
-  // orthonormal computed columns: two passes
+  // orthonormal computed columns: two passes, unless the factor step already
+  // orthonormalised them (its only failure was the rank floor)
   int g = K;
-  for (int pass = 0; pass < 2; ++pass) {
-    const std::vector<double> A = factor_gram(c, n, dev);
-    std::vector<double> T;
-    g = coeff_gram_schmidt(A, K, T);
-    apply_rows_times(c, n, T, dev);
+  if (g_known >= 0) {
+    g = g_known;
+  } else {
+    for (int pass = 0; pass < 2; ++pass) {
+      const std::vector<double> A = factor_gram(c, n, dev);
+      std::vector<double> T;
+      g = coeff_gram_schmidt(A, K, T);
+      apply_rows_times(c, n, T, dev);
+    }
   }
   if (g == K) {
     refresh_factor_copies(c, n);
@@ -672,7 +705,8 @@ static void complete_on_device(Ctx* c, int n) {
   c->sync();
 }
 
-void complete_factor(Ctx* c, int n);
+void complete_factor(Ctx* c, int n, int g);
+int computed_columns(Ctx* c, const int* flag_dev, int n);
 
 // U = Y W (R x K, FP64 out) on the matrix cores for K <= 16, W khat x K in
 // FP64 (rounded to FP32 for the MFMA operands); `part` receives nwg x K x K
@@ -703,6 +737,7 @@ __global__ void k_clear_unless(uint16_t* __restrict__ p, int64_t n16, const int*
 
 // flag[0]: this mode's failure flag; flag[1]: 1 + the first failed mode of the invocation
 __global__ void k_flag_record(int* flag, int n) {
+  flag[FLAG_BITS + n] = flag[0];
   if (flag[0] && !flag[1]) flag[1] = n + 1;
 }
 
@@ -735,7 +770,7 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   const ModePlan& pl = c->plan[n];
   TK_HIP(hipMemsetAsync(flag_dev, 0, sizeof(int), c->stream));
   hipLaunchKernelGGL(k_make_w, dim3(grid_for((int64_t)khat * K, 256, 64)), dim3(256), 0, c->stream, VK, lam_k, gdiag,
-                     dstride, khat, K, W, flag_dev);
+                     dstride, khat, K, W, flag_dev, flag_dev + FLAG_KVALID + n);
   TK_CHECK_LAUNCH();
   // rows of empty slices (never written below) must be zero: clear the copies
   // only when something else may have written them (tk_set_factor, completion)
@@ -830,17 +865,27 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   if (hflag[1]) return false;   // an earlier mode failed: this mode runs again later
   if (hflag[0] || R < K) {
     if (!c->opt.complete_rank_deficient) fail(TK_ERR_NUMERIC, "rank-deficient penultimate matrix");
-    complete_factor(c, n);
+    complete_factor(c, n, hflag[0] == 2 && R >= K ? computed_columns(c, flag_dev, n) : -1);
     return true;
   }
   return false;
 }
 
+// Columns of factor n above the rank floor, as its factor step recorded them.
+int computed_columns(Ctx* c, const int* flag_dev, int n) {
+  int kv = 0;
+  d2h(c, &kv, flag_dev + FLAG_KVALID + n, 1);
+  c->sync();
+  return kv;
+}
+
 // Complete factor n (rank-deficient penultimate matrix) on the host.
-void complete_factor(Ctx* c, int n) {
+// g >= 0: the factor step failed only on the rank floor, so columns 0..g-1
+// are already orthonormal and the rest exactly zero.
+void complete_factor(Ctx* c, int n, int g) {
   ++c->counters.rank_completions;
   c->completed_once = true;
-  complete_on_device(c, n);
+  complete_on_device(c, n, g);
   c->fac_dirty[n] = true;   // completion may use rows of empty slices
 }
 
