@@ -62,6 +62,70 @@ __global__ __launch_bounds__(256) void k_core_part(const float* __restrict__ Y, 
   }
 }
 
+// The same partial for Khat <= 128 over CORE_ROWS2 rows: thread t owns column
+// t % 128 for one half of the rows (t / 128), the halves' sums are added in
+// LDS (first half + second half), so a workgroup reads four times the rows of
+// k_core_part with every thread busy and writes a quarter of the partials.
+constexpr int CORE_ROWS2 = 256;
+template <int KM>
+__global__ __launch_bounds__(256) void k_core_part2(const float* __restrict__ Y, int64_t R, int khat,
+                                                    const double* __restrict__ F, int K,
+                                                    const int32_t* __restrict__ row_slice,
+                                                    double* __restrict__ part) {
+  __shared__ __align__(16) double ft[CORE_ROWS2 * KM];
+  __shared__ double hsum[128 * KM];
+  static_assert(KM % 2 == 0, "entries are read in pairs");
+  const int64_t r0 = (int64_t)blockIdx.x * CORE_ROWS2;
+  const int nr = (int)min<int64_t>(CORE_ROWS2, R - r0);
+  const int t = threadIdx.x, col = t & 127, h = t >> 7;
+  const bool ok = col < khat;
+  const int cl = ok ? col : 0;
+  const int k0 = blockIdx.z * KM, kn = min(KM, K - k0);
+  for (int i = t; i < nr * KM; i += 256) {
+    const int r = i / KM, k = i - r * KM;
+    ft[i] = k < kn ? F[(int64_t)row_slice[r0 + r] * K + k0 + k] : 0.0;
+  }
+  __syncthreads();
+  const int half = (nr + 1) >> 1;
+  const int ra = h ? half : 0, rb = h ? nr : half;
+  double acc[KM];
+#pragma unroll
+  for (int k = 0; k < KM; ++k) acc[k] = 0.0;
+  const float* yb = Y + r0 * khat + cl;
+  int r = ra;
+  for (; r + 16 <= rb; r += 16) {
+    float y[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) y[u] = yb[(int64_t)(r + u) * khat];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const double2* fr = reinterpret_cast<const double2*>(ft + (r + u) * KM);   // 16-byte broadcasts
+#pragma unroll
+      for (int k2 = 0; k2 < KM / 2; ++k2) {
+        const double2 f = fr[k2];
+        acc[2 * k2] += f.x * (double)y[u];
+        acc[2 * k2 + 1] += f.y * (double)y[u];
+      }
+    }
+  }
+  for (; r < rb; ++r) {
+    const double y = (double)yb[(int64_t)r * khat];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) acc[k] += ft[r * KM + k] * y;
+  }
+  if (h) {
+#pragma unroll
+    for (int k = 0; k < KM; ++k) hsum[k * 128 + col] = acc[k];
+  }
+  __syncthreads();
+  if (!h && ok) {
+    const int64_t nent = (int64_t)K * khat;
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+      if (k < kn) part[(int64_t)blockIdx.x * nent + (int64_t)(k0 + k) * khat + col] = acc[k] + hsum[k * 128 + col];
+  }
+}
+
 constexpr int CORE_GROUP = 32;   // workgroup partials summed per first-level thread
 
 // Level 1: sums of CORE_GROUP consecutive workgroup partials (fixed order).
@@ -111,7 +175,8 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   const int64_t R = pl.L_nz;
   const int khat = (int)pl.khat;
   const int K = c->K[n];
-  const int rows_per_wg = CORE_ROWS;
+  const bool narrow = khat <= 128;
+  const int rows_per_wg = narrow ? CORE_ROWS2 : CORE_ROWS;
   const int nwg = (int)std::max<int64_t>(1, ceil_div(R, rows_per_wg));
   const int nent = K * khat;
   const int ngroups = (nwg + CORE_GROUP - 1) / CORE_GROUP;
@@ -119,9 +184,23 @@ void core_from_last(Ctx* c, const float* Y, double* core, double* out2) {
   double* part = c->gram_part.as<double>();
   double* gsum = part + (size_t)nwg * nent;
   if (R > 0) {
-    const dim3 g((unsigned)nwg, (unsigned)ceil_div(khat, 256), (unsigned)ceil_div(K, 16));
-    hipLaunchKernelGGL(k_core_part<16>, g, dim3(256), 0, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
-                       pl.row_slice.as<int32_t>(), rows_per_wg, part);
+    if (narrow) {
+      // entries per pass: K rounded up to 4, at most 16
+      const int km = K <= 4 ? 4 : K <= 8 ? 8 : K <= 12 ? 12 : 16;
+      const dim3 g((unsigned)nwg, 1, (unsigned)ceil_div(K, km));
+      const double* F64 = c->F64[n].as<double>();
+      const int32_t* rs = pl.row_slice.as<int32_t>();
+      switch (km) {
+        case 4: hipLaunchKernelGGL(k_core_part2<4>, g, dim3(256), 0, c->stream, Y, R, khat, F64, K, rs, part); break;
+        case 8: hipLaunchKernelGGL(k_core_part2<8>, g, dim3(256), 0, c->stream, Y, R, khat, F64, K, rs, part); break;
+        case 12: hipLaunchKernelGGL(k_core_part2<12>, g, dim3(256), 0, c->stream, Y, R, khat, F64, K, rs, part); break;
+        default: hipLaunchKernelGGL(k_core_part2<16>, g, dim3(256), 0, c->stream, Y, R, khat, F64, K, rs, part); break;
+      }
+    } else {
+      const dim3 g((unsigned)nwg, (unsigned)ceil_div(khat, 256), (unsigned)ceil_div(K, 16));
+      hipLaunchKernelGGL(k_core_part<16>, g, dim3(256), 0, c->stream, Y, R, khat, c->F64[n].as<double>(), K,
+                         pl.row_slice.as<int32_t>(), rows_per_wg, part);
+    }
     TK_CHECK_LAUNCH();
     hipLaunchKernelGGL(k_core_group, dim3((unsigned)ceil_div(nent, 256), ngroups), dim3(256), 0, c->stream, part,
                        nwg, nent, gsum);
