@@ -212,6 +212,8 @@ struct Ctx {
   Buf eig_warm[8];        // last eigenvectors of each mode's Gram (Krylov warm start)
   int eig_warm_k[8] = {0};
   bool fac_dirty[8] = {true, true, true, true, true, true, true, true};   // rows of empty slices may be nonzero
+  Buf unit_rows[8];       // int32: rows of empty slices a completion set to unit vectors (device)
+  int n_unit_rows[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // how many; the next factor step zeroes them
   Buf core64;             // double[prod K]
   Buf flag;               // int32 flags
 

@@ -463,9 +463,11 @@ void refresh_factor_copies(Ctx* c, int n) {
 // ---- completion of a rank-deficient factor ----------------------------------------------------
 //
 // The factor's computed columns are orthonormalised, the ones that vanish are
-// dropped, and the missing columns come from unit vectors e_i (lowest i first)
-// made orthogonal to everything before them.  The columns are not unique; only
-// their span with the computed ones and their orthonormality are fixed.
+// dropped, and the missing columns are unit vectors: at the lowest-index empty
+// slices when the mode has enough of them (the computed columns are zero on
+// those rows), else e_i (lowest i first) made orthogonal to everything before
+// them.  The columns are not unique; only their span with the computed ones
+// and their orthonormality are fixed.
 //
 // On the device: two passes of (Gram F^T F, FP64 over the L rows; Gram-Schmidt
 // of the columns in coefficient space on the host, K x K; F <- F T in place).
@@ -599,7 +601,47 @@ void apply_rows_times(Ctx* c, int n, const std::vector<double>& T, double* dev) 
 
 }  // namespace
 
-static void complete_on_device(Ctx* c, int n, int g_known) {
+// ids[t], t < M: the t-th empty slice (ascending) of a mode with nonempty
+// slices row_slice[0..R) (ascending).  Before row_slice[r] lie row_slice[r] - r
+// empty ids, so the t-th is t + r for the first r with row_slice[r] - r > t
+// (r = R when the empty ids past the last nonempty slice are reached).
+__global__ void k_find_empty(const int32_t* __restrict__ row_slice, int64_t R, int M, int32_t* __restrict__ ids) {
+  const int t = threadIdx.x;
+  if (t >= M) return;
+  int64_t lo = 0, hi = R;   // first r in [0, R] with row_slice[r] - r > t
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if ((int64_t)row_slice[mid] - mid > t) hi = mid; else lo = mid + 1;
+  }
+  ids[t] = (int32_t)(t + lo);
+}
+
+// Column g + t of factor n becomes e_{ids[t]} (its FP64 row and its FP32 copy at
+// the row's storage label): the rows were zero, as rows of empty slices are.
+__global__ void k_set_units(const int32_t* __restrict__ ids, int M, int g, int K, const int32_t* __restrict__ label,
+                            double* __restrict__ F64, float* __restrict__ F32, int kp32) {
+  const int t = threadIdx.x;
+  if (t >= M) return;
+  const int64_t i = ids[t];
+  F64[i * K + g + t] = 1.0;
+  F32[(int64_t)label[i] * kp32 + g + t] = 1.0f;
+}
+
+// Zero the rows ids[0..M) of factor n (FP64 and FP32 copy), unless an earlier
+// mode of this invocation failed.
+__global__ void k_zero_rows(const int32_t* __restrict__ ids, int M, int K, const int32_t* __restrict__ label,
+                            double* __restrict__ F64, float* __restrict__ F32, int kp32, const int* __restrict__ abort) {
+  if (abort && *abort) return;
+  for (int q = threadIdx.x; q < M * K; q += blockDim.x) {
+    const int t = q / K, k = q - t * K;
+    const int64_t i = ids[t];
+    F64[i * K + k] = 0.0;
+    F32[(int64_t)label[i] * kp32 + k] = 0.0f;
+  }
+}
+
+// Returns true when the missing columns are unit vectors at rows of empty slices.
+static bool complete_on_device(Ctx* c, int n, int g_known) {
   const int64_t L = c->dims[n];
   const int K = c->K[n];
   const int KK = K * K;
@@ -622,7 +664,24 @@ static void complete_on_device(Ctx* c, int n, int g_known) {
   if (g == K) {
     refresh_factor_copies(c, n);
     c->sync();
-    return;
+    return false;
+  }
+  // a mode with enough empty slices: the computed columns vanish on those rows,
+  // so unit vectors there are already orthogonal to them and to each other
+  const ModePlan& pl = c->plan[n];
+  const int M = K - g;
+  if (L - pl.L_nz >= M) {
+    ensure(c, c->unit_rows[n], sizeof(int32_t) * 32);
+    int32_t* ids = c->unit_rows[n].as<int32_t>();
+    hipLaunchKernelGGL(k_find_empty, dim3(1), dim3(32), 0, c->stream, pl.row_slice.as<int32_t>(), pl.L_nz, M, ids);
+    TK_CHECK_LAUNCH();
+    if (g_known < 0) refresh_factor_copies(c, n);   // the passes above rewrote F64
+    hipLaunchKernelGGL(k_set_units, dim3(1), dim3(32), 0, c->stream, ids, M, g, K, pl.label.as<int32_t>(),
+                       c->F64[n].as<double>(), c->F32[n].as<float>(), c->kp32[n]);
+    TK_CHECK_LAUNCH();
+    c->n_unit_rows[n] = M;
+    c->sync();
+    return true;
   }
   // unit vectors e_i, lowest i first.  A column is (b, a): Q b + sum_r a[r] e_{cand[r]}.
   struct Col {
@@ -703,6 +762,7 @@ static void complete_on_device(Ctx* c, int n, int g_known) {
   h2d(c, c->F64[n].as<double>(), patch.data(), patch.size());
   refresh_factor_copies(c, n);
   c->sync();
+  return false;
 }
 
 void complete_factor(Ctx* c, int n, int g);
@@ -775,7 +835,16 @@ bool form_factor(Ctx* c, int n, const float* Y, int64_t R, int khat, const doubl
   // rows of empty slices (never written below) must be zero: clear the copies
   // only when something else may have written them (tk_set_factor, completion)
   auto clear_factor = [&]() {
+    if (!c->fac_dirty[n] && c->n_unit_rows[n] > 0) {
+      const int M = c->n_unit_rows[n];
+      hipLaunchKernelGGL(k_zero_rows, dim3(1), dim3(256), 0, c->stream, c->unit_rows[n].as<int32_t>(), M, K,
+                         pl.label.as<int32_t>(), c->F64[n].as<double>(), c->F32[n].as<float>(), c->kp32[n], abort);
+      TK_CHECK_LAUNCH();
+      c->n_unit_rows[n] = 0;
+      return;
+    }
     if (!c->fac_dirty[n]) return;
+    c->n_unit_rows[n] = 0;
     if (abort) {
       // deferred check: a later pass may have to keep this factor as it was;
       // the clear then does not happen, and the driver marks the factor dirty
@@ -885,8 +954,9 @@ int computed_columns(Ctx* c, const int* flag_dev, int n) {
 void complete_factor(Ctx* c, int n, int g) {
   ++c->counters.rank_completions;
   c->completed_once = true;
-  complete_on_device(c, n, g);
-  c->fac_dirty[n] = true;   // completion may use rows of empty slices
+  // the unit-vector rows of empty slices are zeroed by the next factor step
+  // (only those rows after a completion by k_set_units, all of them otherwise)
+  if (!complete_on_device(c, n, g)) c->fac_dirty[n] = true;
 }
 
 }  // namespace tk
