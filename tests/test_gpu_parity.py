@@ -375,6 +375,9 @@ def test_rank_deficient_completion(tk):
     ctx.hooi_iterate(1)
     F = ctx.get_factor(0)
     np.testing.assert_allclose(F.T @ F, np.eye(4), atol=1e-12)
+    # the missing column is the unit vector at the lowest-index empty slice (3)
+    np.testing.assert_array_equal(F[:, 3], np.eye(6)[3])
+    assert np.all(F[3:, :3] == 0.0)
 
 
 def test_rank_deficient_mid_sweep_matches_oracle(tk):
