@@ -62,8 +62,13 @@ __device__ __forceinline__ void macro_pair(bool diag, int p, int MB, int& I, int
   J = I + 1 + p;
 }
 
+// Macro pairs of up to 4 x 4 tiles are capped at four waves per SIMD (at most
+// 128 registers per lane; the compiler's own choice, 154, allows three): the
+// waves wait on their loads for most of their cycles, and the fourth hides
+// more of it (the wide c3 Gram 34.7 -> 32.2 ms).  Larger macro pairs would spill.
 template <int NBA, int NBB, bool DIAG>
-__global__ __launch_bounds__(256) void k_gram(const float* __restrict__ Y, int64_t R, int khat, int rows_per_wg,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NBA * NBB <= 16 ? 4 : 1))) void k_gram(
+    const float* __restrict__ Y, int64_t R, int khat, int rows_per_wg,
                                               int MB, float* __restrict__ part) {
   using TS = TileSet<NBA, NBB, DIAG>;
   constexpr int T = TS::count;
