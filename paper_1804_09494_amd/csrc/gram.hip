@@ -227,29 +227,38 @@ __global__ __launch_bounds__(256) void k_gram_bf16(const float* __restrict__ Y, 
 // operand (column c, rows 8*(l/16) .. +7 of the block) is one 16-byte load.
 // Values are rounded to nearest even, as the direct kernel rounds them in
 // registers; rows past R and columns past Khat are zero.  One workgroup turns
-// a 32 x 64 tile around through LDS.
+// 32 rows x 256 columns around through LDS, 64 columns at a time, reading Y
+// with 16-byte loads when Khat is a multiple of 4.
+constexpr int YB_COLS = 256;   // columns per workgroup
 __global__ __launch_bounds__(256) void k_y_bf16_blocked(const float* __restrict__ Y, int64_t R, int khat, int KP,
                                                         __bf16* __restrict__ Yb) {
   __shared__ float t[32][65];
   const int64_t rb = blockIdx.x;
-  const int c0 = blockIdx.y * 64;
   const int tid = threadIdx.x;
-  {
-    const int r = tid >> 3, cq = (tid & 7) * 8;
-    const int64_t row = rb * 32 + r;
+  const int r = tid >> 3, cq = (tid & 7) * 8;
+  const int64_t row = rb * 32 + r;
+  const bool vec = (khat & 3) == 0;
+  const int cend = min(KP, (int)(blockIdx.y + 1) * YB_COLS);
+  for (int c0 = blockIdx.y * YB_COLS; c0 < cend; c0 += 64) {
+    const int col = c0 + cq;
+    if (row < R && vec && col + 8 <= khat) {
+      const float4* src = reinterpret_cast<const float4*>(Y + row * khat + col);
+      const float4 a = src[0], b = src[1];
+      t[r][cq + 0] = a.x; t[r][cq + 1] = a.y; t[r][cq + 2] = a.z; t[r][cq + 3] = a.w;
+      t[r][cq + 4] = b.x; t[r][cq + 5] = b.y; t[r][cq + 6] = b.z; t[r][cq + 7] = b.w;
+    } else {
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int col = c0 + cq + q;
-      t[r][cq + q] = (row < R && col < khat) ? Y[row * khat + col] : 0.f;
+      for (int q = 0; q < 8; ++q) t[r][cq + q] = (row < R && col + q < khat) ? Y[row * khat + col + q] : 0.f;
     }
-  }
-  __syncthreads();
-  const int c = tid >> 2, g = tid & 3;
-  if (c0 + c < KP) {
-    bf16x8 v;
+    __syncthreads();
+    const int c = tid >> 2, g = tid & 3;
+    if (c0 + c < KP) {
+      bf16x8 v;
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (__bf16)t[8 * g + q][c];
-    *reinterpret_cast<bf16x8*>(Yb + ((rb * KP + c0 + c) * 32 + 8 * g)) = v;
+      for (int q = 0; q < 8; ++q) v[q] = (__bf16)t[8 * g + q][c];
+      *reinterpret_cast<bf16x8*>(Yb + ((rb * KP + c0 + c) * 32 + 8 * g)) = v;
+    }
+    __syncthreads();
   }
 }
 
@@ -432,7 +441,7 @@ static void gram_impl(Ctx* c, const float* Y, int64_t R, int khat, double* G) {
     KP = NB * 16;
     const int64_t RB = ceil_div(R, 32);
     ensure(c, c->ybf, sizeof(uint16_t) * (size_t)RB * KP * 32);
-    hipLaunchKernelGGL(k_y_bf16_blocked, dim3((unsigned)RB, (unsigned)ceil_div(KP, 64)), dim3(256), 0, c->stream, Y, R,
+    hipLaunchKernelGGL(k_y_bf16_blocked, dim3((unsigned)RB, (unsigned)ceil_div(KP, YB_COLS)), dim3(256), 0, c->stream, Y, R,
                        khat, KP, c->ybf.as<__bf16>());
     TK_CHECK_LAUNCH();
     Yb = c->ybf.as<__bf16>();
