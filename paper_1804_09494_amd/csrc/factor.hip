@@ -117,18 +117,29 @@ __global__ __launch_bounds__(256) void k_uw_mfma(const float* __restrict__ Y, in
     const bool rok = row < R;
     const float* yr = Y + row * khat;
     floatx4_f c = {0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < kpad; s += 16) {
-      const int col = s + 4 * q;
-      float y[4];
-      if (VEC) {
-        const float4 v = (rok && col < khat) ? *reinterpret_cast<const float4*>(yr + col) : float4{0.f, 0.f, 0.f, 0.f};
-        y[0] = v.x; y[1] = v.y; y[2] = v.z; y[3] = v.w;
-      } else {
+    // four 16-column steps per iteration, their loads issued before the first
+    // MFMA (the MFMAs keep their order: same U as one step at a time)
+    for (int s = 0; s < kpad; s += 64) {
+      float y[4][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) y[u] = (rok && col + u < khat) ? yr[col + u] : 0.f;
+      for (int d = 0; d < 4; ++d) {
+        const int col = s + 16 * d + 4 * q;
+        if (VEC) {
+          const float4 v = (rok && col < khat) ? *reinterpret_cast<const float4*>(yr + col) : float4{0.f, 0.f, 0.f, 0.f};
+          y[d][0] = v.x; y[d][1] = v.y; y[d][2] = v.z; y[d][3] = v.w;
+        } else {
+#pragma unroll
+          for (int u = 0; u < 4; ++u) y[d][u] = (rok && col + u < khat) ? yr[col + u] : 0.f;
+        }
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) c = __builtin_amdgcn_mfma_f32_16x16x4f32(y[u], wl[(col + u) * 16 + i16], c, 0, 0, 0);
+      for (int d = 0; d < 4; ++d) {
+        if (s + 16 * d >= kpad) break;   // the same in every lane
+        const int col = s + 16 * d + 4 * q;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+          c = __builtin_amdgcn_mfma_f32_16x16x4f32(y[d][u], wl[(col + u) * 16 + i16], c, 0, 0, 0);
+      }
     }
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
