@@ -238,7 +238,9 @@ tk_status tk_ttm_shape(tk_ctx* ctx, int n, int64_t* R_n, int64_t* Khat_n);
 /* TTM-chain along mode n with the current factors (eq. 1): Y gets the rows of
  * the nonempty slices in ascending slice id (R_n x Khat_n, row-major FP32);
  * row_slice (may be NULL) gets their slice ids (int32).  With prec = TK_BF16
- * the Kronecker tiles are BF16 on the matrix cores (where such a kernel runs). */
+ * the Kronecker tiles are BF16 on the matrix cores (where such a kernel runs).
+ * A 16-byte aligned device Y is written in place; any other Y is filled
+ * through the library's own buffer and copied. */
 tk_status tk_ttm_chain(tk_ctx* ctx, int n, float* Y, int32_t* row_slice, tk_mem mem);
 /* Size of the library's static scratch array per GPU (bytes), used by
  * tk_ttm_chain_noalloc. */
@@ -248,8 +250,9 @@ tk_status tk_ttm_chain(tk_ctx* ctx, int n, float* Y, int32_t* row_slice, tk_mem 
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * TTM-chain as tk_ttm_chain (same kernels, same results bit for bit), with no
  * allocation of any kind (no hipMalloc, hipFree or allocating library call,
- * and no memset node).  Y (R_n x Khat_n FP32) and row_slice (R_n int32, may be
- * NULL) must be device memory of the context's GPU.  The partial rows of
+ * and no memset node).  Y (R_n x Khat_n FP32, 16-byte aligned) and row_slice
+ * (R_n int32, may be NULL) must be device memory of the context's GPU
+ * (TK_ERR_INVALID_ARG otherwise).  The partial rows of
  * slices split across bins live in a static array of
  * TK_NOALLOC_SCRATCH_BYTES per GPU (set up by tk_create, held until the
  * process ends): a mode whose split slices need more (Khat_n * 4 bytes per

@@ -614,13 +614,15 @@ tk_status tk_ttm_chain(tk_ctx* c, int n, float* Y, int32_t* row_slice, tk_mem me
     const ModePlan& pl = c->plan[n];
     const size_t ny = (size_t)pl.L_nz * (size_t)pl.khat;
     if (Y) {
-      if (mem == TK_MEM_DEVICE) {
+      // the kernels store rows 16 bytes at a time: a device Y that is not
+      // 16-byte aligned is filled through the library's buffer
+      if (mem == TK_MEM_DEVICE && (reinterpret_cast<uintptr_t>(Y) & 15) == 0) {
         ttm_chain(c, n, Y, c->opt.prec == TK_BF16);
       } else {
         ensure(c, c->Y, sizeof(float) * std::max<size_t>(ny, 1));
         ttm_chain(c, n, c->Y.as<float>(), c->opt.prec == TK_BF16);
         copy_out(c, Y, c->Y.as<float>(), ny, mem);
-        c->sync();
+        if (mem == TK_MEM_HOST) c->sync();
       }
     }
     if (row_slice) {
@@ -647,6 +649,8 @@ tk_status tk_ttm_chain_noalloc(tk_ctx* c, int n, float* Y, int32_t* row_slice) {
     const ModePlan& pl = c->plan[n];
     if (pl.L_nz > 0) {
       TK_REQUIRE(Y && is_device_ptr(Y, c->device), TK_ERR_INVALID_ARG, "Y must be device memory of the context's GPU");
+      TK_REQUIRE((reinterpret_cast<uintptr_t>(Y) & 15) == 0, TK_ERR_INVALID_ARG,
+                 "Y must be 16-byte aligned (rows are stored 16 bytes at a time)");
       TK_REQUIRE(!row_slice || is_device_ptr(row_slice, c->device), TK_ERR_INVALID_ARG,
                  "row_slice must be device memory of the context's GPU");
     }

@@ -169,6 +169,30 @@ def test_ttm_chain_parity(tk, name):
         assert err <= TOL
 
 
+def test_ttm_chain_into_unaligned_device_buffer(tk):
+    """The kernels store rows 16 bytes at a time.  A device Y that is not
+    16-byte aligned (a view one float into its allocation) still gets the same
+    rows, bit for bit, through the library's buffer; the allocation-free call
+    rejects it before launching anything."""
+    import torch
+    idx, vals = zipf_tensor((3000, 2000, 500), 60_000, s=1.2, seed=71)
+    dims = tuple(int(i.max()) + 1 for i in idx)
+    ctx = _load(tk, idx, vals, dims, (10, 10, 10))
+    for n, d in enumerate(dims):
+        ctx.set_factor(n, synth.normal(81, 200 + n, d * 10).reshape(d, 10))
+    for n in range(3):
+        R, kh = ctx.ttm_shape(n)
+        Ya, _ = ctx.ttm_chain(n, device=True)
+        buf = torch.full((R * kh + 1,), float("nan"), dtype=torch.float32, device="cuda")
+        Yu = buf[1:].view(R, kh)
+        assert Yu.data_ptr() % 16 != 0
+        ctx.ttm_chain(n, Yu, torch.empty(R, dtype=torch.int32, device="cuda"))
+        torch.cuda.synchronize()
+        assert torch.equal(Ya, Yu)
+        with pytest.raises(tk.TuckerError, match="INVALID_ARG"):
+            ctx.ttm_chain_noalloc(n, Yu)
+
+
 def test_ttm_empty_tensor(tk):
     dims = (4, 5, 6)
     ctx = _load(tk, [np.zeros(0, np.int32)] * 3, np.zeros(0, np.float32), dims, (2, 2, 2))
