@@ -926,10 +926,9 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
 }
 
-// bf16: gather the BF16 factor copies (precision form); taken only where the
-// matrix-core kernel runs and every other factor's BF16 row stride is 16.
 // bf16: the precision form's BF16 Kronecker tiles on the matrix cores (where a
-// matrix-core kernel runs; other shapes stay FP32).
+// matrix-core kernel runs, the FP32 factor rows rounded in registers; other
+// shapes stay FP32).
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial) {
   if (c->opt.ttm_kernel == TK_TTM_ATOMIC) {
     ttm_atomic(c, n, Y);
