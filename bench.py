@@ -369,6 +369,17 @@ def run_completion(args):
                                   f"observations, ranks 16x16x16, one forward + adjoint per step"},
            "forward_ms": round(fwd / args.steps, 3), "adjoint_ms": round(adj / args.steps, 3),
            "setup_s": round(setup_s, 2)}
+    # algorithmic bytes of a step: each observation's N coordinates and one
+    # value in the forward (model) and again in the adjoint (residual); the
+    # core and factors read by both, their gradients written by the adjoint
+    N = len(dims)
+    params = sum(d * k for d, k in zip(dims, ranks)) + int(np.prod(ranks))
+    step_bytes = n_obs * 2 * (4 * N + 4) + 3 * 4 * params
+    step_ms = (fwd + adj) / args.steps
+    achieved = step_bytes / (step_ms * 1e-3) / 1e9
+    out["roofline"] = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                       "kernel": "forward + adjoint step, all launches (HIP events)", "bytes_per_step": step_bytes}
     print(json.dumps(out), flush=True)
 
 
