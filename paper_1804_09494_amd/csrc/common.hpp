@@ -329,9 +329,14 @@ int ttm_tile_width(int N, const int32_t* K, int n);
 int64_t ttm_default_bin_nnz(int N, const int32_t* K, int n, int kernel);
 bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp);
 bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp);
+bool ttm_takes_mfma3(const Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const int* kp);
 void refresh_factor_copies(Ctx* c, int n);
+// val_order non-null: lay_val is indexed through it (layout position p takes
+// lay_val[val_order[p]], 0xffffffff giving zero); only where the three-mode
+// matrix-core kernel runs (ttm_uses_mfma).
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y, bool bf16 = false, float* partial = nullptr);
+             const float* lay_val, int64_t m, float* Y, bool bf16 = false, float* partial = nullptr,
+             const uint32_t* val_order = nullptr);
 void ttm_chain(Ctx* c, int n, float* Y, bool bf16, float* partial = nullptr);
 void noalloc_scratch_init(int device);
 void ttm_chain_noalloc(Ctx* c, int n, float* Y);

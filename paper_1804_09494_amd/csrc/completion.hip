@@ -448,12 +448,17 @@ void obs_adjoint(Ctx* c, const float* g, const float* core, const float* const* 
   for (int n = 0; n < N; ++n) {
     ModePlan& pl = o.plan[n];
     const int khat = (int)pl.khat;
-    ensure(c, o.gl, sizeof(float) * (size_t)std::max<int64_t>(pl.m_pad, 1));
-    hipLaunchKernelGGL(k_gather_layout, dim3(grid_for(pl.m_pad, 256)), dim3(256), 0, c->stream, gd,
-                       pl.order_pad.as<uint32_t>(), pl.m_pad, o.gl.as<float>());
-    TK_CHECK_LAUNCH();
     float* Yg = o.Yg.as<float>();
-    ttm_run(c, pl, N, n, o.K, Fp, o.kp, o.gl.as<float>(), o.n_obs, Yg);
+    if (ttm_takes_mfma3(c, pl, N, n, o.K, o.kp)) {
+      // the kernel fetches each residual from observation order as it stages a bin
+      ttm_run(c, pl, N, n, o.K, Fp, o.kp, gd, o.n_obs, Yg, false, nullptr, pl.order_pad.as<uint32_t>());
+    } else {
+      ensure(c, o.gl, sizeof(float) * (size_t)std::max<int64_t>(pl.m_pad, 1));
+      hipLaunchKernelGGL(k_gather_layout, dim3(grid_for(pl.m_pad, 256)), dim3(256), 0, c->stream, gd,
+                         pl.order_pad.as<uint32_t>(), pl.m_pad, o.gl.as<float>());
+      TK_CHECK_LAUNCH();
+      ttm_run(c, pl, N, n, o.K, Fp, o.kp, o.gl.as<float>(), o.n_obs, Yg);
+    }
     Buf tdF;
     float* dFn = dF[n];
     if (mem == TK_MEM_HOST) {

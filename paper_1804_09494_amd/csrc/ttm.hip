@@ -221,7 +221,10 @@ constexpr int TTM4_RING = 3;   // the same for the four-mode kernel (three 16-by
 // supplies the block's four elements 4q .. 4q+3 (one padded quad, so one
 // slice).  A block whose quads belong to several slices issues one MFMA per
 // slice, the other lane groups' A operands zeroed.
-template <bool BFM>
+// GATHER: the values come from A.val in another order (A.val_order), each
+// fetched on its own while the bin is staged (the completion adjoint's
+// residuals, kept in observation order).
+template <bool BFM, bool GATHER = false>
 __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.KA, kb = A.KW;
@@ -255,12 +258,21 @@ __global__ __launch_bounds__(64) void k_ttm3_mfma(TtmArgs A, int Epad) {
     const u32x4* la4 = reinterpret_cast<const u32x4*>(A.lay[0] + e0);
     const u32x4* lb4 = reinterpret_cast<const u32x4*>(A.lay[1] + e0);
     const u32x4* v4 = reinterpret_cast<const u32x4*>(A.val + e0);
+    const u32x4* o4 = reinterpret_cast<const u32x4*>(A.val_order + e0);
     const u32x4 z = {0u, 0u, 0u, 0u};
     for (int i = lane; 4 * i < Ep; i += 64) {
       const bool ok = 4 * i < E;
       reinterpret_cast<u32x4*>(sia)[i] = ok ? __builtin_nontemporal_load(la4 + i) : z;
       reinterpret_cast<u32x4*>(sib)[i] = ok ? __builtin_nontemporal_load(lb4 + i) : z;
-      reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
+      if constexpr (GATHER) {
+        const u32x4 o = ok ? __builtin_nontemporal_load(o4 + i) : u32x4{~0u, ~0u, ~0u, ~0u};
+        u32x4 v;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) v[j] = o[j] == ~0u ? 0u : __float_as_uint(A.val[o[j]]);
+        reinterpret_cast<u32x4*>(sv)[i] = v;
+      } else {
+        reinterpret_cast<u32x4*>(sv)[i] = ok ? __builtin_nontemporal_load(v4 + i) : z;
+      }
     }
   }
   load_segs(0);
@@ -771,6 +783,13 @@ bool ttm_uses_mfma(int N, const int32_t* K, int n, const int* kp) {
   return true;
 }
 
+// The three-mode matrix-core kernel is the one ttm_run launches for mode n.
+bool ttm_takes_mfma3(const Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const int* kp) {
+  if (pl.whole_slices || c->opt.ttm_kernel == TK_TTM_VECTOR) return false;
+  if (c->opt.ttm_kernel == TK_TTM_FIBER && ttm_uses_fiber(N, K, n, kp)) return false;
+  return ttm_uses_mfma(N, K, n, kp);
+}
+
 // Four-mode tensors with all remaining ranks <= 16 and 16-float factor rows
 // take the four-mode matrix-core kernel.
 bool ttm_uses_mfma4(int N, const int32_t* K, int n, const int* kp) {
@@ -822,7 +841,7 @@ int ttm_rows_cap(Ctx* c, int64_t tile_w) {
 // TTM-chain of the elements of plan `pl` along mode n with FP32 factor copies
 // F32[j] (row stride kp[j]) of every mode j != n; values are the plan's layout values.
 void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const float* const* F32, const int* kp,
-             const float* lay_val, int64_t m, float* Y, bool bf16, float* partial) {
+             const float* lay_val, int64_t m, float* Y, bool bf16, float* partial, const uint32_t* val_order) {
   TtmArgs a{};
   a.bin_ptr = pl.bin_pptr.as<int64_t>();
   a.seg_ptr = pl.seg_ptr.as<int32_t>();
@@ -844,6 +863,7 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   a.KW = prod;
   a.khat = (int)pl.khat;
   a.val = lay_val;
+  a.val_order = val_order;
   a.Y = Y;
   if (!partial) {
     ensure(c, c->partial, sizeof(float) * (size_t)std::max<int64_t>(pl.fix_rows, 1) * (size_t)pl.khat);
@@ -862,16 +882,22 @@ void ttm_run(Ctx* c, const ModePlan& pl, int N, int n, const int32_t* K, const f
   }
   if (c->ev_ttm[0]) TK_HIP(hipEventRecord(c->ev_ttm[0], c->stream));
   const bool vector_only = pl.whole_slices || c->opt.ttm_kernel == TK_TTM_VECTOR;
+  TK_REQUIRE(!val_order || ttm_takes_mfma3(c, pl, N, n, K, kp), TK_ERR_UNSUPPORTED,
+             "TTM-chain: gathered values need the three-mode matrix-core kernel");
   if (!pl.whole_slices && c->opt.ttm_kernel == TK_TTM_FIBER && ttm_uses_fiber(N, K, n, kp)) {
     ttm_fiber_launch(c, pl, a, N);
   } else if (!vector_only && ttm_uses_mfma(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);
     const size_t lds = 12 * (size_t)Epad + sizeof(float) * 512 + sizeof(float) * (size_t)pl.R_max * (size_t)pl.khat;
     TK_REQUIRE(lds <= c->lds_per_block, TK_ERR_UNSUPPORTED, "TTM-chain: bin too large for LDS");
-    if (bf16)
+    if (val_order) {
+      TK_REQUIRE(!bf16, TK_ERR_UNSUPPORTED, "TTM-chain: gathered values take the FP32 tiles");
+      hipLaunchKernelGGL((k_ttm3_mfma<false, true>), dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
+    } else if (bf16) {
       hipLaunchKernelGGL(k_ttm3_mfma<true>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
-    else
+    } else {
       hipLaunchKernelGGL(k_ttm3_mfma<false>, dim3((unsigned)pl.P), dim3(64), lds, c->stream, a, Epad);
+    }
     TK_CHECK_LAUNCH();
   } else if (!vector_only && ttm_uses_mfma4(N, K, n, kp)) {
     const int Epad = (int)((pl.E_pad_max + 15) & ~(int64_t)15);

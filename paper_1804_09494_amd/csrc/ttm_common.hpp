@@ -18,6 +18,7 @@ struct TtmArgs {
   const int32_t* seg_slot;
   const int32_t* lay[7];    // other modes' coordinates in layout order (ascending mode)
   const float* val;
+  const uint32_t* val_order;  // non-null: the value of layout position p is val[val_order[p]] (0xffffffff: zero)
   const float* F[7];        // FP32 factor copies of the other modes
   int fstride[7];
   int Kj[7];
