@@ -433,12 +433,16 @@ def test_rank_deficient_mid_sweep_matches_oracle(tk):
 
 # ---- completion (differentiation form) ----------------------------------------------------------
 
-def test_completion_eval_and_adjoint_match_oracle(tk):
+@pytest.mark.parametrize("kernel", ["auto", "vector"])
+def test_completion_eval_and_adjoint_match_oracle(tk, kernel):
+    """auto: the adjoint's TTM-chains fetch the residuals through the layout
+    order while staging each bin; vector: they are gathered into layout order
+    by a separate pass first."""
     import torch
     from oracle import completion
     d = synth.make_completion((100, 100, 50), 20_000, (16, 16, 16), seed=4949)
     dims, ranks = d["dims"], d["ranks"]
-    ctx = tk.TuckerContext(0)
+    ctx = tk.TuckerContext(0, ttm_kernel=kernel)
     ctx.load_obs([torch.from_numpy(i).cuda() for i in d["idx"]], dims, ranks)
     rng = np.random.default_rng(1)
     G = rng.standard_normal(ranks) * 0.5
