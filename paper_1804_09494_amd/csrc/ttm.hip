@@ -456,9 +456,10 @@ template <int NT, bool BFM>
 // Up to eight output tiles, at most 170 registers per lane (three waves per
 // SIMD): at ranks 10 the BF16 form would otherwise take 194 (166 + 28
 // accumulation registers) and run at two waves, 26% slower, and the FP32 form
-// drops from 154 to 119.  Wider tiles keep the compiler's choice (the cap
-// would spill).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 3 : 1))) void k_ttm4_mfma(
+// drops from 154 to 119.  Wider tiles (a three-wave cap would spill) are held
+// to two waves: left unbounded, 14 to 16 tiles take 250 to 284 registers and
+// run at one wave (ranks 16, four modes: TTM-chain 53 ms against 31 at two).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NT <= 8 ? 3 : 2))) void k_ttm4_mfma(
     TtmArgs A, int Epad, int nseg_pad) {
   extern __shared__ __align__(16) unsigned char smem[];
   const int ka = A.Kj[0], kb = A.Kj[1], kbc = A.Kj[1] * A.Kj[2];
