@@ -125,6 +125,10 @@ TTM_CASES = {
     "4mode_odd": (lambda: zipf_tensor((300, 200, 100, 30), 20_000, s=1.0, seed=36), (3, 4, 2, 5), 1024),
     # K_b K_c = 256: sixteen output tiles per step in the four-mode kernel
     "4mode_k16": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=40), (4, 16, 16, 16), 1024),
+    # 14 / 14 / 12 / 11 and 13 / 13 / 8 / 9 output tiles: the widths held to
+    # two waves per SIMD, and the widest three-wave one
+    "4mode_wide_a": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=49), (5, 12, 14, 15), 1024),
+    "4mode_wide_b": (lambda: zipf_tensor((300, 200, 100, 40), 20_000, s=1.0, seed=50), (3, 9, 16, 13), 1024),
     # ranks above 16: the vector-ALU kernel (K̂ = 340, 544, 640)
     "k32_vector": (lambda: zipf_tensor((500, 400, 300), 30_000, s=1.0, seed=45), (32, 20, 17), 1024),
     # the default bin size (448 elements for the three-mode matrix-core kernel)

@@ -28,15 +28,16 @@ def _allowed(ic, vc, dims, F_out, n, K, tol):
     return factor_tolerance(sv, K, tol)
 
 
-@pytest.mark.parametrize("shape", ["3mode", "4mode"])
+@pytest.mark.parametrize("shape", ["3mode", "4mode", "4mode_wide"])
 def test_bf16_kronecker_tiles_ttm_within_1e2(tk, shape):
     """tk_ttm_chain with prec = BF16: the Kronecker tiles rounded to BF16 on the
     matrix cores (FP32 accumulation), three modes (one slice run or several
-    per 16-element block: Zipf heads and tails) and four modes (Khat = 1000)."""
+    per 16-element block: Zipf heads and tails) and four modes (Khat = 1000,
+    7 output tiles per step; and 11 to 14 tiles)."""
     if shape == "3mode":
         w = synth.make_workload("c2", scale=0.002)
     else:
-        dims, ranks = (400, 300, 200, 60), (10, 10, 10, 10)
+        dims, ranks = (400, 300, 200, 60), ((10, 10, 10, 10) if shape == "4mode" else (5, 12, 14, 15))
         idx, vals = synth.make_tensor(dims, 60_000, "zipf", (0.9, 1.1, 1.3, 0.7), "lognormal", seed=44)
         w = {"dims": dims, "ranks": ranks, "idx": idx, "vals": vals, "F0": synth.orthonormal_init(44, dims, ranks)}
     ctx = _ctx(tk, w, prec="bf16")
