@@ -464,6 +464,14 @@ tk_status tk_get_coo(tk_ctx* c, int32_t* const* idx, float* vals, tk_mem mem) {
   });
 }
 
+// F (L x K, row-major) = the first K columns of the identity: the factors'
+// placeholder until the caller sets them.
+__global__ void k_leading_identity(double* __restrict__ F, int64_t L, int K) {
+  const int64_t total = L * K;
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < total; i += (int64_t)gridDim.x * blockDim.x)
+    F[i] = (i / K == i % K) ? 1.0 : 0.0;
+}
+
 tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
   if (!c) return TK_ERR_INVALID_ARG;
   return guard(c, [&] {
@@ -491,20 +499,24 @@ tk_status tk_set_ranks(tk_ctx* c, const int32_t* K) {
       for (int n = 0; n < N; ++n)
         TK_REQUIRE(c->slice_order[n].bytes() == sizeof(int32_t) * (size_t)c->dims[n], TK_ERR_STATE,
                    "the CoarseG partition needs tk_set_slice_order for every mode");
-    for (int n = 0; n < N; ++n) {
-      const int tw = ttm_tile_width(N, K, n);
-      build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
-                 ttm_default_bin_nnz(N, K, n, c->opt.ttm_kernel), c->opt.keep_elem_order != 0,
-                 coarse ? c->slice_order[n].as<int32_t>() : nullptr);
+    {
+      SortScratch ss;
+      for (int n = 0; n < N; ++n) {
+        const int tw = ttm_tile_width(N, K, n);
+        build_plan(c, c->plan[n], N, n, c->dims, c->m, c->idx_c, c->val_c.as<float>(), khat_of(c, n), tw,
+                   ttm_default_bin_nnz(N, K, n, c->opt.ttm_kernel), c->opt.keep_elem_order != 0, ss, n == N - 1,
+                   coarse ? c->slice_order[n].as<int32_t>() : nullptr);
+      }
     }
     for (int n = 0; n < N; ++n) relabel_layout(c, c->plan[n], N, n, c->plan, c->m);
     for (int n = 0; n < N; ++n) {
       c->kp32[n] = K[n] <= 16 ? 16 : (K[n] + 3) & ~3;  // 64-byte rows: one 16-lane MFMA operand load
       c->F64[n].alloc(c, sizeof(double) * (size_t)c->dims[n] * K[n]);
       c->F32[n].alloc(c, sizeof(float) * (size_t)c->dims[n] * c->kp32[n]);
-      std::vector<double> I((size_t)c->dims[n] * K[n], 0.0);
-      for (int k = 0; k < K[n]; ++k) I[(size_t)k * K[n] + k] = 1.0;
-      h2d(c, c->F64[n].as<double>(), I.data(), I.size());
+      const int64_t LK = c->dims[n] * K[n];
+      hipLaunchKernelGGL(k_leading_identity, dim3(grid_for(LK, 256)), dim3(256), 0, c->stream,
+                         c->F64[n].as<double>(), c->dims[n], K[n]);
+      TK_CHECK_LAUNCH();
       refresh_factor_copies(c, n);
       c->fac_dirty[n] = true;
       c->eig_warm_k[n] = 0;

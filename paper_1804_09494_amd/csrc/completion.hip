@@ -55,12 +55,16 @@ void load_obs(Ctx* c, int N, const int64_t* dims, const int32_t* ranks, int64_t 
   c->sync();
   TK_REQUIRE(h == 0, TK_ERR_INVALID_ARG, "tk_load_obs: a coordinate is out of range");
   int64_t maxY = 1;
-  for (int n = 0; n < N; ++n) {
-    int64_t khat = 1;
-    for (int j = 0; j < N; ++j)
-      if (j != n) khat *= ranks[j];
-    build_plan(c, o.plan[n], N, n, dims, n_obs, o.idx, nullptr, khat, ttm_tile_width(N, ranks, n), 1024, true);
-    maxY = std::max(maxY, o.plan[n].L_nz * khat);
+  {
+    SortScratch ss;
+    for (int n = 0; n < N; ++n) {
+      int64_t khat = 1;
+      for (int j = 0; j < N; ++j)
+        if (j != n) khat *= ranks[j];
+      build_plan(c, o.plan[n], N, n, dims, n_obs, o.idx, nullptr, khat, ttm_tile_width(N, ranks, n), 1024, true, ss,
+                 n == N - 1);
+      maxY = std::max(maxY, o.plan[n].L_nz * khat);
+    }
   }
   for (int j = 0; j < N; ++j) {
     o.kp[j] = ranks[j] <= 16 ? 16 : (ranks[j] + 3) & ~3;

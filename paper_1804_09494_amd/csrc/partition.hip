@@ -375,7 +375,8 @@ static void build_plan_coarse(Ctx* c, ModePlan& pl, int N, int n, int64_t L, int
                               Buf& row_of);
 
 void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t m, Buf* idx, const float* vals,
-                int64_t khat, int tile_w, int64_t wg_default, bool keep_order, const int32_t* coarse_order) {
+                int64_t khat, int tile_w, int64_t wg_default, bool keep_order, SortScratch& ss, bool last,
+                const int32_t* coarse_order) {
   const int B = 256;
   const int64_t L = dims[n];
   pl = ModePlan();
@@ -384,17 +385,24 @@ void build_plan(Ctx* c, ModePlan& pl, int N, int n, const int64_t* dims, int64_t
   TK_REQUIRE(m < ((int64_t)1 << 32), TK_ERR_UNSUPPORTED, "this build handles fewer than 2^32 elements");
 
   // 1. slice-sorted order of the elements (stable => canonical order inside a slice)
-  Buf key(c, 4 * (size_t)(m ? m : 1)), skey(c, 4 * (size_t)(m ? m : 1));
-  Buf perm(c, 4 * (size_t)(m ? m : 1)), sperm(c, 4 * (size_t)(m ? m : 1));
+  const size_t eb = 4 * (size_t)(m ? m : 1);
+  ensure(c, ss.key, eb);
+  ensure(c, ss.skey, eb);
+  ensure(c, ss.perm, eb);
+  ensure(c, ss.sperm, eb);
+  Buf &key = ss.key, &skey = ss.skey, &perm = ss.perm, &sperm = ss.sperm;
   hipLaunchKernelGGL(k_copy_key, dim3(grid_for(m, B)), dim3(B), 0, c->stream, idx[n].as<int32_t>(),
                      key.as<uint32_t>(), m);
   TK_CHECK_LAUNCH();
   hipLaunchKernelGGL(k_iota_u32b, dim3(grid_for(m, B)), dim3(B), 0, c->stream, perm.as<uint32_t>(), m);
   TK_CHECK_LAUNCH();
   sort_pairs_u32(c, key.as<uint32_t>(), skey.as<uint32_t>(), perm.as<uint32_t>(), sperm.as<uint32_t>(), m,
-                 bits_for_len(L));
-  key.release();
-  perm.release();
+                 bits_for_len(L), &ss.tmp);
+  if (last) {   // the sorted pair stays until the layout; the rest is done with
+    key.release();
+    perm.release();
+    ss.tmp.release();
+  }
 
   // 2. slice sizes, nonempty slices, sort by (size, id)
   Buf sstart(c, 8 * (size_t)L), count(c, 8 * (size_t)L), nonempty(c, 4 * (size_t)L), row_of(c, 4 * (size_t)L);

@@ -16,13 +16,15 @@ namespace tk {
   } while (0)
 
 void sort_pairs_u32(Ctx* c, const uint32_t* kin, uint32_t* kout, const uint32_t* vin, uint32_t* vout, int64_t n,
-                    int end_bit) {
+                    int end_bit, Buf* keep) {
   if (n <= 0) return;
   size_t tmp = 0;
   TK_PRIM(rocprim::radix_sort_pairs(nullptr, tmp, kin, kout, vin, vout, (size_t)n, 0, end_bit, c->stream));
-  Buf t(c, tmp);
-  TK_PRIM(rocprim::radix_sort_pairs(t.get(), tmp, kin, kout, vin, vout, (size_t)n, 0, end_bit, c->stream));
-  c->sync();  // temporary storage is released on return
+  Buf t;
+  Buf& st = keep ? *keep : t;
+  ensure(c, st, tmp);
+  TK_PRIM(rocprim::radix_sort_pairs(st.get(), tmp, kin, kout, vin, vout, (size_t)n, 0, end_bit, c->stream));
+  c->sync();  // a local temporary storage is released on return
 }
 
 void sort_pairs_u64_u32(Ctx* c, const uint64_t* kin, uint64_t* kout, const uint32_t* vin, uint32_t* vout, int64_t n,
