@@ -52,17 +52,28 @@ struct IdxPtrs {
   const int32_t* p[8];
 };
 
+// Each lane gathers its own element's coordinates once; the previous sorted
+// element's come from the lane before it (consecutive positions share a
+// wave), and only lane 0 gathers them itself.  A lane that runs an iteration
+// has its left neighbour running it too, since positions increase with the
+// lane.
 template <class PT>
 __global__ void k_mark_runs(IdxPtrs idx, int N, const PT* __restrict__ perm, int64_t m, PT* __restrict__ mark) {
+  const int lane = threadIdx.x & 63;
   for (int64_t s = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; s < m; s += (int64_t)gridDim.x * blockDim.x) {
-    PT f = 1;
-    if (s > 0) {
-      const PT a = perm[s], b = perm[s - 1];
-      int d = 0;
-      for (int j = 0; j < N; ++j) d |= (idx.p[j][a] != idx.p[j][b]);
-      f = (PT)d;
+    const PT a = perm[s];
+    const PT b = (lane == 0 && s > 0) ? perm[s - 1] : a;
+    int d = 0;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      if (j < N) {
+        const int32_t cur = idx.p[j][a];
+        int32_t prev = __shfl_up(cur, 1, 64);
+        if (lane == 0) prev = idx.p[j][b];
+        d |= (cur != prev);
+      }
     }
-    mark[s] = f;
+    mark[s] = s == 0 ? (PT)1 : (PT)d;
   }
 }
 
